@@ -1,0 +1,92 @@
+"""Post-processing of density fields (FP64, NumPy).
+
+TEST INFRASTRUCTURE ONLY (oracle).  Measures what the paper evaluates on its
+runs: the Laplace pressure jump (Sec. IV.B and IV.C use Laplace's law to
+evaluate the surface tension), the effective droplet radius, the interface
+thickness (Sec. IV.B, Fig. 3) and the maximum spurious velocity (Table I).
+
+Readings (the paper does not define these precisely):
+  * pressure p = p_EOS(rho) per site (equal to Eq. (11) when psi follows Eq. (24));
+  * p_in = mean over sites at distance d <= R0/2 from the droplet centre,
+    p_out = mean over d >= R0 + 3W (W = 5, the tanh width of Eq. (31));
+  * R_eff = sqrt((sum rho - rho_out N) / (pi (rho_in - rho_out)));
+  * interface thickness = distance between the 10 % and 90 % crossings of
+    (rho - rho_g)/(rho_l - rho_g), linearly interpolated.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import eos
+
+
+def distance_field(nx, ny, cx, cy, periodic_y=True):
+    """Distance of every site (x, y) to (cx, cy); minimum image in x, and in y if periodic."""
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    dx = np.abs(x - cx)
+    dx = np.minimum(dx, nx - dx)
+    dy = np.abs(y - cy)
+    if periodic_y:
+        dy = np.minimum(dy, ny - dy)
+    return np.sqrt(dx * dx + dy * dy)
+
+
+def region_means(field, d, r_min, r_max):
+    """Mean of field over sites with r_min <= d < r_max, and the site count."""
+    m = (d >= r_min) & (d < r_max)
+    n = int(m.sum())
+    return (float(field[m].mean()) if n else float("nan")), n
+
+
+def laplace(rho, params, R0, W=5.0, cx=None, cy=None):
+    """Pressure jump and effective radius of a centred droplet.
+
+    Returns dict(p_in, p_out, dp, rho_in, rho_out, R_eff, theta) with theta = dp * R_eff
+    (2-D Laplace law dp = theta / R)."""
+    ny, nx = rho.shape
+    cx = (nx - 1) / 2.0 if cx is None else cx
+    cy = (ny - 1) / 2.0 if cy is None else cy
+    d = distance_field(nx, ny, cx, cy, periodic_y=(params.get("bc", 0) == 0))
+    p = eos.p_eos(rho, params["a"], params["b"], params["R"], params["T"])
+    p_in, _ = region_means(p, d, 0.0, R0 / 2.0 + 1e-12)
+    p_out, _ = region_means(p, d, R0 + 3.0 * W, np.inf)
+    rho_in, _ = region_means(rho, d, 0.0, R0 / 2.0 + 1e-12)
+    rho_out, _ = region_means(rho, d, R0 + 3.0 * W, np.inf)
+    R_eff = math.sqrt((rho.sum() - rho_out * rho.size) / (math.pi * (rho_in - rho_out)))
+    dp = p_in - p_out
+    return dict(p_in=p_in, p_out=p_out, dp=dp, rho_in=rho_in, rho_out=rho_out, R_eff=R_eff,
+                theta=dp * R_eff)
+
+
+def interface_width(profile, rho_l, rho_g, lo=0.1, hi=0.9):
+    """Distance between the lo and hi crossings of the normalised profile along a
+    monotone stretch (first crossing pair found scanning from the liquid side)."""
+    phi = (np.asarray(profile, dtype=np.float64) - rho_g) / (rho_l - rho_g)
+    i0 = int(np.argmax(phi))
+    seg = phi[i0:]
+    def crossing(level):
+        k = np.nonzero(seg < level)[0]
+        if k.size == 0:
+            raise ValueError("profile does not cross the level")
+        k = int(k[0])
+        # linear interpolation between seg[k-1] >= level > seg[k]
+        return (k - 1) + (seg[k - 1] - level) / (seg[k - 1] - seg[k])
+    return crossing(lo) - crossing(hi)
+
+
+def max_speed(ux, uy):
+    return float(np.sqrt(ux * ux + uy * uy).max())
+
+
+def linear_fit(x, y):
+    """Least-squares y = s x + c; returns (s, c, r2)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    A = np.vstack([x, np.ones_like(x)]).T
+    (s, c), *_ = np.linalg.lstsq(A, y, rcond=None)
+    yhat = s * x + c
+    r2 = 1.0 - ((y - yhat) ** 2).sum() / ((y - y.mean()) ** 2).sum()
+    return float(s), float(c), float(r2)

@@ -1,0 +1,193 @@
+"""Seeded synthetic inputs for the D2Q9 pseudopotential runs.
+
+This module is shared by the FP64 oracle tests and by the GPU path.  It holds
+no arithmetic of the lattice Boltzmann step: it only builds initial density and
+velocity fields and parameter sets.
+
+Sources of the recipes (Li, Luo & Li):
+  * Eq. (31), Sec. IV.A: tanh density profile of width W = 5 across the interface,
+    between the coexistence densities rho_l and rho_g;
+  * Sec. IV.A: b = 4, R = 1, G = -1, relaxation rates 1/tau_rho = 1/tau_j = 1,
+    1/tau_e = 1/tau_zeta = 1/tau_q = 1.1; sigma = 0.11 for a = 0.5;
+  * Sec. IV.B: sigma = 0.114 for a = 0.25;
+  * Sec. IV.C: droplet splashing on a thin film: no-slip walls in y, periodic x,
+    impact velocity (0, -U), 1/tau_e = 1/tau_zeta = 0.8, nu(rho) switched at rho_c.
+
+Readings of points the paper leaves open:
+  * T_c = 0.094 a (the rounded value the paper quotes for a = 1, 0.5, 0.25);
+  * rho_l, rho_g of the initial profile are the Maxwell densities at T/T_c,
+    interpolated from ``coexistence_table.json`` (written by
+    ``python -m oracle.make_coexistence_table``);
+  * the viscosity switch density is the printed rho_c = 0.5218 / b;
+  * sigma = 0.11 for a = 1.0 (not stated in the paper);
+  * droplet centre ((nx - 1)/2, (ny - 1)/2) so that the field is D4-symmetric;
+  * splash: film interface at y = film, droplet centre (nx/2, film + R + gap),
+    rho0 = max(film, drop), u0 = (0, -U) times the droplet's liquid fraction.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+TC_PER_A = 0.094
+W_TANH = 5.0
+_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "coexistence_table.json")
+_table_cache = None
+
+SIGMA_FOR_A = {0.25: 0.114, 0.5: 0.11, 1.0: 0.11}
+
+
+def critical_temperature(a: float) -> float:
+    return TC_PER_A * a
+
+
+def rho_switch(b: float = 4.0) -> float:
+    return 0.5218 / b
+
+
+def coexistence(t_over_tc: float):
+    """(rho_l, rho_g) of the Maxwell construction at T/T_c (b = 4), interpolated
+    from the stored table: linear in rho_l, linear in log(rho_g)."""
+    global _table_cache
+    if _table_cache is None:
+        with open(_TABLE) as fh:
+            _table_cache = np.array(json.load(fh)["rows"], dtype=np.float64)
+    t = _table_cache
+    if not (t[0, 0] <= t_over_tc <= t[-1, 0]):
+        raise ValueError(f"T/T_c = {t_over_tc} outside the stored table")
+    rl = float(np.interp(t_over_tc, t[:, 0], t[:, 1]))
+    rg = float(np.exp(np.interp(t_over_tc, t[:, 0], np.log(t[:, 2]))))
+    return rl, rg
+
+
+def tanh_profile(d, rho_l, rho_g, W=W_TANH):
+    """Eq. (31) as a function of the signed distance d = r - r0 (liquid where d < 0)."""
+    return 0.5 * (rho_l + rho_g) - 0.5 * (rho_l - rho_g) * np.tanh(2.0 * d / W)
+
+
+def _grid(nx, ny):
+    return np.arange(nx, dtype=np.float64)[None, :], np.arange(ny, dtype=np.float64)[:, None]
+
+
+def _min_image(d, n):
+    d = np.abs(d)
+    return np.minimum(d, n - d)
+
+
+def droplet_field(nx, ny, R0, rho_l, rho_g, W=W_TANH, cx=None, cy=None, periodic_y=True):
+    """Circular droplet of radius R0 (Eq. 31), minimum-image distances on the torus."""
+    cx = (nx - 1) / 2.0 if cx is None else cx
+    cy = (ny - 1) / 2.0 if cy is None else cy
+    x, y = _grid(nx, ny)
+    dx = _min_image(x - cx, nx)
+    dy = _min_image(y - cy, ny) if periodic_y else np.abs(y - cy)
+    return tanh_profile(np.sqrt(dx * dx + dy * dy) - R0, rho_l, rho_g, W)
+
+
+def ellipse_field(nx, ny, R0, aspect, rho_l, rho_g, W=W_TANH):
+    """Elliptic droplet with semi-axes R0 sqrt(aspect) (x) and R0 / sqrt(aspect) (y),
+    level set d = R0 (sqrt((x/A)^2 + (y/B)^2) - 1)."""
+    cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
+    x, y = _grid(nx, ny)
+    A, B = R0 * math.sqrt(aspect), R0 / math.sqrt(aspect)
+    dx = _min_image(x - cx, nx)
+    dy = _min_image(y - cy, ny)
+    d = R0 * (np.sqrt((dx / A) ** 2 + (dy / B) ** 2) - 1.0)
+    return tanh_profile(d, rho_l, rho_g, W)
+
+
+def slab_field(nx, ny, thickness, rho_l, rho_g, W=W_TANH):
+    """Liquid slab of the given thickness centred in y (two flat interfaces), uniform in x."""
+    cy = (ny - 1) / 2.0
+    _, y = _grid(nx, ny)
+    d = np.abs(y - cy) - thickness / 2.0
+    return np.broadcast_to(tanh_profile(d, rho_l, rho_g, W), (ny, nx)).copy()
+
+
+def splash_field(nx, ny, R, film, U, rho_l, rho_g, gap, W=W_TANH):
+    """Droplet of radius R above a liquid film of thickness `film` on the bottom wall.
+    Returns rho0, ux0, uy0 (u0 = (0, -U) weighted by the droplet's liquid fraction)."""
+    x, y = _grid(nx, ny)
+    rho_film = tanh_profile(y - film + 0.0 * x, rho_l, rho_g, W)
+    cx, cy = nx / 2.0, film + R + gap
+    dx = _min_image(x - cx, nx)
+    rho_drop = tanh_profile(np.sqrt(dx * dx + (y - cy) ** 2) - R, rho_l, rho_g, W)
+    rho0 = np.maximum(rho_film, rho_drop)
+    phi = (rho_drop - rho_g) / (rho_l - rho_g)
+    ux0 = np.zeros_like(rho0)
+    uy0 = -U * phi
+    return rho0, ux0, uy0
+
+
+@dataclass
+class Workload:
+    """One run: parameter dictionary (absolute T), initial fields and a name."""
+    name: str
+    params: dict
+    rho0: np.ndarray
+    ux0: np.ndarray | None = None
+    uy0: np.ndarray | None = None
+    info: dict = field(default_factory=dict)
+
+
+def base_params(nx, ny, a=0.5, t_over_tc=0.6, bc=0, sigma=None, s_e=1.1, s_zeta=1.1, s_q=1.1,
+                nu_l=0.1, nu_g=0.3, b=4.0):
+    sigma = SIGMA_FOR_A.get(a, 0.11) if sigma is None else sigma
+    return dict(nx=int(nx), ny=int(ny), bc=int(bc), a=float(a), b=float(b), R=1.0,
+                T=float(t_over_tc * critical_temperature(a)), G=-1.0, sigma=float(sigma),
+                s_rho=1.0, s_e=float(s_e), s_zeta=float(s_zeta), s_j=1.0, s_q=float(s_q),
+                nu_l=float(nu_l), nu_g=float(nu_g), rho_switch=rho_switch(b))
+
+
+def stationary_droplet(n=128, R0=25.0, a=0.5, t_over_tc=0.6, nu_l=0.1, nu_g=0.3, **kw) -> Workload:
+    """Stationary droplet on an n x n periodic grid, tanh-initialised (Sec. IV.A recipe)."""
+    p = base_params(n, n, a=a, t_over_tc=t_over_tc, nu_l=nu_l, nu_g=nu_g, **kw)
+    rl, rg = coexistence(t_over_tc)
+    rho0 = droplet_field(n, n, R0, rl, rg)
+    return Workload(f"stationary_droplet_{n}x{n}_R{R0:g}", p, rho0,
+                    info=dict(R0=R0, rho_l=rl, rho_g=rg, t_over_tc=t_over_tc))
+
+
+def splash(scale=1, Re=200, nx=None, ny=None, U=0.05, t_over_tc=0.45, a=0.25, ratio=15.0) -> Workload:
+    """Droplet splashing on a thin film (Sec. IV.C recipe at 2048 x 1024 per unit scale):
+    R = 100 scale, film 20 scale, gap 5 scale, walls in y, periodic x.
+    Re = U D / nu_l with D = 200 (the scale-1 diameter); nu_g = ratio * nu_l."""
+    nx = 2048 * scale if nx is None else nx
+    ny = 1024 * scale if ny is None else ny
+    nu_l = U * 200.0 / Re
+    p = base_params(nx, ny, a=a, t_over_tc=t_over_tc, bc=1, s_e=0.8, s_zeta=0.8, s_q=1.1,
+                    nu_l=nu_l, nu_g=ratio * nu_l)
+    rl, rg = coexistence(t_over_tc)
+    R, film, gap = 100.0 * scale, 20.0 * scale, 5.0 * scale
+    rho0, ux0, uy0 = splash_field(nx, ny, R, film, U, rl, rg, gap)
+    return Workload(f"splash_{nx}x{ny}_Re{Re:g}", p, rho0, ux0, uy0,
+                    info=dict(R=R, film=film, U=U, Re=Re, rho_l=rl, rho_g=rg, t_over_tc=t_over_tc))
+
+
+def splash_crop(Re=200) -> Workload:
+    """512 x 256 cut-down of the splash case (same R = 100, film 20, centre (256, 125))."""
+    return splash(scale=1, Re=Re, nx=512, ny=256)
+
+
+def batch_instances(n=512, seed=1211, side_lo=64, side_hi=512):
+    """Sweep of independent droplets: square periodic grids with side ~ U{side_lo..side_hi},
+    a ~ {0.25, 0.5, 1.0}, T/T_c ~ U[0.5, 0.85], R0 ~ U[0.1, 0.3] side, half of them
+    elliptic (aspect 1.2, oscillating), nu_l = 0.1, nu_g = 0.3."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        side = int(rng.integers(side_lo, side_hi + 1))
+        a = float(rng.choice([0.25, 0.5, 1.0]))
+        tb = float(rng.uniform(0.5, 0.85))
+        R0 = float(rng.uniform(0.1, 0.3) * side)
+        ellipse = bool(rng.random() < 0.5)
+        p = base_params(side, side, a=a, t_over_tc=tb)
+        rl, rg = coexistence(tb)
+        rho0 = ellipse_field(side, side, R0, 1.2, rl, rg) if ellipse else droplet_field(side, side, R0, rl, rg)
+        out.append(Workload(f"inst{k}_{'ell' if ellipse else 'drop'}_{side}", p, rho0,
+                            info=dict(R0=R0, rho_l=rl, rho_g=rg, t_over_tc=tb, ellipse=ellipse)))
+    return out
