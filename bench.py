@@ -1,0 +1,211 @@
+"""Benchmark of the improved MRT pseudopotential D2Q9 step on one MI355X.
+
+Workload: droplet splashing on a thin film, 8192 x 4096 lattice (the 2048 x 1024
+splash geometry scaled by 4: R = 400, film 80, gap 20), x periodic, halfway
+bounce-back walls in y, Carnahan-Starling a = 0.25, T = 0.45 T_c, sigma = 0.114,
+s_e = s_zeta = 0.8, s_q = 1.1, U = 0.05, nu_l = 0.05, nu_g = 0.75.  Synthetic,
+seedless (the initial field is a deterministic tanh profile).
+
+One "step" is one full time step over the lattice (pull streaming, density, psi,
+force, MRT collision with the improved forcing, store).  The metric is MLUPS
+(million lattice-site updates per second) with the distributions resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--store f32|f16|bf16] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+BYTES_PER_SITE = {"f32": 72, "f16": 36, "bf16": 36}
+PEAK_HBM_GBPS = 8000.0
+KERNEL_SOURCES = ["paper_1211_6932_amd/csrc/d2q9_core.hpp", "paper_1211_6932_amd/csrc/d2q9_kernels.hip"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(store, nsites):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            doc = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = doc.get(store)
+    if not ent or ent.get("kernel_sha") != kernel_hash() or ent.get("sites") != nsites:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def copy_probe_gbps(torch, lbmp, stream, nbytes=1 << 30, reps=20):
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(3):
+        lbmp.lb_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lbmp.lb_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle as it stands, on the same workload, timed on the host cores."""
+    import numpy as np
+    from oracle import lbref as O
+
+    p = O.Params(**w.params)
+    rho0 = np.asarray(w.rho0, dtype=np.float32).astype(np.float64)
+    ux0 = np.asarray(w.ux0, dtype=np.float32).astype(np.float64)
+    uy0 = np.asarray(w.uy0, dtype=np.float32).astype(np.float64)
+    st = O.State(p, rho0, ux0, uy0)
+    t0 = time.perf_counter()
+    st.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, min(20, int(budget_s / max(one, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    st.step(n)
+    dt = time.perf_counter() - t0
+    sites = w.params["nx"] * w.params["ny"]
+    return {
+        "value": sites * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+        "sample": f"{n} FP64 steps of the full {w.params['nx']}x{w.params['ny']} workload "
+                  f"(after 1 untimed step), {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--store", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--scale", type=int, default=4, help="splash geometry scale (4 -> 8192x4096)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-copy-probe", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1211_6932_amd import lbmp
+
+    torch.cuda.set_device(0)
+    lbmp.load()
+    w = W.splash(scale=args.scale, Re=200)
+    nx, ny = w.params["nx"], w.params["ny"]
+    rho_ref = w.info["rho_l"] if args.store != "f32" else 0.0
+    log(f"workload {w.name} store={args.store}: init")
+    sim = lbmp.Sim(w.params, torch.from_numpy(np.asarray(w.rho0, np.float32)),
+                   torch.from_numpy(np.asarray(w.ux0, np.float32)),
+                   torch.from_numpy(np.asarray(w.uy0, np.float32)), store=args.store, rho_ref=rho_ref)
+    c = (nx / 2.0, w.info["film"] + w.info["R"] + 5.0 * args.scale)
+    d0 = sim.diagnostics(c[0], c[1], 1.0, 2.0)
+
+    log(f"warmup {args.warmup} steps")
+    sim.step(args.warmup)
+    sim.stream.synchronize()
+    torch.cuda.synchronize()
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"timed {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(sim.stream)
+    sim.step(args.steps)
+    e1.record(sim.stream)
+    sim.stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = e0.elapsed_time(e1) / args.steps
+
+    stable = lbmp.lb_check(sim.ctx) == lbmp.LB_OK
+    d1 = sim.diagnostics(c[0], c[1], 1.0, 2.0, raise_unstable=False)
+    sites = nx * ny
+    mlups = sites * args.steps / wall / 1e6
+    bps = BYTES_PER_SITE[args.store]
+    achieved = bps * sites / (kern_ms * 1e-3) / 1e9
+    log(f"{mlups:.0f} MLUPS, step {kern_ms:.4f} ms, {achieved:.0f} GB/s algorithmic, stable={stable}")
+
+    copy_gbps = None
+    if not args.no_copy_probe:
+        copy_gbps = copy_probe_gbps(torch, lbmp, sim.stream)
+        log(f"copy probe {copy_gbps:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        del sim
+        torch.cuda.empty_cache()
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+        log(f"cpu baseline {cpu['value']:.2f} MLUPS on {cpu['cores']} threads")
+
+    out = {
+        "metric": "MLUPS (D2Q9 MRT improved pseudopotential step) and % of HBM roofline",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.store == "f32" else f"{args.store}-offset storage, f32 compute",
+        "data": "synthetic",
+        "config": {
+            "workload": f"droplet splash on a thin film, {nx}x{ny}, walls in y, x periodic, "
+                        f"a=0.25, T=0.45Tc, sigma=0.114, U=0.05, nu_l=0.05, nu_g=0.75",
+            "nx": nx, "ny": ny, "store": args.store, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(args.store, sites),
+            "bytes_per_site": bps, "kernel_ms": round(kern_ms, 5),
+            "copy_probe_GBps": None if copy_gbps is None else round(copy_gbps, 1),
+        },
+        "cpu_baseline": cpu,
+        "checks": {
+            "stable": bool(stable),
+            "mass_rel_drift": (d1["mass"] - d0["mass"]) / d0["mass"],
+            "max_u": d1["max_u"],
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

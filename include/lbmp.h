@@ -1,0 +1,179 @@
+/*
+ * lbmp.h -- C ABI of the MI355X (gfx950) improved MRT pseudopotential
+ * lattice Boltzmann library (liblbmp.so).
+ *
+ * Method: Q. Li, K. H. Luo, X. J. Li, "Lattice Boltzmann modeling of
+ * multiphase flows at large density ratio with an improved pseudopotential
+ * model" (arXiv:1211.6932).  One time step of the D2Q9 update is
+ *   1. pull streaming of the post-collision distributions      Eq. (5)
+ *      (x periodic; y periodic or halfway bounce-back walls)    Sec. IV.C
+ *   2. density summation                                        Eq. (6)
+ *   3. Carnahan-Starling pressure and pseudopotential psi       Eqs. (30), (24)
+ *   4. 8-neighbour interaction force, w(1)=1/3, w(2)=1/12       Eq. (7)
+ *   5. half-force-corrected velocity                            Eq. (6)
+ *   6. MRT collision in moment space with the improved forcing  Eqs. (2)-(4), (25)
+ *      and a density-dependent shear rate (nu_l / nu_g)         Sec. IV.C
+ *
+ * Conventions common to every entry point
+ *   - All calls return lb_status; none throws or aborts.  On failure
+ *     lb_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread).
+ *   - Device pointers are HIP device addresses (for example a torch tensor's
+ *     data_ptr() on a ROCm device).  The caller owns every device buffer:
+ *     the workspace, inputs and outputs.  The library owns only the small
+ *     host-side context and its captured graphs; lb_destroy frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream, on which step loops are launched without graph capture).
+ *     Calls are asynchronous on that stream unless stated otherwise.
+ *   - Fields are FP32, row-major [ny][nx], x fastest, contiguous.
+ *   - Lattice units throughout: c = dt = 1, c_s^2 = 1/3.
+ */
+#ifndef LBMP_H
+#define LBMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,     /* invalid argument or parameter; nothing was launched          */
+    LB_ENOMEM = -2,     /* workspace too small                                           */
+    LB_EHIP = -3,       /* a HIP runtime call failed; see lb_last_error()                */
+    LB_EUNSTABLE = -4,  /* a site had a non-finite density, b rho/4 >= 1 or psi^2 <= 0   */
+    LB_ESTATE = -5      /* context poisoned by an earlier LB_EUNSTABLE / LB_EHIP          */
+} lb_status;
+
+typedef enum {
+    LB_BC_PERIODIC = 0, /* periodic in x and y                                           */
+    LB_BC_WALLS_Y = 1   /* periodic in x; no-slip walls half a cell below row 0 and half
+                           a cell above row ny-1 (halfway bounce-back).  psi beyond a
+                           wall equals psi of the adjacent fluid row, same column.       */
+} lb_bc;
+
+typedef enum {
+    LB_STORE_F32 = 0,          /* distributions stored as FP32 (72 B/site/step moved)     */
+    LB_STORE_F16_OFFSET = 1,   /* stored as FP16 of f_a - w_a rho_ref (36 B/site/step)    */
+    LB_STORE_BF16_OFFSET = 2   /* stored as BF16 of f_a - w_a rho_ref (36 B/site/step)    */
+} lb_store;
+
+/* Run parameters.  Rates are the inverse relaxation times 1/tau of Eq. (2).
+ * The shear rate is per site: s_nu = 1/(3 nu + 1/2) with nu = nu_l where
+ * rho >= rho_switch and nu_g elsewhere (Sec. IV.C; Eq. (10) gives
+ * nu = (tau_nu - 1/2)/3).  s_rho and s_j are validated but, with the
+ * half-force velocity of Eq. (6), do not change the result (the density and
+ * momentum moments after collision are rho and rho v + F/2 for any rate). */
+typedef struct {
+    int32_t nx, ny;          /* grid size, each >= 3                                     */
+    int32_t bc;              /* lb_bc                                                    */
+    int32_t store;           /* lb_store                                                 */
+    double a, b, R, T;       /* Carnahan-Starling constants and absolute temperature,
+                                Eq. (30); b > 0, T > 0                                   */
+    double G;                /* interaction strength of Eq. (7), G < 0                   */
+    double sigma;            /* improved-forcing coefficient of Eq. (25), >= 0           */
+    double s_rho, s_e, s_zeta, s_j, s_q;   /* rates in (0, 2)                            */
+    double nu_l, nu_g;       /* kinematic viscosities, > 0                               */
+    double rho_switch;       /* density at which nu switches from nu_g to nu_l           */
+    double rho_ref;          /* reference density of the 16-bit offsets (ignored for F32) */
+} lb_params;
+
+/* An annulus r_min <= d < r_max around (cx, cy); d uses the minimum image in
+ * x, and in y when bc is periodic.  r_max may be +inf. */
+typedef struct {
+    double cx, cy, r_min, r_max;
+} lb_region;
+
+/* Reductions over the current state, accumulated in FP64 on the GPU in a
+ * fixed order (bitwise reproducible for a given grid and launch shape). */
+typedef struct {
+    double mass;             /* sum of rho                                               */
+    double mom_x, mom_y;     /* sum of rho v, v the half-force velocity of Eq. (6)       */
+    double p_in, p_out, dp;  /* mean p_EOS (Eq. 30) over region `in`, `out`, difference  */
+    double rho_in, rho_out;  /* mean rho over the two regions                            */
+    double n_in, n_out;      /* number of sites in each region                           */
+    double max_u;            /* max |v|                                                  */
+    int32_t unstable;        /* nonzero if a step since init saw an unstable site        */
+    int32_t reserved;
+    int64_t step;            /* time t of the state                                      */
+} lb_diag;
+
+typedef struct lb_ctx lb_ctx; /* opaque host-side context */
+
+/* Pure host check of the parameter block (no GPU needed).  LB_OK or LB_EINVAL. */
+lb_status lb_validate_params(const lb_params* p);
+
+/* Bytes of device workspace lb_init needs for these parameters (0 if invalid).
+ * Pure host function. */
+size_t lb_workspace_bytes(const lb_params* p);
+
+/* Bytes of one stored state (9 * nx * ny elements of the storage type), the
+ * size of the buffers lb_get_state / lb_set_state copy.  Pure host function. */
+size_t lb_state_bytes(const lb_params* p);
+
+/* Create a context and set the state at t = 0 to f_a = [M^-1 m_eq(rho0, u0)]_a,
+ * the equilibrium of Eq. (3) at every site.
+ *   workspace        device buffer of at least workspace_bytes (lb_workspace_bytes),
+ *                    256-byte aligned, owned by the caller and used by the context
+ *                    until lb_destroy.
+ *   rho0, ux0, uy0   device FP32 [ny][nx]; ux0/uy0 may be NULL (zero velocity).
+ *                    Read during this call only.
+ * Validates every rho0 on the device (finite, 0 < rho < 4/b, psi^2 > 0): this
+ * call synchronises `stream` once and returns LB_EINVAL if a value is out of
+ * range.  On failure *out is set to NULL. */
+lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t workspace_bytes,
+                  const float* rho0, const float* ux0, const float* uy0, void* stream);
+
+/* Advance nsteps >= 0 time steps (asynchronous; captured into graphs of
+ * lb_set_launch's chunk size when the stream is not the legacy stream).
+ * Instability is detected on the device and reported by lb_check /
+ * lb_diagnostics. */
+lb_status lb_step(lb_ctx* ctx, int64_t nsteps);
+
+/* Write rho and the half-force velocity v = (sum e f + F/2)/rho (Eq. 6) of the
+ * current state into device FP32 [ny][nx] buffers (asynchronous).  Any of the
+ * three pointers may be NULL. */
+lb_status lb_moments(lb_ctx* ctx, float* rho, float* ux, float* uy);
+
+/* Reductions of the current state over the whole grid and two regions (host
+ * pointers).  Synchronises the stream.  Returns LB_EUNSTABLE (and poisons the
+ * context) if an instability was flagged; *out is filled in either case. */
+lb_status lb_diagnostics(lb_ctx* ctx, const lb_region* in, const lb_region* out, lb_diag* diag);
+
+/* Synchronise the stream and report LB_EUNSTABLE if any step since lb_init
+ * flagged an unstable site (the context is then poisoned). */
+lb_status lb_check(lb_ctx* ctx);
+
+/* Current time t (host value, no synchronisation). */
+int64_t lb_time(const lb_ctx* ctx);
+
+/* Checkpoint: copy the stored state (the post-collision distributions of
+ * step t-1, laid out [9][ny][nx] in the storage type) to / from a device
+ * buffer of lb_state_bytes bytes (asynchronous).  lb_set_state also sets the
+ * time to t. */
+lb_status lb_get_state(lb_ctx* ctx, void* dst);
+lb_status lb_set_state(lb_ctx* ctx, const void* src, int64_t t);
+
+/* Launch shape: strip_rows = rows each wavefront walks (>= 1; 0 keeps the
+ * current value), graph_chunk = steps per captured graph (even, >= 2; 0 keeps).
+ * Results do not depend on either (bitwise). */
+lb_status lb_set_launch(lb_ctx* ctx, int32_t strip_rows, int32_t graph_chunk);
+
+/* Release the context and its graphs (not the caller's workspace). */
+lb_status lb_destroy(lb_ctx* ctx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* lb_last_error(void);
+
+/* Measurement utility (not part of the method): stream `bytes` (a multiple of
+ * 16) from device buffer src to device buffer dst with a plain copy kernel.
+ * Used as the attainable-HBM-bandwidth reference next to the step kernel and
+ * to calibrate hardware byte counters.  Asynchronous on `stream`. */
+lb_status lb_copy_probe(const void* src, void* dst, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMP_H */

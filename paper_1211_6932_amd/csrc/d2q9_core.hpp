@@ -1,0 +1,243 @@
+// d2q9_core.hpp -- device code of the improved MRT pseudopotential D2Q9 step
+// (Li, Luo & Li, arXiv:1211.6932) for gfx950.
+//
+// Layout in HBM: the stored state is the post-collision distribution f*
+// (pull streaming), structure-of-arrays f[alpha][y][pitch], alpha-major planes,
+// row pitch a multiple of 64 elements.  Two such buffers ping-pong.
+//
+// Work decomposition: one 64-lane wavefront owns a strip of 62 output columns
+// and `strip_rows` rows.  Lane l handles column x0 - 1 + l; lanes 0 and 63 are
+// halo columns that only evaluate the pseudopotential psi.  The wave walks
+// down the strip keeping psi of rows y-1, y, y+1 in registers; the x-neighbours
+// of psi come from the adjacent lanes by cross-lane shuffles, so the stencil of
+// Eq. (7) needs neither LDS nor workgroup barriers.  Rows y0-1 and y1 are
+// pulled once more per strip to provide the y-halo of psi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmp {
+
+constexpr int kWave = 64;
+constexpr int kTileW = kWave - 2;     // output columns per wavefront strip
+constexpr int kWavesPerBlock = 4;     // 256-thread workgroups
+constexpr int kDiagFields = 10;       // doubles per wave partial in the diagnostics pass
+
+enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2 };
+enum : int { kModeStep = 0, kModeMoments = 1, kModeDiag = 2 };
+enum : int { kFlagUnstable = 1, kFlagBadInput = 2 };
+
+// Per-launch constants (FP32 copies of FP64 host-derived values).
+struct StepConst {
+    int nx, ny, pitch;          // pitch in elements
+    int tiles_x, tiles_y, strip_rows;
+    long long plane;            // ny * pitch: elements per velocity plane
+    float b4;                   // b / 4
+    float RT;                   // R T
+    float a;                    // attraction constant of Eq. (30)
+    float two_over_G;           // 2 / G  (Eq. 24 with c = 1)
+    float negG;                 // -G     (Eq. 7)
+    float rho_switch;           // nu_l for rho >= rho_switch, nu_g below
+    float s_e, s_z, s_q, s_nu_l, s_nu_g;
+    float c_e, c_z;             // 12 sigma G^2 s_e, 12 sigma G^2 s_zeta (Eq. 25 through I - Lambda/2)
+    float off[9];               // w_a rho_ref: offsets of the 16-bit storage (0 for FP32)
+};
+
+// Diagnostics regions (annuli) and output.
+struct DiagConst {
+    double in_cx, in_cy, in_r0, in_r1;
+    double out_cx, out_cy, out_r0, out_r1;
+    int periodic_y;
+};
+
+// ---------------------------------------------------------------- storage codecs
+template <int S> struct Codec;
+
+template <> struct Codec<kStoreF32> {
+    using T = float;
+    static __device__ __forceinline__ float load(const T* __restrict__ p, long long i, float) { return p[i]; }
+    static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float) { p[i] = v; }
+};
+
+template <> struct Codec<kStoreF16> {
+    using T = _Float16;
+    static __device__ __forceinline__ float load(const T* __restrict__ p, long long i, float o) {
+        return static_cast<float>(p[i]) + o;
+    }
+    static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float o) {
+        p[i] = static_cast<_Float16>(v - o);  // round to nearest even
+    }
+};
+
+template <> struct Codec<kStoreBF16> {
+    using T = __bf16;
+    static __device__ __forceinline__ float load(const T* __restrict__ p, long long i, float o) {
+        return static_cast<float>(p[i]) + o;
+    }
+    static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float o) {
+        p[i] = static_cast<__bf16>(v - o);    // round to nearest even
+    }
+};
+
+// ---------------------------------------------------------------- streaming (Eq. 5)
+// Velocity ordering: 0 rest; 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1);
+// 5 (1,1); 6 (-1,1); 7 (-1,-1); 8 (1,-1).  Opposites 1-3, 2-4, 5-7, 6-8.
+//
+// Pull: f_a(x, y, t) = f*_a(x - e_a, t - 1).  At a wall (halfway bounce-back)
+// the population that would come from outside is the reversed one that left
+// the same site: f_a(x, t) = f*_abar(x, t - 1).
+template <int S, bool WALLS>
+__device__ __forceinline__ void pull_row(const typename Codec<S>::T* __restrict__ fin,
+                                         const StepConst& k, int y, int xm, int xc, int xp,
+                                         float f[9])
+{
+    using C = Codec<S>;
+    const long long P = k.plane;
+    const long long r0 = (long long)y * k.pitch;
+    int ya = y - 1, yb = y + 1;
+    bool bot = false, top = false;
+    if (WALLS) {
+        bot = ya < 0;
+        top = yb >= k.ny;
+    } else {
+        if (ya < 0) ya += k.ny;
+        if (yb >= k.ny) yb -= k.ny;
+    }
+    const long long ra = (long long)ya * k.pitch;
+    const long long rb = (long long)yb * k.pitch;
+    f[0] = C::load(fin, 0 * P + r0 + xc, k.off[0]);
+    f[1] = C::load(fin, 1 * P + r0 + xm, k.off[1]);
+    f[3] = C::load(fin, 3 * P + r0 + xp, k.off[3]);
+    if (!bot) {
+        f[2] = C::load(fin, 2 * P + ra + xc, k.off[2]);
+        f[5] = C::load(fin, 5 * P + ra + xm, k.off[5]);
+        f[6] = C::load(fin, 6 * P + ra + xp, k.off[6]);
+    } else {
+        f[2] = C::load(fin, 4 * P + r0 + xc, k.off[4]);
+        f[5] = C::load(fin, 7 * P + r0 + xc, k.off[7]);
+        f[6] = C::load(fin, 8 * P + r0 + xc, k.off[8]);
+    }
+    if (!top) {
+        f[4] = C::load(fin, 4 * P + rb + xc, k.off[4]);
+        f[7] = C::load(fin, 7 * P + rb + xp, k.off[7]);
+        f[8] = C::load(fin, 8 * P + rb + xm, k.off[8]);
+    } else {
+        f[4] = C::load(fin, 2 * P + r0 + xc, k.off[2]);
+        f[7] = C::load(fin, 5 * P + r0 + xc, k.off[5]);
+        f[8] = C::load(fin, 6 * P + r0 + xc, k.off[6]);
+    }
+}
+
+__device__ __forceinline__ float density(const float f[9])
+{
+    // Eq. (6): rho = sum_a f_a  (rest + axis + diagonal partial sums)
+    return f[0] + ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
+}
+
+// Eq. (30) Carnahan-Starling pressure.
+__device__ __forceinline__ float p_eos(float rho, const StepConst& k)
+{
+    const float eta = k.b4 * rho;
+    const float om = 1.0f - eta;
+    const float num = fmaf(eta, fmaf(eta, 1.0f - eta, 1.0f), 1.0f);  // 1 + eta + eta^2 - eta^3
+    const float inv = __builtin_amdgcn_rcpf(om * om * om);
+    return rho * fmaf(k.RT * num, inv, -k.a * rho);
+}
+
+// Eq. (24): psi = sqrt(2 (p_EOS - rho/3) / G).  Flags non-finite rho, b rho/4 >= 1
+// and psi^2 <= 0; psi is then taken as 0 so the step stays finite-cost.
+__device__ __forceinline__ float pseudopotential(float rho, const StepConst& k, bool& bad)
+{
+    const float psi2 = k.two_over_G * (p_eos(rho, k) - rho * (1.0f / 3.0f));
+    const bool ok = (psi2 > 0.0f) && (k.b4 * rho < 1.0f);
+    bad |= !ok;
+    return ok ? __builtin_amdgcn_sqrtf(psi2) : 0.0f;
+}
+
+// Eq. (7) with w(1) = 1/3, w(2) = 1/12, written out per neighbour:
+// psi rows m (y-1), c (y), p (y+1); columns L (x-1), C (x), R (x+1).
+__device__ __forceinline__ void force_stencil(float mL, float mC, float mR, float cL, float cC,
+                                              float cR, float pL, float pC, float pR,
+                                              const StepConst& k, float& Fx, float& Fy,
+                                              float& Fs2)
+{
+    const float sx = (1.0f / 3.0f) * (cR - cL) + (1.0f / 12.0f) * ((pR - pL) + (mR - mL));
+    const float sy = (1.0f / 3.0f) * (pC - mC) + (1.0f / 12.0f) * ((pR + pL) - (mR + mL));
+    const float g = k.negG * cC;
+    Fx = g * sx;
+    Fy = g * sy;
+    // |F|^2 / psi^2 = G^2 |sum w psi e|^2: the improved term of Eq. (25) needs no division
+    Fs2 = sx * sx + sy * sy;
+}
+
+// MRT collision of Eq. (4) with the forcing of Eq. (25), applied as
+// f* = f + M^-1 (m* - m) with M the orthogonal D2Q9 basis (rows rho, e, eps,
+// jx, qx, jy, qy, pxx, pxy; norms 9, 36, 36, 6, 12, 6, 12, 4, 4).
+// With v from Eq. (6): m*_rho - m_rho = 0 and m*_j - m_j = F exactly.
+// (1 - s/2) times the extra Eq. (25) terms equals +12 sigma G^2 s_e |Fs|^2 for e
+// and -12 sigma G^2 s_zeta |Fs|^2 for eps.
+__device__ __forceinline__ void collide(float f[9], float rho, float vx, float vy, float Fx,
+                                        float Fy, float Fs2, const StepConst& k)
+{
+    const float ax = f[1] + f[2] + f[3] + f[4];
+    const float dg = f[5] + f[6] + f[7] + f[8];
+    const float m_e = fmaf(-4.0f, f[0], fmaf(2.0f, dg, -ax));
+    const float m_z = fmaf(4.0f, f[0], fmaf(-2.0f, ax, dg));
+    const float d57 = f[5] - f[7], d68 = f[6] - f[8];
+    const float m_qx = fmaf(-2.0f, f[1] - f[3], d57 - d68);
+    const float m_qy = fmaf(-2.0f, f[2] - f[4], d57 + d68);
+    const float m_xx = (f[1] + f[3]) - (f[2] + f[4]);
+    const float m_xy = (f[5] + f[7]) - (f[6] + f[8]);
+
+    const float vF = vx * Fx + vy * Fy;
+    const float v2 = vx * vx + vy * vy;
+    const float s_nu = (rho >= k.rho_switch) ? k.s_nu_l : k.s_nu_g;
+
+    // m* - m for the non-conserved moments (Eq. 4, Eq. 3, Eq. 25)
+    const float dm_e = -k.s_e * (m_e - rho * fmaf(3.0f, v2, -2.0f))
+                       + (1.0f - 0.5f * k.s_e) * 6.0f * vF + k.c_e * Fs2;
+    const float dm_z = -k.s_z * (m_z - rho * fmaf(-3.0f, v2, 1.0f))
+                       - (1.0f - 0.5f * k.s_z) * 6.0f * vF - k.c_z * Fs2;
+    const float hq = 1.0f - 0.5f * k.s_q;
+    const float dm_qx = -k.s_q * (m_qx + rho * vx) - hq * Fx;
+    const float dm_qy = -k.s_q * (m_qy + rho * vy) - hq * Fy;
+    const float hn = 1.0f - 0.5f * s_nu;
+    const float dm_xx = -s_nu * (m_xx - rho * (vx * vx - vy * vy)) + hn * 2.0f * (vx * Fx - vy * Fy);
+    const float dm_xy = -s_nu * (m_xy - rho * vx * vy) + hn * (vx * Fy + vy * Fx);
+
+    // f* = f + M^-1 dm  (column k of M^-1 is row k of M divided by its norm)
+    const float te = dm_e * (1.0f / 36.0f), tz = dm_z * (1.0f / 36.0f);
+    const float jx = Fx * (1.0f / 6.0f), jy = Fy * (1.0f / 6.0f);
+    const float qx = dm_qx * (1.0f / 12.0f), qy = dm_qy * (1.0f / 12.0f);
+    const float pxx = dm_xx * 0.25f, pxy = dm_xy * 0.25f;
+    const float c_ax = -te - 2.0f * tz;
+    const float c_dg = 2.0f * te + tz;
+    f[0] += 4.0f * (tz - te);
+    f[1] += c_ax + jx - 2.0f * qx + pxx;
+    f[3] += c_ax - jx + 2.0f * qx + pxx;
+    f[2] += c_ax + jy - 2.0f * qy - pxx;
+    f[4] += c_ax - jy + 2.0f * qy - pxx;
+    const float xp = jx + qx, yp = jy + qy;
+    f[5] += c_dg + xp + yp + pxy;
+    f[6] += c_dg - xp + yp - pxy;
+    f[7] += c_dg - xp - yp + pxy;
+    f[8] += c_dg + xp - yp - pxy;
+}
+
+__device__ __forceinline__ float lane_from_left(float v) { return __shfl_up(v, 1, kWave); }
+__device__ __forceinline__ float lane_from_right(float v) { return __shfl_down(v, 1, kWave); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+}  // namespace lbmp

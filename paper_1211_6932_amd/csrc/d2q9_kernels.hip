@@ -1,0 +1,315 @@
+// d2q9_kernels.hip -- gfx950 kernels of the improved MRT pseudopotential D2Q9
+// method and their host-side launchers.
+//
+//   d2q9_strip<MODE>  one template walks a wavefront strip (pull, density,
+//                     psi, force, velocity) and then, by MODE, collides and
+//                     stores (the time step), writes rho/v (moments), or
+//                     accumulates FP64 reductions (diagnostics).
+//   d2q9_init         equilibrium initial state, written "pre-streamed" so
+//                     that the first pull returns f_eq(rho0, u0)
+//   diag_finalize     fixed-order FP64 reduction of the per-wave partials
+//   copy_probe        plain streaming copy: attainable-bandwidth reference
+#include "d2q9_core.hpp"
+#include "d2q9_launch.hpp"
+
+namespace lbmp {
+
+template <int S, bool WALLS, int MODE>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_strip(
+    const typename Codec<S>::T* __restrict__ fin, typename Codec<S>::T* __restrict__ fout,
+    StepConst k, int* __restrict__ flag, float* __restrict__ rho_out, float* __restrict__ ux_out,
+    float* __restrict__ uy_out, DiagConst dg, double* __restrict__ partial)
+{
+    using C = Codec<S>;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
+    const int tx = tile % k.tiles_x;
+    const int ty = tile / k.tiles_x;
+
+    // Column of this lane; lanes 0 and 63 are the psi halo.  Columns wrap in x.
+    const int xs = tx * kTileW - 1 + lane;
+    const bool live = (lane >= 1) && (lane <= kTileW) && (xs < k.nx);
+    int xc = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
+    if (xs > k.nx) xc = 0;  // beyond the right halo: in-range dummy column, never stored
+    const int xm = (xc == 0) ? k.nx - 1 : xc - 1;
+    const int xp = (xc == k.nx - 1) ? 0 : xc + 1;
+
+    const int y0 = ty * k.strip_rows;
+    const int y1 = min(y0 + k.strip_rows, k.ny);
+
+    bool bad = false;
+    float f[9], fn[9];
+
+    // psi of the row above the strip (y0 - 1), or its mirror at a wall
+    float pm = 0.0f;
+    int yh = y0 - 1;
+    if (!WALLS && yh < 0) yh += k.ny;
+    if (yh >= 0) {
+        pull_row<S, WALLS>(fin, k, yh, xm, xc, xp, fn);
+        pm = pseudopotential(density(fn), k, bad);
+    }
+    pull_row<S, WALLS>(fin, k, y0, xm, xc, xp, f);
+    float rc = density(f);
+    float pc = pseudopotential(rc, k, bad);
+    if (WALLS && y0 == 0) pm = pc;
+    float pmL = lane_from_left(pm), pmR = lane_from_right(pm);
+    float pcL = lane_from_left(pc), pcR = lane_from_right(pc);
+
+    double acc[kDiagFields];
+    if (MODE == kModeDiag) {
+        for (int i = 0; i < kDiagFields; ++i) acc[i] = 0.0;
+    }
+
+    for (int y = y0; y < y1; ++y) {
+        int yn = y + 1;
+        float pp, rn = 0.0f;
+        if (!WALLS || yn < k.ny) {
+            if (yn >= k.ny) yn -= k.ny;
+            pull_row<S, WALLS>(fin, k, yn, xm, xc, xp, fn);
+            rn = density(fn);
+            pp = pseudopotential(rn, k, bad);
+        } else {
+            pp = pc;  // mirror beyond the top wall
+        }
+        const float ppL = lane_from_left(pp), ppR = lane_from_right(pp);
+
+        float Fx, Fy, Fs2;
+        force_stencil(pmL, pm, pmR, pcL, pc, pcR, ppL, pp, ppR, k, Fx, Fy, Fs2);
+        const float jx = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));
+        const float jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
+        const float inv_rho = __builtin_amdgcn_rcpf(rc);
+        const float vx = fmaf(0.5f, Fx, jx) * inv_rho;
+        const float vy = fmaf(0.5f, Fy, jy) * inv_rho;
+
+        if (MODE == kModeStep) {
+            collide(f, rc, vx, vy, Fx, Fy, Fs2, k);
+            if (live) {
+                const long long o = (long long)y * k.pitch + xc;
+#pragma unroll
+                for (int a = 0; a < 9; ++a) C::store(fout, a * k.plane + o, f[a], k.off[a]);
+            }
+        } else if (MODE == kModeMoments) {
+            if (live) {
+                const long long o = (long long)y * k.nx + xc;
+                if (rho_out) rho_out[o] = rc;
+                if (ux_out) ux_out[o] = vx;
+                if (uy_out) uy_out[o] = vy;
+            }
+        } else {
+            if (live) {
+                const double r = rc;
+                const double p = p_eos(rc, k);
+                acc[0] += r;
+                acc[1] += r * (double)vx;
+                acc[2] += r * (double)vy;
+                double dx = fabs((double)xc - dg.in_cx);
+                dx = fmin(dx, (double)k.nx - dx);
+                double dy = fabs((double)y - dg.in_cy);
+                if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
+                double d = sqrt(dx * dx + dy * dy);
+                if (d >= dg.in_r0 && d < dg.in_r1) { acc[3] += p; acc[5] += r; acc[7] += 1.0; }
+                dx = fabs((double)xc - dg.out_cx);
+                dx = fmin(dx, (double)k.nx - dx);
+                dy = fabs((double)y - dg.out_cy);
+                if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
+                d = sqrt(dx * dx + dy * dy);
+                if (d >= dg.out_r0 && d < dg.out_r1) { acc[4] += p; acc[6] += r; acc[8] += 1.0; }
+                acc[9] = fmax(acc[9], (double)sqrtf(vx * vx + vy * vy));
+            }
+        }
+
+        // slide the window one row down
+        pmL = pcL; pm = pc; pmR = pcR;
+        pcL = ppL; pc = pp; pcR = ppR;
+        rc = rn;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[a] = fn[a];
+    }
+
+    if (MODE == kModeDiag) {
+        for (int i = 0; i < 9; ++i) acc[i] = wave_sum(acc[i]);
+        acc[9] = wave_max(acc[9]);
+        if (lane == 0) {
+            for (int i = 0; i < kDiagFields; ++i) partial[(long long)tile * kDiagFields + i] = acc[i];
+        }
+    }
+    if (bad) flag[0] = kFlagUnstable;  // vector store from any flagging lane; all write the same value
+}
+
+// Single-block, fixed-order reduction of per-wave partials (deterministic).
+__global__ __launch_bounds__(256) void diag_finalize(const double* __restrict__ partial, int ntiles,
+                                                     double* __restrict__ out)
+{
+    __shared__ double sh[256][kDiagFields];
+    double acc[kDiagFields];
+    for (int i = 0; i < kDiagFields; ++i) acc[i] = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += 256) {
+        for (int i = 0; i < 9; ++i) acc[i] += partial[(long long)t * kDiagFields + i];
+        acc[9] = fmax(acc[9], partial[(long long)t * kDiagFields + 9]);
+    }
+    for (int i = 0; i < kDiagFields; ++i) sh[threadIdx.x][i] = acc[i];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int i = 0; i < 9; ++i) sh[threadIdx.x][i] += sh[threadIdx.x + s][i];
+            sh[threadIdx.x][9] = fmax(sh[threadIdx.x][9], sh[threadIdx.x + s][9]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiagFields) out[threadIdx.x] = sh[0][threadIdx.x];
+}
+
+// Initial state.  Slot (z, b) of the stored (pre-streamed) buffer holds the
+// value the first pull will read: f_eq_b at z + e_b, or, where z + e_b lies
+// beyond a wall, f_eq_bbar at z (it comes back by bounce-back).
+// f_eq = M^-1 m_eq(rho, u) of Eq. (3), i.e. w_a rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u^2).
+template <int S, bool WALLS>
+__global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
+                                                 const float* __restrict__ ux0,
+                                                 const float* __restrict__ uy0,
+                                                 typename Codec<S>::T* __restrict__ fout,
+                                                 StepConst k, int* __restrict__ flag)
+{
+    using C = Codec<S>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= k.nx) return;
+    constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    constexpr float W[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
+                            1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+    {
+        // validate this site's input
+        const long long i = (long long)y * k.nx + x;
+        const float r = rho0[i];
+        const float ux = ux0 ? ux0[i] : 0.0f, uy = uy0 ? uy0[i] : 0.0f;
+        bool bad = !(r > 0.0f) || !isfinite(ux) || !isfinite(uy) || !isfinite(r);
+        if (!bad) pseudopotential(r, k, bad);
+        if (bad) flag[0] = kFlagBadInput;
+    }
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        int xs = x + EX[b];
+        xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
+        int ys = y + EY[b];
+        int a = b;
+        if (ys < 0 || ys >= k.ny) {
+            if (WALLS) { xs = x; ys = y; a = OPP[b]; }
+            else ys = ys < 0 ? ys + k.ny : ys - k.ny;
+        }
+        const long long i = (long long)ys * k.nx + xs;
+        const float r = rho0[i];
+        const float ux = ux0 ? ux0[i] : 0.0f, uy = uy0 ? uy0[i] : 0.0f;
+        const float eu = EX[a] * ux + EY[a] * uy;
+        const float feq = W[a] * r * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * (ux * ux + uy * uy));
+        C::store(fout, b * k.plane + (long long)y * k.pitch + x, feq, k.off[b]);
+    }
+}
+
+__global__ __launch_bounds__(256) void copy_probe(const float4* __restrict__ src,
+                                                  float4* __restrict__ dst, long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int strip_blocks(const StepConst& k)
+{
+    const long long tiles = (long long)k.tiles_x * k.tiles_y;
+    return (int)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
+template <int S, bool WALLS, int MODE>
+static hipError_t launch_mode(const void* fin, void* fout, const StepConst& k, int* flag,
+                              float* rho, float* ux, float* uy, const DiagConst& dg,
+                              double* partial, hipStream_t s)
+{
+    using T = typename Codec<S>::T;
+    hipLaunchKernelGGL((d2q9_strip<S, WALLS, MODE>), dim3(strip_blocks(k)),
+                       dim3(kWave * kWavesPerBlock), 0, s, static_cast<const T*>(fin),
+                       static_cast<T*>(fout), k, flag, rho, ux, uy, dg, partial);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t dispatch(int store, bool walls, const void* fin, void* fout, const StepConst& k,
+                           int* flag, float* rho, float* ux, float* uy, const DiagConst& dg,
+                           double* partial, hipStream_t s)
+{
+    switch (store) {
+    case kStoreF32:
+        return walls ? launch_mode<kStoreF32, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_mode<kStoreF32, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+    case kStoreF16:
+        return walls ? launch_mode<kStoreF16, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_mode<kStoreF16, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+    case kStoreBF16:
+        return walls ? launch_mode<kStoreBF16, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_mode<kStoreBF16, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
+                       int* flag, hipStream_t s)
+{
+    DiagConst dg{};
+    return dispatch<kModeStep>(store, walls, fin, fout, k, flag, nullptr, nullptr, nullptr, dg,
+                               nullptr, s);
+}
+
+hipError_t launch_moments(int store, bool walls, const void* fin, const StepConst& k, int* flag,
+                          float* rho, float* ux, float* uy, hipStream_t s)
+{
+    DiagConst dg{};
+    return dispatch<kModeMoments>(store, walls, fin, nullptr, k, flag, rho, ux, uy, dg, nullptr, s);
+}
+
+hipError_t launch_diag(int store, bool walls, const void* fin, const StepConst& k, int* flag,
+                       const DiagConst& dg, double* partial, double* out, hipStream_t s)
+{
+    hipError_t e = dispatch<kModeDiag>(store, walls, fin, nullptr, k, flag, nullptr, nullptr,
+                                       nullptr, dg, partial, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(diag_finalize, dim3(1), dim3(256), 0, s, partial, k.tiles_x * k.tiles_y, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux0,
+                       const float* uy0, void* fout, const StepConst& k, int* flag, hipStream_t s)
+{
+    dim3 grid((k.nx + 255) / 256, k.ny), block(256);
+#define LBMP_INIT(S_, W_)                                                                          \
+    hipLaunchKernelGGL((d2q9_init<S_, W_>), grid, block, 0, s, rho0, ux0, uy0,                     \
+                       static_cast<typename Codec<S_>::T*>(fout), k, flag)
+    switch (store) {
+    case kStoreF32: if (walls) LBMP_INIT(kStoreF32, true); else LBMP_INIT(kStoreF32, false); break;
+    case kStoreF16: if (walls) LBMP_INIT(kStoreF16, true); else LBMP_INIT(kStoreF16, false); break;
+    case kStoreBF16: if (walls) LBMP_INIT(kStoreBF16, true); else LBMP_INIT(kStoreBF16, false); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef LBMP_INIT
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, long long n16, hipStream_t s)
+{
+    int dev = 0, ncu = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    long long blocks = (n16 + 255) / 256;
+    const long long cap = (long long)ncu * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(copy_probe, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const float4*>(src), static_cast<float4*>(dst), n16);
+    return hipGetLastError();
+}
+
+}  // namespace lbmp

@@ -1,0 +1,31 @@
+// d2q9_launch.hpp -- host-side launchers of the D2Q9 kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "d2q9_core.hpp"
+
+namespace lbmp {
+
+// One time step: pull from `fin`, collide, store into `fout` (both the
+// post-collision layout).  Sets flag[0] on an unstable site.
+hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
+                       int* flag, hipStream_t s);
+
+// rho and v of the state in `fin` into unpadded [ny][nx] FP32 buffers (NULL allowed).
+hipError_t launch_moments(int store, bool walls, const void* fin, const StepConst& k, int* flag,
+                          float* rho, float* ux, float* uy, hipStream_t s);
+
+// FP64 reductions of the state in `fin`: per-wave partials, then a fixed-order
+// single-block pass into out[kDiagFields].
+hipError_t launch_diag(int store, bool walls, const void* fin, const StepConst& k, int* flag,
+                       const DiagConst& dg, double* partial, double* out, hipStream_t s);
+
+// Equilibrium initial state into `fout`; flag[0] = kFlagBadInput on invalid input.
+hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux0,
+                       const float* uy0, void* fout, const StepConst& k, int* flag, hipStream_t s);
+
+// Streaming copy of n16 16-byte elements (attainable-bandwidth reference).
+hipError_t launch_copy_probe(const void* src, void* dst, long long n16, hipStream_t s);
+
+}  // namespace lbmp

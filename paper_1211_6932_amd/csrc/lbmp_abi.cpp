@@ -1,0 +1,437 @@
+// lbmp_abi.cpp -- host runtime behind the C ABI of include/lbmp.h.
+//
+// Responsibilities: parameter validation (pure host), FP64 derivation of the
+// FP32 kernel constants, carving of the caller-owned workspace, graph capture
+// and replay of step loops, error state.  Every numerical step of the method
+// runs in the kernels of d2q9_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbmp.h"
+#include "d2q9_launch.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lb_status fail(lb_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+lb_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(LB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kDiagStripRows = 32;
+constexpr int kDefaultStripRows = 64;
+constexpr int kDefaultGraphChunk = 32;
+constexpr int kMaxSide = 1 << 20;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int store) { return store == LB_STORE_F32 ? 4 : 2; }
+
+int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+
+struct Layout {
+    size_t flag_off, dout_off, partial_off, f_off[2], total, buf_bytes;
+    int diag_tiles;
+};
+
+Layout layout_of(const lb_params& p)
+{
+    Layout L{};
+    const int pitch = pitch_of(p.nx);
+    L.buf_bytes = align_up((size_t)9 * p.ny * pitch * elem_bytes(p.store), kAlign);
+    const int tx = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
+    const int ty = (p.ny + kDiagStripRows - 1) / kDiagStripRows;
+    L.diag_tiles = tx * ty;
+    L.flag_off = 0;
+    L.dout_off = kAlign;
+    L.partial_off = 2 * kAlign;
+    size_t off = align_up(L.partial_off + (size_t)L.diag_tiles * lbmp::kDiagFields * sizeof(double), kAlign);
+    L.f_off[0] = off;
+    L.f_off[1] = off + L.buf_bytes;
+    L.total = off + 2 * L.buf_bytes;
+    return L;
+}
+
+bool finite_all(std::initializer_list<double> v)
+{
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+bool rate_ok(double s) { return s > 0.0 && s < 2.0; }
+
+lb_status validate(const lb_params* p)
+{
+    if (!p) return fail(LB_EINVAL, "params is NULL");
+    if (p->nx < 3 || p->ny < 3 || p->nx > kMaxSide || p->ny > kMaxSide)
+        return fail(LB_EINVAL, "nx and ny must lie in [3, 2^20]");
+    if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LB_EINVAL, "nx * ny exceeds 2^31 sites");
+    if (p->bc != LB_BC_PERIODIC && p->bc != LB_BC_WALLS_Y) return fail(LB_EINVAL, "unknown bc");
+    if (p->store < LB_STORE_F32 || p->store > LB_STORE_BF16_OFFSET) return fail(LB_EINVAL, "unknown store");
+    if (!finite_all({p->a, p->b, p->R, p->T, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta, p->s_j,
+                     p->s_q, p->nu_l, p->nu_g, p->rho_switch, p->rho_ref}))
+        return fail(LB_EINVAL, "non-finite parameter");
+    if (!(p->b > 0.0) || !(p->T > 0.0) || !(p->R > 0.0) || !(p->a >= 0.0))
+        return fail(LB_EINVAL, "need a >= 0, b > 0, R > 0, T > 0");
+    if (!(p->G < 0.0)) return fail(LB_EINVAL, "need G < 0 (Eq. 24 radicand)");
+    if (!(p->sigma >= 0.0)) return fail(LB_EINVAL, "need sigma >= 0");
+    if (!rate_ok(p->s_rho) || !rate_ok(p->s_e) || !rate_ok(p->s_zeta) || !rate_ok(p->s_j) ||
+        !rate_ok(p->s_q))
+        return fail(LB_EINVAL, "relaxation rates must lie in (0, 2)");
+    if (!(p->nu_l > 0.0) || !(p->nu_g > 0.0)) return fail(LB_EINVAL, "viscosities must be > 0");
+    if (!(p->rho_switch >= 0.0)) return fail(LB_EINVAL, "rho_switch must be >= 0");
+    if (p->store != LB_STORE_F32 && !(p->rho_ref >= 0.0)) return fail(LB_EINVAL, "rho_ref must be >= 0");
+    return LB_OK;
+}
+
+lbmp::StepConst derive(const lb_params& p, int strip_rows)
+{
+    lbmp::StepConst k{};
+    k.nx = p.nx;
+    k.ny = p.ny;
+    k.pitch = pitch_of(p.nx);
+    k.strip_rows = strip_rows;
+    k.tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
+    k.tiles_y = (p.ny + strip_rows - 1) / strip_rows;
+    k.plane = (long long)p.ny * k.pitch;
+    k.b4 = (float)(p.b / 4.0);
+    k.RT = (float)(p.R * p.T);
+    k.a = (float)p.a;
+    k.two_over_G = (float)(2.0 / p.G);
+    k.negG = (float)(-p.G);
+    k.rho_switch = (float)p.rho_switch;
+    k.s_e = (float)p.s_e;
+    k.s_z = (float)p.s_zeta;
+    k.s_q = (float)p.s_q;
+    k.s_nu_l = (float)(1.0 / (3.0 * p.nu_l + 0.5));
+    k.s_nu_g = (float)(1.0 / (3.0 * p.nu_g + 0.5));
+    const double G2 = p.G * p.G;
+    k.c_e = (float)(12.0 * p.sigma * G2 * p.s_e);
+    k.c_z = (float)(12.0 * p.sigma * G2 * p.s_zeta);
+    static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    for (int a = 0; a < 9; ++a) k.off[a] = p.store == LB_STORE_F32 ? 0.0f : (float)(w[a] * p.rho_ref);
+    return k;
+}
+
+}  // namespace
+
+struct lb_ctx {
+    lb_params p;
+    Layout L;
+    lbmp::StepConst k;   // step launches
+    lbmp::StepConst kd;  // moments / diagnostics launches
+    char* ws;
+    void* f[2];
+    int* flag;
+    double* dout;
+    double* partial;
+    int cur;
+    int64_t t;
+    hipStream_t stream;
+    int graph_chunk;
+    hipGraph_t graph[2];
+    hipGraphExec_t exec[2];
+    bool poisoned;
+};
+
+namespace {
+
+void drop_graphs(lb_ctx* c)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (c->exec[i]) (void)hipGraphExecDestroy(c->exec[i]);
+        if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+        c->exec[i] = nullptr;
+        c->graph[i] = nullptr;
+    }
+}
+
+lb_status step_direct(lb_ctx* c, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        hipError_t e = lbmp::launch_step(c->p.store, c->p.bc == LB_BC_WALLS_Y, c->f[c->cur],
+                                         c->f[c->cur ^ 1], c->k, c->flag, c->stream);
+        if (e != hipSuccess) {
+            c->poisoned = true;
+            return hip_fail(e, "step launch");
+        }
+        c->cur ^= 1;
+        c->t += 1;
+    }
+    return LB_OK;
+}
+
+lb_status build_graph(lb_ctx* c, int from)
+{
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int cur = from;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < c->graph_chunk && le == hipSuccess; ++i) {
+        le = lbmp::launch_step(c->p.store, c->p.bc == LB_BC_WALLS_Y, c->f[cur], c->f[cur ^ 1], c->k,
+                               c->flag, c->stream);
+        cur ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "step launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    c->graph[from] = g;
+    c->exec[from] = x;
+    return LB_OK;
+}
+
+lb_status read_flag(lb_ctx* c, int* host_flag)
+{
+    hipError_t e = hipMemcpyAsync(host_flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return hip_fail(e, "reading the device flag");
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_validate_params(const lb_params* p) { return validate(p); }
+
+size_t lb_workspace_bytes(const lb_params* p)
+{
+    if (validate(p) != LB_OK) return 0;
+    return layout_of(*p).total;
+}
+
+size_t lb_state_bytes(const lb_params* p)
+{
+    if (validate(p) != LB_OK) return 0;
+    return (size_t)9 * p->nx * p->ny * elem_bytes(p->store);
+}
+
+lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t workspace_bytes,
+                  const float* rho0, const float* ux0, const float* uy0, void* stream)
+{
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    lb_status st = validate(p);
+    if (st != LB_OK) return st;
+    if (!workspace || !rho0) return fail(LB_EINVAL, "workspace and rho0 must be non-NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(LB_EINVAL, "workspace must be 256-byte aligned");
+    Layout L = layout_of(*p);
+    if (workspace_bytes < L.total)
+        return fail(LB_ENOMEM, "workspace smaller than lb_workspace_bytes");
+
+    lb_ctx* c = new (std::nothrow) lb_ctx{};
+    if (!c) return fail(LB_ENOMEM, "host allocation failed");
+    c->p = *p;
+    c->L = L;
+    c->k = derive(*p, kDefaultStripRows);
+    c->kd = derive(*p, kDiagStripRows);
+    c->ws = static_cast<char*>(workspace);
+    c->flag = reinterpret_cast<int*>(c->ws + L.flag_off);
+    c->dout = reinterpret_cast<double*>(c->ws + L.dout_off);
+    c->partial = reinterpret_cast<double*>(c->ws + L.partial_off);
+    c->f[0] = c->ws + L.f_off[0];
+    c->f[1] = c->ws + L.f_off[1];
+    c->stream = static_cast<hipStream_t>(stream);
+    c->graph_chunk = kDefaultGraphChunk;
+
+    hipError_t e = hipMemsetAsync(c->flag, 0, kAlign, c->stream);
+    if (e == hipSuccess)
+        e = lbmp::launch_init(p->store, p->bc == LB_BC_WALLS_Y, rho0, ux0, uy0, c->f[0], c->k,
+                              c->flag, c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "init launch");
+    }
+    int hf = 0;
+    st = read_flag(c, &hf);
+    if (st != LB_OK) {
+        delete c;
+        return st;
+    }
+    if (hf & lbmp::kFlagBadInput) {
+        delete c;
+        return fail(LB_EINVAL, "rho0/u0 out of range (need finite, rho > 0, b rho/4 < 1, psi^2 > 0)");
+    }
+    c->cur = 0;
+    c->t = 0;
+    *out = c;
+    g_last_error.clear();
+    return LB_OK;
+}
+
+lb_status lb_step(lb_ctx* c, int64_t n)
+{
+    if (!c) return fail(LB_EINVAL, "ctx is NULL");
+    if (c->poisoned) return fail(LB_ESTATE, "context poisoned by an earlier failure");
+    if (n < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+    if (c->stream != nullptr) {
+        while (n >= c->graph_chunk) {
+            if (!c->exec[c->cur]) {
+                lb_status st = build_graph(c, c->cur);
+                if (st != LB_OK) {
+                    c->poisoned = true;
+                    return st;
+                }
+            }
+            hipError_t e = hipGraphLaunch(c->exec[c->cur], c->stream);
+            if (e != hipSuccess) {
+                c->poisoned = true;
+                return hip_fail(e, "hipGraphLaunch");
+            }
+            n -= c->graph_chunk;
+            c->t += c->graph_chunk;  // chunk is even: the state returns to buffer cur
+        }
+    }
+    return step_direct(c, n);
+}
+
+lb_status lb_moments(lb_ctx* c, float* rho, float* ux, float* uy)
+{
+    if (!c) return fail(LB_EINVAL, "ctx is NULL");
+    if (c->poisoned) return fail(LB_ESTATE, "context poisoned by an earlier failure");
+    hipError_t e = lbmp::launch_moments(c->p.store, c->p.bc == LB_BC_WALLS_Y, c->f[c->cur], c->kd,
+                                        c->flag, rho, ux, uy, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "moments launch");
+    return LB_OK;
+}
+
+lb_status lb_diagnostics(lb_ctx* c, const lb_region* in, const lb_region* outr, lb_diag* d)
+{
+    if (!c || !in || !outr || !d) return fail(LB_EINVAL, "NULL argument");
+    if (c->poisoned) return fail(LB_ESTATE, "context poisoned by an earlier failure");
+    lbmp::DiagConst dg{in->cx, in->cy, in->r_min, in->r_max,
+                       outr->cx, outr->cy, outr->r_min, outr->r_max,
+                       c->p.bc == LB_BC_PERIODIC ? 1 : 0};
+    hipError_t e = lbmp::launch_diag(c->p.store, c->p.bc == LB_BC_WALLS_Y, c->f[c->cur], c->kd,
+                                     c->flag, dg, c->partial, c->dout, c->stream);
+    double h[lbmp::kDiagFields];
+    int hf = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hf, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return hip_fail(e, "diagnostics");
+    }
+    std::memset(d, 0, sizeof(*d));
+    d->mass = h[0];
+    d->mom_x = h[1];
+    d->mom_y = h[2];
+    d->n_in = h[7];
+    d->n_out = h[8];
+    d->p_in = h[7] > 0 ? h[3] / h[7] : NAN;
+    d->p_out = h[8] > 0 ? h[4] / h[8] : NAN;
+    d->rho_in = h[7] > 0 ? h[5] / h[7] : NAN;
+    d->rho_out = h[8] > 0 ? h[6] / h[8] : NAN;
+    d->dp = d->p_in - d->p_out;
+    d->max_u = h[9];
+    d->unstable = hf & lbmp::kFlagUnstable;
+    d->step = c->t;
+    if (d->unstable) {
+        c->poisoned = true;
+        return fail(LB_EUNSTABLE, "unstable site (non-finite rho or psi^2 <= 0) since init");
+    }
+    return LB_OK;
+}
+
+lb_status lb_check(lb_ctx* c)
+{
+    if (!c) return fail(LB_EINVAL, "ctx is NULL");
+    if (c->poisoned) return fail(LB_ESTATE, "context poisoned by an earlier failure");
+    int hf = 0;
+    lb_status st = read_flag(c, &hf);
+    if (st != LB_OK) return st;
+    if (hf & lbmp::kFlagUnstable) {
+        c->poisoned = true;
+        return fail(LB_EUNSTABLE, "unstable site (non-finite rho or psi^2 <= 0) since init");
+    }
+    return LB_OK;
+}
+
+int64_t lb_time(const lb_ctx* c) { return c ? c->t : -1; }
+
+lb_status lb_get_state(lb_ctx* c, void* dst)
+{
+    if (!c || !dst) return fail(LB_EINVAL, "NULL argument");
+    const size_t eb = elem_bytes(c->p.store);
+    hipError_t e = hipMemcpy2DAsync(dst, (size_t)c->p.nx * eb, c->f[c->cur], (size_t)c->k.pitch * eb,
+                                    (size_t)c->p.nx * eb, (size_t)9 * c->p.ny, hipMemcpyDeviceToDevice,
+                                    c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lb_get_state copy");
+    return LB_OK;
+}
+
+lb_status lb_set_state(lb_ctx* c, const void* src, int64_t t)
+{
+    if (!c || !src) return fail(LB_EINVAL, "NULL argument");
+    if (t < 0) return fail(LB_EINVAL, "t must be >= 0");
+    const size_t eb = elem_bytes(c->p.store);
+    hipError_t e = hipMemcpy2DAsync(c->f[0], (size_t)c->k.pitch * eb, src, (size_t)c->p.nx * eb,
+                                    (size_t)c->p.nx * eb, (size_t)9 * c->p.ny, hipMemcpyDeviceToDevice,
+                                    c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lb_set_state copy");
+    c->cur = 0;
+    c->t = t;
+    return LB_OK;
+}
+
+lb_status lb_set_launch(lb_ctx* c, int32_t strip_rows, int32_t graph_chunk)
+{
+    if (!c) return fail(LB_EINVAL, "ctx is NULL");
+    if (strip_rows < 0 || graph_chunk < 0) return fail(LB_EINVAL, "negative launch parameter");
+    if (graph_chunk != 0 && (graph_chunk < 2 || graph_chunk % 2))
+        return fail(LB_EINVAL, "graph_chunk must be even and >= 2");
+    drop_graphs(c);
+    if (strip_rows > 0) c->k = derive(c->p, strip_rows);
+    if (graph_chunk > 0) c->graph_chunk = graph_chunk;
+    return LB_OK;
+}
+
+lb_status lb_destroy(lb_ctx* c)
+{
+    if (!c) return LB_OK;
+    drop_graphs(c);
+    delete c;
+    return LB_OK;
+}
+
+const char* lb_last_error(void) { return g_last_error.c_str(); }
+
+lb_status lb_copy_probe(const void* src, void* dst, size_t bytes, void* stream)
+{
+    if (!src || !dst || bytes % 16) return fail(LB_EINVAL, "need non-NULL buffers and bytes % 16 == 0");
+    hipError_t e = lbmp::launch_copy_probe(src, dst, (long long)(bytes / 16), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "copy probe launch");
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+"""ctypes binding of liblbmp.so (include/lbmp.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  The functions keep the C names; ``Sim`` is a small convenience
+wrapper that lets torch supply device memory and the stream.
+
+The library must have been built (``python -m paper_1211_6932_amd.build``);
+importing this module raises if it is missing, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmp.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
+LB_BC_PERIODIC, LB_BC_WALLS_Y = 0, 1
+LB_STORE_F32, LB_STORE_F16_OFFSET, LB_STORE_BF16_OFFSET = 0, 1, 2
+STORE_NAMES = {"f32": LB_STORE_F32, "f16": LB_STORE_F16_OFFSET, "bf16": LB_STORE_BF16_OFFSET}
+STATUS_NAMES = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EHIP", -4: "LB_EUNSTABLE",
+                -5: "LB_ESTATE"}
+
+
+class lb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc", ctypes.c_int32), ("store", ctypes.c_int32),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("T", ctypes.c_double),
+        ("G", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("s_rho", ctypes.c_double), ("s_e", ctypes.c_double), ("s_zeta", ctypes.c_double),
+        ("s_j", ctypes.c_double), ("s_q", ctypes.c_double),
+        ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("rho_switch", ctypes.c_double),
+        ("rho_ref", ctypes.c_double),
+    ]
+
+
+class lb_region(ctypes.Structure):
+    _fields_ = [("cx", ctypes.c_double), ("cy", ctypes.c_double), ("r_min", ctypes.c_double),
+                ("r_max", ctypes.c_double)]
+
+
+class lb_diag(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double),
+        ("p_in", ctypes.c_double), ("p_out", ctypes.c_double), ("dp", ctypes.c_double),
+        ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("n_in", ctypes.c_double), ("n_out", ctypes.c_double), ("max_u", ctypes.c_double),
+        ("unstable", ctypes.c_int32), ("reserved", ctypes.c_int32), ("step", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+EXPORTS = [
+    "lb_validate_params", "lb_workspace_bytes", "lb_state_bytes", "lb_init", "lb_step", "lb_moments",
+    "lb_diagnostics", "lb_check", "lb_time", "lb_get_state", "lb_set_state", "lb_set_launch",
+    "lb_destroy", "lb_last_error", "lb_copy_probe",
+]
+
+_lib = None
+
+
+def load():
+    """Load liblbmp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1211_6932_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(lb_params)
+    vp = ctypes.c_void_p
+    L.lb_validate_params.argtypes = [P]
+    L.lb_validate_params.restype = ctypes.c_int
+    L.lb_workspace_bytes.argtypes = [P]
+    L.lb_workspace_bytes.restype = ctypes.c_size_t
+    L.lb_state_bytes.argtypes = [P]
+    L.lb_state_bytes.restype = ctypes.c_size_t
+    L.lb_init.argtypes = [ctypes.POINTER(vp), P, vp, ctypes.c_size_t, vp, vp, vp, vp]
+    L.lb_init.restype = ctypes.c_int
+    L.lb_step.argtypes = [vp, ctypes.c_int64]
+    L.lb_step.restype = ctypes.c_int
+    L.lb_moments.argtypes = [vp, vp, vp, vp]
+    L.lb_moments.restype = ctypes.c_int
+    L.lb_diagnostics.argtypes = [vp, ctypes.POINTER(lb_region), ctypes.POINTER(lb_region),
+                                 ctypes.POINTER(lb_diag)]
+    L.lb_diagnostics.restype = ctypes.c_int
+    L.lb_check.argtypes = [vp]
+    L.lb_check.restype = ctypes.c_int
+    L.lb_time.argtypes = [vp]
+    L.lb_time.restype = ctypes.c_int64
+    L.lb_get_state.argtypes = [vp, vp]
+    L.lb_get_state.restype = ctypes.c_int
+    L.lb_set_state.argtypes = [vp, vp, ctypes.c_int64]
+    L.lb_set_state.restype = ctypes.c_int
+    L.lb_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.lb_set_launch.restype = ctypes.c_int
+    L.lb_destroy.argtypes = [vp]
+    L.lb_destroy.restype = ctypes.c_int
+    L.lb_last_error.argtypes = []
+    L.lb_last_error.restype = ctypes.c_char_p
+    L.lb_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.lb_copy_probe.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class LbError(RuntimeError):
+    def __init__(self, status, where):
+        msg = load().lb_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({msg})")
+        self.status = status
+
+
+def _check(status, where):
+    if status != LB_OK:
+        raise LbError(status, where)
+    return status
+
+
+def make_params(d: dict, store="f32", rho_ref=0.0) -> lb_params:
+    """lb_params from a parameter dictionary (keys as in the C struct)."""
+    s = STORE_NAMES[store] if isinstance(store, str) else int(store)
+    return lb_params(int(d["nx"]), int(d["ny"]), int(d.get("bc", 0)), s,
+                     float(d["a"]), float(d["b"]), float(d["R"]), float(d["T"]), float(d["G"]),
+                     float(d["sigma"]), float(d["s_rho"]), float(d["s_e"]), float(d["s_zeta"]),
+                     float(d["s_j"]), float(d["s_q"]), float(d["nu_l"]), float(d["nu_g"]),
+                     float(d["rho_switch"]), float(rho_ref))
+
+
+# -------------------------------------------------------------- C names (marshalling only)
+
+def lb_validate_params(p: lb_params) -> int:
+    return load().lb_validate_params(ctypes.byref(p))
+
+
+def lb_workspace_bytes(p: lb_params) -> int:
+    return load().lb_workspace_bytes(ctypes.byref(p))
+
+
+def lb_state_bytes(p: lb_params) -> int:
+    return load().lb_state_bytes(ctypes.byref(p))
+
+
+def lb_init(p: lb_params, workspace_ptr: int, workspace_bytes: int, rho0_ptr: int, ux0_ptr,
+            uy0_ptr, stream: int):
+    ctx = ctypes.c_void_p()
+    st = load().lb_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(workspace_ptr),
+                        workspace_bytes, ctypes.c_void_p(rho0_ptr), ctypes.c_void_p(ux0_ptr or None),
+                        ctypes.c_void_p(uy0_ptr or None), ctypes.c_void_p(stream or None))
+    _check(st, "lb_init")
+    return ctx
+
+
+def lb_step(ctx, n: int):
+    return _check(load().lb_step(ctx, int(n)), "lb_step")
+
+
+def lb_moments(ctx, rho_ptr, ux_ptr, uy_ptr):
+    return _check(load().lb_moments(ctx, ctypes.c_void_p(rho_ptr or None), ctypes.c_void_p(ux_ptr or None),
+                                    ctypes.c_void_p(uy_ptr or None)), "lb_moments")
+
+
+def lb_diagnostics(ctx, region_in: lb_region, region_out: lb_region, raise_unstable=True) -> lb_diag:
+    d = lb_diag()
+    st = load().lb_diagnostics(ctx, ctypes.byref(region_in), ctypes.byref(region_out), ctypes.byref(d))
+    if st != LB_OK and (raise_unstable or st != LB_EUNSTABLE):
+        raise LbError(st, "lb_diagnostics")
+    return d
+
+
+def lb_check(ctx) -> int:
+    return load().lb_check(ctx)
+
+
+def lb_time(ctx) -> int:
+    return load().lb_time(ctx)
+
+
+def lb_get_state(ctx, dst_ptr: int):
+    return _check(load().lb_get_state(ctx, ctypes.c_void_p(dst_ptr)), "lb_get_state")
+
+
+def lb_set_state(ctx, src_ptr: int, t: int):
+    return _check(load().lb_set_state(ctx, ctypes.c_void_p(src_ptr), int(t)), "lb_set_state")
+
+
+def lb_set_launch(ctx, strip_rows: int = 0, graph_chunk: int = 0):
+    return _check(load().lb_set_launch(ctx, int(strip_rows), int(graph_chunk)), "lb_set_launch")
+
+
+def lb_destroy(ctx):
+    return load().lb_destroy(ctx)
+
+
+def lb_last_error() -> str:
+    return load().lb_last_error().decode(errors="replace")
+
+
+def lb_copy_probe(src_ptr: int, dst_ptr: int, nbytes: int, stream: int):
+    return _check(load().lb_copy_probe(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(nbytes),
+                                       ctypes.c_void_p(stream or None)), "lb_copy_probe")
+
+
+# -------------------------------------------------------------- torch convenience wrapper
+
+class Sim:
+    """One lattice on the current ROCm device.  torch allocates the workspace,
+    the input/output fields and (by default) a dedicated non-default stream."""
+
+    def __init__(self, params: dict, rho0, ux0=None, uy0=None, store="f32", rho_ref=0.0,
+                 stream=None, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("lbmp.Sim needs a ROCm GPU")
+        self.torch = torch
+        self.p = make_params(params, store, rho_ref)
+        _check(lb_validate_params(self.p), "lb_validate_params")
+        self.nx, self.ny = self.p.nx, self.p.ny
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.device = torch.device(device)
+        shape = (self.ny, self.nx)
+
+        def dev(t):
+            if t is None:
+                return None
+            t = torch.as_tensor(t)
+            if tuple(t.shape) != shape:
+                raise ValueError(f"field shape {tuple(t.shape)} != {shape}")
+            return t.to(device=self.device, dtype=torch.float32).contiguous()
+
+        r, ux, uy = dev(rho0), dev(ux0), dev(uy0)
+        nbytes = lb_workspace_bytes(self.p)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(self.stream):
+            # the inputs were produced on torch's current stream
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            self.ctx = lb_init(self.p, self.workspace.data_ptr(), nbytes, r.data_ptr(),
+                               ux.data_ptr() if ux is not None else 0,
+                               uy.data_ptr() if uy is not None else 0, self.stream.cuda_stream)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None:
+            try:
+                self.stream.synchronize()
+            finally:
+                lb_destroy(ctx)
+            self.ctx = None
+
+    @property
+    def t(self):
+        return lb_time(self.ctx)
+
+    def step(self, n=1):
+        lb_step(self.ctx, n)
+        return self
+
+    def set_launch(self, strip_rows=0, graph_chunk=0):
+        lb_set_launch(self.ctx, strip_rows, graph_chunk)
+
+    def moments(self):
+        """(rho, ux, uy) FP32 device tensors [ny][nx] at the current time."""
+        torch = self.torch
+        out = [torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) for _ in range(3)]
+        lb_moments(self.ctx, *[o.data_ptr() for o in out])
+        self.stream.synchronize()
+        return tuple(out)
+
+    def check(self):
+        st = lb_check(self.ctx)
+        if st != LB_OK:
+            raise LbError(st, "lb_check")
+
+    def diagnostics(self, cx, cy, r_in, r_out0, r_out1=math.inf, raise_unstable=True):
+        """Reductions with region in = d < r_in and out = r_out0 <= d < r_out1 around (cx, cy)."""
+        rin = lb_region(cx, cy, 0.0, r_in)
+        rout = lb_region(cx, cy, r_out0, r_out1)
+        return lb_diagnostics(self.ctx, rin, rout, raise_unstable).as_dict()
+
+    def get_state(self):
+        torch = self.torch
+        buf = torch.empty(lb_state_bytes(self.p), dtype=torch.uint8, device=self.device)
+        lb_get_state(self.ctx, buf.data_ptr())
+        self.stream.synchronize()
+        return buf
+
+    def set_state(self, buf, t):
+        lb_set_state(self.ctx, buf.data_ptr(), t)
+        self.stream.synchronize()

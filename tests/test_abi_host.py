@@ -1,0 +1,108 @@
+"""C ABI checks that need no GPU: the library loads, exports every function the
+header declares, and the pure host functions validate and size correctly."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import workloads as W
+from paper_1211_6932_amd import lbmp as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbmp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(lb\w*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("lb_init", "lb_step", "lb_moments", "lb_diagnostics", "lb_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+    assert set(B.EXPORTS) <= exported
+
+
+def test_struct_layouts_match_header():
+    # lb_params: 4 int32 + 15 doubles; lb_diag: 11 doubles + 2 int32 + int64
+    assert ctypes.sizeof(B.lb_params) == 16 + 15 * 8
+    assert ctypes.sizeof(B.lb_diag) == 11 * 8 + 8 + 8
+    assert ctypes.sizeof(B.lb_region) == 32
+
+
+def good():
+    return B.make_params(W.stationary_droplet(n=128).params)
+
+
+def test_validate_accepts_paper_parameters():
+    assert B.lb_validate_params(good()) == B.LB_OK
+    sp = W.splash(nx=64, ny=32).params
+    assert B.lb_validate_params(B.make_params(sp)) == B.LB_OK
+    for st in ("f16", "bf16"):
+        assert B.lb_validate_params(B.make_params(sp, st, 0.47)) == B.LB_OK
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 2), ("ny", 0), ("nx", (1 << 20) + 1), ("bc", 2), ("store", 3), ("b", 0.0), ("T", -1.0),
+    ("G", 0.0), ("G", 1.0), ("sigma", -0.1), ("s_e", 0.0), ("s_e", 2.0), ("s_q", 2.5),
+    ("s_rho", -1.0), ("s_j", 2.0), ("nu_l", 0.0), ("nu_g", -0.1), ("a", float("nan")),
+    ("R", 0.0), ("T", float("inf")),
+])
+def test_validate_rejects(field, value):
+    p = good()
+    setattr(p, field, value)
+    assert B.lb_validate_params(p) == B.LB_EINVAL
+    assert B.lb_last_error() != ""
+    assert B.lb_workspace_bytes(p) == 0
+    assert B.lb_state_bytes(p) == 0
+
+
+def test_sizes():
+    p = good()
+    assert B.lb_state_bytes(p) == 9 * 128 * 128 * 4
+    ws = B.lb_workspace_bytes(p)
+    assert ws >= 2 * 9 * 128 * 128 * 4 and ws % 256 == 0
+    p.store = B.LB_STORE_F16_OFFSET
+    assert B.lb_state_bytes(p) == 9 * 128 * 128 * 2
+    # ragged widths are padded to 64-element rows
+    p2 = good()
+    p2.nx, p2.ny = 67, 5
+    assert B.lb_workspace_bytes(p2) >= 2 * 9 * 5 * 128 * 4
+
+
+def test_host_side_errors_need_no_gpu():
+    L = B.load()
+    p = good()
+    ctx = ctypes.c_void_p()
+    # NULL out pointer, NULL workspace, bad params: rejected before any device work
+    assert L.lb_init(None, ctypes.byref(p), None, 0, None, None, None, None) == B.LB_EINVAL
+    assert L.lb_init(ctypes.byref(ctx), ctypes.byref(p), None, 0, None, None, None, None) == B.LB_EINVAL
+    p.nx = 1
+    assert L.lb_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(256), 1 << 30,
+                     ctypes.c_void_p(256), None, None, None) == B.LB_EINVAL
+    p = good()
+    assert L.lb_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(256 + 8), 1 << 30,
+                     ctypes.c_void_p(256), None, None, None) == B.LB_EINVAL  # misaligned
+    assert L.lb_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(256), 16,
+                     ctypes.c_void_p(256), None, None, None) == B.LB_ENOMEM
+    assert L.lb_step(None, 1) == B.LB_EINVAL
+    assert L.lb_moments(None, None, None, None) == B.LB_EINVAL
+    assert L.lb_check(None) == B.LB_EINVAL
+    assert L.lb_time(None) == -1
+    assert L.lb_destroy(None) == B.LB_OK
+    assert L.lb_copy_probe(None, None, 16, None) == B.LB_EINVAL

@@ -1,0 +1,330 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP32 kernel against the FP64 oracle, same FP32-rounded inputs):
+  * 1000 steps of the 128 x 128 stationary droplet: max|d rho| / rho_l <= 1e-5 and
+    max|d u| <= 1e-3 max|u| + 1e-7;
+  * one step from the same state: |d f*| <= 2e-6 max|f| (a few FP32 roundings of
+    O(1e-1) values through ~100 operations);
+  * launch shapes, graph replay, checkpoints and translations: bitwise.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import lbref as O
+from oracle import post
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1211_6932_amd.lbmp")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    B.load()  # fails loudly if the HIP library is not built
+    yield
+
+
+def f32(a):
+    return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def make_sim(w, store="f32", rho_ref=0.0, strip_rows=0, stream=None):
+    r, ux, uy = f32(w.rho0), f32(w.ux0), f32(w.uy0)
+    s = B.Sim(w.params, torch.from_numpy(r), None if ux is None else torch.from_numpy(ux),
+              None if uy is None else torch.from_numpy(uy), store=store, rho_ref=rho_ref, stream=stream)
+    if strip_rows:
+        s.set_launch(strip_rows=strip_rows)
+    return s
+
+
+def make_oracle(w):
+    r, ux, uy = f32(w.rho0), f32(w.ux0), f32(w.uy0)
+    return O.State(O.Params(**w.params), r.astype(np.float64),
+                   None if ux is None else ux.astype(np.float64),
+                   None if uy is None else uy.astype(np.float64))
+
+
+def gpu_moments(s):
+    return [m.cpu().numpy().astype(np.float64) for m in s.moments()]
+
+
+def gpu_state(s):
+    """Stored state as float64 [9][ny][nx] (post-collision f* of the previous step)."""
+    buf = s.get_state()
+    if s.p.store == B.LB_STORE_F32:
+        a = buf.view(torch.float32)
+    elif s.p.store == B.LB_STORE_F16_OFFSET:
+        a = buf.view(torch.float16).float()
+    else:
+        a = buf.view(torch.bfloat16).float()
+    a = a.cpu().numpy().astype(np.float64).reshape(9, s.ny, s.nx)
+    if s.p.store != B.LB_STORE_F32:
+        w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+        a = a + (w * s.p.rho_ref)[:, None, None]
+    return a
+
+
+def print_case(name, **kw):
+    print(f"[gpu-case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+# ------------------------------------------------------------------ initial state
+
+def test_init_state_and_moments_match_oracle():
+    w = W.stationary_droplet(n=128, R0=25)
+    print_case("init", shape=(128, 128))
+    s, o = make_sim(w), make_oracle(w)
+    f_gpu = O.stream(O.Params(**w.params), gpu_state(s))
+    assert np.abs(f_gpu - o.f).max() <= 2e-8
+    rho, ux, uy = gpu_moments(s)
+    ro, uxo, uyo, *_ = o.moments()
+    assert np.abs(rho - ro).max() <= 1e-7
+    assert np.abs(ux - uxo).max() <= 1e-7 and np.abs(uy - uyo).max() <= 1e-7
+
+
+def test_init_with_velocity_and_walls_matches_oracle():
+    w = W.splash(nx=150, ny=90, Re=200)
+    print_case("init_walls", shape=(90, 150))
+    s, o = make_sim(w), make_oracle(w)
+    f_gpu = O.stream(O.Params(**w.params), gpu_state(s))
+    assert np.abs(f_gpu - o.f).max() <= 2e-8
+
+
+# ------------------------------------------------------------------ one step, element by element
+
+@pytest.mark.parametrize("case", ["droplet_periodic", "splash_walls", "ragged_periodic"])
+def test_one_step_every_site_matches_oracle(case):
+    if case == "droplet_periodic":
+        w = W.stationary_droplet(n=128, R0=25)
+    elif case == "splash_walls":
+        w = W.splash(nx=200, ny=150, Re=200)
+    else:
+        w = W.stationary_droplet(n=67, R0=12)  # 2 column tiles, ragged tail
+        w.params.update(nx=67, ny=67)
+    print_case("one_step", case=case, shape=(w.params["ny"], w.params["nx"]))
+    s = make_sim(w, strip_rows=16)
+    s.step(7)
+    S7 = gpu_state(s)
+    s.step(1)
+    S8 = gpu_state(s)
+    p = O.Params(**w.params)
+    f7 = O.stream(p, S7)
+    ny, nx = w.params["ny"], w.params["nx"]
+    ref = O.collide_at(p, f7, np.arange(nx * ny)).T.reshape(9, ny, nx)
+    err = np.abs(S8 - ref).max()
+    assert err <= 2e-6 * np.abs(ref).max(), err
+
+
+# ------------------------------------------------------------------ the parity gate
+
+def test_stationary_droplet_1000_steps_parity():
+    """128 x 128 periodic droplet (a = 0.5, T = 0.6 T_c, R0 = 25, nu 0.1 / 0.3),
+    FP32 GPU against the FP64 oracle after 1000 steps."""
+    w = W.stationary_droplet(n=128, R0=25)
+    print_case("parity_1000", shape=(128, 128))
+    s, o = make_sim(w), make_oracle(w)
+    s.step(1000)
+    s.check()
+    o.step(1000)
+    rho, ux, uy = gpu_moments(s)
+    ro, uxo, uyo, *_ = o.moments()
+    rho_l = w.info["rho_l"]
+    drho = np.abs(rho - ro).max() / rho_l
+    umax = np.sqrt(uxo ** 2 + uyo ** 2).max()
+    du = max(np.abs(ux - uxo).max(), np.abs(uy - uyo).max())
+    print(f"max|drho|/rho_l = {drho:.3e}  max|du| = {du:.3e}  max|u| = {umax:.3e}")
+    assert drho <= 1e-5
+    assert du <= 1e-3 * umax + 1e-7
+
+
+def test_walls_300_steps_parity():
+    """Splash geometry on a 200 x 150 crop (walls in y, x periodic, 4 column tiles,
+    ragged strips), 300 steps."""
+    w = W.splash(nx=200, ny=150, Re=200)
+    print_case("walls_300", shape=(150, 200))
+    s, o = make_sim(w, strip_rows=40), make_oracle(w)
+    s.step(300)
+    s.check()
+    o.step(300)
+    rho, ux, uy = gpu_moments(s)
+    ro, uxo, uyo, *_ = o.moments()
+    drho = np.abs(rho - ro).max() / w.info["rho_l"]
+    du = max(np.abs(ux - uxo).max(), np.abs(uy - uyo).max())
+    umax = np.sqrt(uxo ** 2 + uyo ** 2).max()
+    print(f"walls: max|drho|/rho_l = {drho:.3e}  max|du| = {du:.3e}  max|u| = {umax:.3e}")
+    assert drho <= 1e-5
+    assert du <= 1e-3 * umax + 1e-7
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (5, 3), (3, 70), (64, 3), (63, 125)])
+def test_tiny_and_ragged_grids(shape):
+    """Degenerate sizes: single-tile grids down to 3 x 3, a strip thinner than a tile."""
+    ny, nx = shape
+    rng = np.random.default_rng(nx * 1000 + ny)
+    p = W.base_params(nx, ny, a=0.5, t_over_tc=0.8)
+    rho0 = 0.2 + 0.02 * rng.standard_normal((ny, nx))
+    w = W.Workload("tiny", p, rho0)
+    print_case("tiny", shape=shape)
+    for bc in (0, 1):
+        w.params["bc"] = bc
+        s, o = make_sim(w, strip_rows=2), make_oracle(w)
+        s.step(50)
+        o.step(50)
+        rho, ux, uy = gpu_moments(s)
+        ro, uxo, uyo, *_ = o.moments()
+        assert np.abs(rho - ro).max() <= 1e-5 * 0.2
+        assert max(np.abs(ux - uxo).max(), np.abs(uy - uyo).max()) <= 1e-6
+
+
+# ------------------------------------------------------------------ bitwise invariances
+
+def test_launch_shape_and_graph_do_not_change_bits():
+    w = W.splash(nx=190, ny=100, Re=1000)
+    print_case("launch_shapes", shape=(100, 190))
+    ref = None
+    for rows, chunk, stream in [(64, 32, None), (1, 2, None), (7, 8, None), (1000, 4, None),
+                                (13, 32, "default")]:
+        st = torch.cuda.default_stream() if stream == "default" else None
+        s = make_sim(w, stream=st)
+        if stream == "default":
+            # the legacy stream cannot be captured: plain launches
+            pass
+        s.set_launch(strip_rows=rows, graph_chunk=chunk)
+        s.step(37)
+        state = s.get_state().cpu().numpy()
+        if ref is None:
+            ref = state
+        else:
+            assert np.array_equal(state, ref), (rows, chunk, stream)
+
+
+def test_checkpoint_resume_is_bitwise():
+    w = W.stationary_droplet(n=96, R0=20)
+    print_case("checkpoint", shape=(96, 96))
+    a = make_sim(w)
+    a.step(40)
+    ref = a.get_state().cpu().numpy()
+    b = make_sim(w)
+    b.step(15)
+    snap = b.get_state()
+    c = make_sim(W.stationary_droplet(n=96, R0=30))  # different field, same shape
+    c.set_state(snap, 15)
+    c.step(25)
+    assert c.t == 40
+    assert np.array_equal(c.get_state().cpu().numpy(), ref)
+
+
+def test_translation_is_bitwise():
+    """Periodic box: shifting rho0 across tile borders shifts the result exactly."""
+    w = W.stationary_droplet(n=130, R0=20)
+    print_case("translation", shape=(130, 130))
+    dy, dx = 37, 61
+    w2 = W.Workload("shifted", dict(w.params), np.roll(w.rho0, (dy, dx), axis=(0, 1)))
+    s1, s2 = make_sim(w, strip_rows=32), make_sim(w2, strip_rows=32)
+    s1.step(60)
+    s2.step(60)
+    r1 = s1.moments()[0].cpu().numpy()
+    r2 = s2.moments()[0].cpu().numpy()
+    assert np.array_equal(np.roll(r1, (dy, dx), axis=(0, 1)), r2)
+
+
+def test_determinism_two_runs():
+    w = W.splash(nx=256, ny=128, Re=200)
+    a, b = make_sim(w), make_sim(w)
+    a.step(50)
+    b.step(50)
+    assert np.array_equal(a.get_state().cpu().numpy(), b.get_state().cpu().numpy())
+
+
+# ------------------------------------------------------------------ diagnostics
+
+def test_diagnostics_match_oracle_postprocessing():
+    w = W.stationary_droplet(n=128, R0=25)
+    print_case("diagnostics", shape=(128, 128))
+    s, o = make_sim(w), make_oracle(w)
+    s.step(500)
+    o.step(500)
+    c = (128 - 1) / 2.0
+    R0 = 25.0
+    d = s.diagnostics(c, c, R0 / 2 + 1e-12, R0 + 15.0)
+    ro, uxo, uyo, *_ = o.moments()
+    lp = post.laplace(ro, w.params, R0)
+    assert d["mass"] == pytest.approx(ro.sum(), rel=1e-6)
+    assert d["p_in"] == pytest.approx(lp["p_in"], rel=1e-5)
+    assert d["p_out"] == pytest.approx(lp["p_out"], rel=1e-5)
+    assert d["dp"] == pytest.approx(lp["dp"], rel=1e-3)
+    assert d["rho_in"] == pytest.approx(lp["rho_in"], rel=1e-5)
+    assert d["max_u"] == pytest.approx(np.sqrt(uxo ** 2 + uyo ** 2).max(), rel=1e-3)
+    dist = post.distance_field(128, 128, c, c)
+    assert d["n_in"] == (dist < R0 / 2 + 1e-12).sum()
+    assert d["n_out"] == (dist >= R0 + 15.0).sum()
+    # exact mass conservation of the FP32 step (FP64 sum)
+    d0 = make_sim(w).diagnostics(c, c, 1.0, 2.0)
+    assert d["mass"] == pytest.approx(d0["mass"], rel=2e-6)
+
+
+# ------------------------------------------------------------------ failure handling
+
+def test_unstable_run_is_flagged_and_poisons():
+    """The original forcing (sigma = 0) below T/T_c ~ 0.8 drives the vapour density
+    out of the EOS domain (the oracle fails the same way)."""
+    w = W.stationary_droplet(n=64, R0=14, t_over_tc=0.6, sigma=0.0)
+    o = make_oracle(w)
+    with pytest.raises(O.OracleError):
+        o.step(400)
+    s = make_sim(w)
+    s.step(400)
+    with pytest.raises(B.LbError) as e:
+        s.check()
+    assert e.value.status == B.LB_EUNSTABLE
+    with pytest.raises(B.LbError) as e:
+        s.step(1)
+    assert e.value.status == B.LB_ESTATE
+
+
+def test_init_rejects_out_of_range_density():
+    w = W.stationary_droplet(n=64, R0=14)
+    bad = w.rho0.copy()
+    bad[3, 5] = np.nan
+    with pytest.raises(B.LbError) as e:
+        make_sim(W.Workload("nan", w.params, bad))
+    assert e.value.status == B.LB_EINVAL
+    bad = w.rho0.copy()
+    bad[10, 10] = 0.9  # b rho / 4 < 1 but psi^2 < 0 (above the liquid limit ~0.57)
+    with pytest.raises(B.LbError) as e:
+        make_sim(W.Workload("dense", w.params, bad))
+    assert e.value.status == B.LB_EINVAL
+
+
+# ------------------------------------------------------------------ full size, sampled
+
+def test_full_size_sampled_one_step_parity():
+    """8192 x 4096 splash (bench workload and launch shape): after 2 steps, the GPU's
+    third step at 40,000 sampled sites (plus every tile corner row/column sample)
+    matches the oracle's collision of the streamed GPU state."""
+    w = W.splash(scale=4, Re=200)
+    ny, nx = w.params["ny"], w.params["nx"]
+    print_case("full_size", shape=(ny, nx))
+    s = make_sim(w)
+    s.step(2)
+    S2 = gpu_state(s)
+    s.step(1)
+    S3 = gpu_state(s)
+    p = O.Params(**w.params)
+    f2 = O.stream(p, S2)
+    del S2
+    rng = np.random.default_rng(2024)
+    ys = np.concatenate([rng.integers(0, ny, 40000), [0, 0, ny - 1, ny - 1, 63, 64, 127, 128]])
+    xs = np.concatenate([rng.integers(0, nx, 40000), [0, nx - 1, 0, nx - 1, 61, 62, 123, 124]])
+    sites = ys.astype(np.int64) * nx + xs
+    ref = O.collide_at(p, f2, sites)
+    got = S3[:, ys, xs].T
+    err = np.abs(got - ref).max()
+    assert err <= 2e-6 * np.abs(ref).max(), err
