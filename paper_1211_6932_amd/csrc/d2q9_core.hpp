@@ -58,6 +58,9 @@ template <> struct Codec<kStoreF32> {
     using T = float;
     static __device__ __forceinline__ float load(const T* __restrict__ p, long long i, float) { return p[i]; }
     static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float) { p[i] = v; }
+    static __device__ __forceinline__ void store_init(T* __restrict__ p, long long i, double v, double) {
+        p[i] = static_cast<float>(v);
+    }
 };
 
 template <> struct Codec<kStoreF16> {
@@ -68,6 +71,9 @@ template <> struct Codec<kStoreF16> {
     static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float o) {
         p[i] = static_cast<_Float16>(v - o);  // round to nearest even
     }
+    static __device__ __forceinline__ void store_init(T* __restrict__ p, long long i, double v, double o) {
+        p[i] = static_cast<_Float16>(static_cast<float>(v - o));
+    }
 };
 
 template <> struct Codec<kStoreBF16> {
@@ -77,6 +83,9 @@ template <> struct Codec<kStoreBF16> {
     }
     static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float o) {
         p[i] = static_cast<__bf16>(v - o);    // round to nearest even
+    }
+    static __device__ __forceinline__ void store_init(T* __restrict__ p, long long i, double v, double o) {
+        p[i] = static_cast<__bf16>(static_cast<float>(v - o));
     }
 };
 
@@ -104,29 +113,24 @@ __device__ __forceinline__ void pull_row(const typename Codec<S>::T* __restrict_
         if (ya < 0) ya += k.ny;
         if (yb >= k.ny) yb -= k.ny;
     }
-    const long long ra = (long long)ya * k.pitch;
-    const long long rb = (long long)yb * k.pitch;
+    // At a wall the three populations of a row group come from the reversed
+    // planes of the same site: select plane, row and column (wave-uniform planes
+    // and rows; the offsets w_a rho_ref of opposite directions are equal).
+    const long long ra = (long long)(bot ? y : ya) * k.pitch;
+    const long long rb = (long long)(top ? y : yb) * k.pitch;
+    const long long p2 = (bot ? 4 : 2) * P, p5 = (bot ? 7 : 5) * P, p6 = (bot ? 8 : 6) * P;
+    const long long p4 = (top ? 2 : 4) * P, p7 = (top ? 5 : 7) * P, p8 = (top ? 6 : 8) * P;
+    const int x5 = bot ? xc : xm, x6 = bot ? xc : xp;
+    const int x7 = top ? xc : xp, x8 = top ? xc : xm;
     f[0] = C::load(fin, 0 * P + r0 + xc, k.off[0]);
     f[1] = C::load(fin, 1 * P + r0 + xm, k.off[1]);
     f[3] = C::load(fin, 3 * P + r0 + xp, k.off[3]);
-    if (!bot) {
-        f[2] = C::load(fin, 2 * P + ra + xc, k.off[2]);
-        f[5] = C::load(fin, 5 * P + ra + xm, k.off[5]);
-        f[6] = C::load(fin, 6 * P + ra + xp, k.off[6]);
-    } else {
-        f[2] = C::load(fin, 4 * P + r0 + xc, k.off[4]);
-        f[5] = C::load(fin, 7 * P + r0 + xc, k.off[7]);
-        f[6] = C::load(fin, 8 * P + r0 + xc, k.off[8]);
-    }
-    if (!top) {
-        f[4] = C::load(fin, 4 * P + rb + xc, k.off[4]);
-        f[7] = C::load(fin, 7 * P + rb + xp, k.off[7]);
-        f[8] = C::load(fin, 8 * P + rb + xm, k.off[8]);
-    } else {
-        f[4] = C::load(fin, 2 * P + r0 + xc, k.off[2]);
-        f[7] = C::load(fin, 5 * P + r0 + xc, k.off[5]);
-        f[8] = C::load(fin, 6 * P + r0 + xc, k.off[6]);
-    }
+    f[2] = C::load(fin, p2 + ra + xc, k.off[2]);
+    f[5] = C::load(fin, p5 + ra + x5, k.off[5]);
+    f[6] = C::load(fin, p6 + ra + x6, k.off[6]);
+    f[4] = C::load(fin, p4 + rb + xc, k.off[4]);
+    f[7] = C::load(fin, p7 + rb + x7, k.off[7]);
+    f[8] = C::load(fin, p8 + rb + x8, k.off[8]);
 }
 
 __device__ __forceinline__ float density(const float f[9])
@@ -141,18 +145,23 @@ __device__ __forceinline__ float p_eos(float rho, const StepConst& k)
     const float eta = k.b4 * rho;
     const float om = 1.0f - eta;
     const float num = fmaf(eta, fmaf(eta, 1.0f - eta, 1.0f), 1.0f);  // 1 + eta + eta^2 - eta^3
-    const float inv = __builtin_amdgcn_rcpf(om * om * om);
+    const float inv = 1.0f / (om * om * om);  // correctly rounded (see pseudopotential)
     return rho * fmaf(k.RT * num, inv, -k.a * rho);
 }
 
 // Eq. (24): psi = sqrt(2 (p_EOS - rho/3) / G).  Flags non-finite rho, b rho/4 >= 1
 // and psi^2 <= 0; psi is then taken as 0 so the step stays finite-cost.
+// The divisions and the square root here and for 1/rho are the correctly rounded
+// IEEE forms, not the 1-ulp hardware approximations: the force of Eq. (7) takes
+// differences of neighbouring psi values, so an ulp-level staircase error in psi
+// becomes force noise, which in FP32 roughly quadruples the drift from the
+// FP64 solution over 10^3 steps.
 __device__ __forceinline__ float pseudopotential(float rho, const StepConst& k, bool& bad)
 {
     const float psi2 = k.two_over_G * (p_eos(rho, k) - rho * (1.0f / 3.0f));
     const bool ok = (psi2 > 0.0f) && (k.b4 * rho < 1.0f);
     bad |= !ok;
-    return ok ? __builtin_amdgcn_sqrtf(psi2) : 0.0f;
+    return ok ? sqrtf(psi2) : 0.0f;
 }
 
 // Eq. (7) with w(1) = 1/3, w(2) = 1/12, written out per neighbour:

@@ -14,8 +14,13 @@
 
 namespace lbmp {
 
+#ifndef LBMP_STEP_WAVES_PER_EU
+#define LBMP_STEP_WAVES_PER_EU 1
+#endif
+
 template <int S, bool WALLS, int MODE>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_strip(
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
     const typename Codec<S>::T* __restrict__ fin, typename Codec<S>::T* __restrict__ fout,
     StepConst k, int* __restrict__ flag, float* __restrict__ rho_out, float* __restrict__ ux_out,
     float* __restrict__ uy_out, DiagConst dg, double* __restrict__ partial)
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_strip(
         force_stencil(pmL, pm, pmR, pcL, pc, pcR, ppL, pp, ppR, k, Fx, Fy, Fs2);
         const float jx = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));
         const float jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
-        const float inv_rho = __builtin_amdgcn_rcpf(rc);
+        const float inv_rho = 1.0f / rc;
         const float vx = fmaf(0.5f, Fx, jx) * inv_rho;
         const float vy = fmaf(0.5f, Fy, jy) * inv_rho;
 
@@ -163,13 +168,15 @@ __global__ __launch_bounds__(256) void diag_finalize(const double* __restrict__ 
 // Initial state.  Slot (z, b) of the stored (pre-streamed) buffer holds the
 // value the first pull will read: f_eq_b at z + e_b, or, where z + e_b lies
 // beyond a wall, f_eq_bbar at z (it comes back by bounce-back).
-// f_eq = M^-1 m_eq(rho, u) of Eq. (3), i.e. w_a rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u^2).
+// f_eq = M^-1 m_eq(rho, u) of Eq. (3), i.e. w_a rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u^2),
+// evaluated in FP64 and rounded once, so that the stored values sum to rho0 to
+// within the rounding of each population.
 template <int S, bool WALLS>
 __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
                                                  const float* __restrict__ ux0,
                                                  const float* __restrict__ uy0,
                                                  typename Codec<S>::T* __restrict__ fout,
-                                                 StepConst k, int* __restrict__ flag)
+                                                 StepConst k, double rho_ref, int* __restrict__ flag)
 {
     using C = Codec<S>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -178,8 +185,8 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
     constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    constexpr float W[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
-                            1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+    constexpr double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     {
         // validate this site's input
         const long long i = (long long)y * k.nx + x;
@@ -200,20 +207,30 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
             else ys = ys < 0 ? ys + k.ny : ys - k.ny;
         }
         const long long i = (long long)ys * k.nx + xs;
-        const float r = rho0[i];
-        const float ux = ux0 ? ux0[i] : 0.0f, uy = uy0 ? uy0[i] : 0.0f;
-        const float eu = EX[a] * ux + EY[a] * uy;
-        const float feq = W[a] * r * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * (ux * ux + uy * uy));
-        C::store(fout, b * k.plane + (long long)y * k.pitch + x, feq, k.off[b]);
+        const double r = rho0[i];
+        const double ux = ux0 ? ux0[i] : 0.0, uy = uy0 ? uy0[i] : 0.0;
+        const double eu = EX[a] * ux + EY[a] * uy;
+        const double feq = W[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
+        C::store_init(fout, b * k.plane + (long long)y * k.pitch + x, feq, W[b] * rho_ref);
     }
 }
 
+// Each thread moves 4 x 16 B with all loads issued before the stores.
 __global__ __launch_bounds__(256) void copy_probe(const float4* __restrict__ src,
                                                   float4* __restrict__ dst, long long n)
 {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        dst[i] = src[i];
+    const long long base = (long long)blockIdx.x * (256 * 4) + threadIdx.x;
+    float4 v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const long long j = base + i * 256;
+        if (j < n) v[i] = src[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const long long j = base + i * 256;
+        if (j < n) dst[j] = v[i];
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -282,12 +299,13 @@ hipError_t launch_diag(int store, bool walls, const void* fin, const StepConst& 
 }
 
 hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux0,
-                       const float* uy0, void* fout, const StepConst& k, int* flag, hipStream_t s)
+                       const float* uy0, void* fout, const StepConst& k, double rho_ref, int* flag,
+                       hipStream_t s)
 {
     dim3 grid((k.nx + 255) / 256, k.ny), block(256);
 #define LBMP_INIT(S_, W_)                                                                          \
     hipLaunchKernelGGL((d2q9_init<S_, W_>), grid, block, 0, s, rho0, ux0, uy0,                     \
-                       static_cast<typename Codec<S_>::T*>(fout), k, flag)
+                       static_cast<typename Codec<S_>::T*>(fout), k, rho_ref, flag)
     switch (store) {
     case kStoreF32: if (walls) LBMP_INIT(kStoreF32, true); else LBMP_INIT(kStoreF32, false); break;
     case kStoreF16: if (walls) LBMP_INIT(kStoreF16, true); else LBMP_INIT(kStoreF16, false); break;
@@ -300,13 +318,8 @@ hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux
 
 hipError_t launch_copy_probe(const void* src, void* dst, long long n16, hipStream_t s)
 {
-    int dev = 0, ncu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    long long blocks = (n16 + 255) / 256;
-    const long long cap = (long long)ncu * 16;
-    if (blocks > cap) blocks = cap;
-    if (blocks < 1) blocks = 1;
+    const long long blocks = (n16 + 1023) / 1024;
+    if (blocks < 1 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(copy_probe, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float4*>(src), static_cast<float4*>(dst), n16);
     return hipGetLastError();

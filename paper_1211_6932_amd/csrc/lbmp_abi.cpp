@@ -32,7 +32,7 @@ lb_status hip_fail(hipError_t e, const char* what)
 
 constexpr size_t kAlign = 256;
 constexpr int kDiagStripRows = 32;
-constexpr int kDefaultStripRows = 64;
+constexpr int kDefaultStripRows = 8;
 constexpr int kDefaultGraphChunk = 32;
 constexpr int kMaxSide = 1 << 20;
 
@@ -265,7 +265,7 @@ lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t work
     hipError_t e = hipMemsetAsync(c->flag, 0, kAlign, c->stream);
     if (e == hipSuccess)
         e = lbmp::launch_init(p->store, p->bc == LB_BC_WALLS_Y, rho0, ux0, uy0, c->f[0], c->k,
-                              c->flag, c->stream);
+                              p->store == LB_STORE_F32 ? 0.0 : p->rho_ref, c->flag, c->stream);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "init launch");
