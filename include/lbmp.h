@@ -150,16 +150,20 @@ lb_status lb_check(lb_ctx* ctx);
 int64_t lb_time(const lb_ctx* ctx);
 
 /* Checkpoint: copy the stored state (the post-collision distributions of
- * step t-1, laid out [9][ny][nx] in the storage type) to / from a device
- * buffer of lb_state_bytes bytes (asynchronous).  lb_set_state also sets the
- * time to t. */
+ * step t-1, exported as [9][ny][nx] in the storage type, velocity ordering
+ * rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1)) to / from
+ * a device buffer of lb_state_bytes bytes (asynchronous).  lb_set_state also
+ * sets the time to t. */
 lb_status lb_get_state(lb_ctx* ctx, void* dst);
 lb_status lb_set_state(lb_ctx* ctx, const void* src, int64_t t);
 
-/* Launch shape: strip_rows = rows each wavefront walks (>= 1; 0 keeps the
- * current value), graph_chunk = steps per captured graph (even, >= 2; 0 keeps).
- * Results do not depend on either (bitwise). */
-lb_status lb_set_launch(lb_ctx* ctx, int32_t strip_rows, int32_t graph_chunk);
+/* Launch shape of the step kernel.  strip_rows = rows each wavefront walks;
+ * band = strips per tile band (the wavefronts of a workgroup cover `band`
+ * strips in y times the rest in x); graph_chunk = steps per captured graph
+ * (even, >= 2).  For each: a positive value sets it, 0 keeps the current
+ * value, -1 (strip_rows, band only) restores the automatic choice.  Results do
+ * not depend on any of them (bitwise). */
+lb_status lb_set_launch(lb_ctx* ctx, int32_t strip_rows, int32_t band, int32_t graph_chunk);
 
 /* Release the context and its graphs (not the caller's workspace). */
 lb_status lb_destroy(lb_ctx* ctx);

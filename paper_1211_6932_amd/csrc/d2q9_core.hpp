@@ -2,8 +2,11 @@
 // (Li, Luo & Li, arXiv:1211.6932) for gfx950.
 //
 // Layout in HBM: the stored state is the post-collision distribution f*
-// (pull streaming), structure-of-arrays f[alpha][y][pitch], alpha-major planes,
-// row pitch a multiple of 64 elements.  Two such buffers ping-pong.
+// (pull streaming), row-interleaved structure of arrays f[y][alpha][pitch]: the
+// nine population rows of one lattice row are contiguous, x fastest, row pitch
+// a multiple of 64 elements.  A row's pull then reads three contiguous blocks
+// (rows y-1, y, y+1) and its store writes one, instead of touching 18 separate
+// planes.  Two such buffers ping-pong.
 //
 // Work decomposition: one 64-lane wavefront owns a strip of 62 output columns
 // and `strip_rows` rows.  Lane l handles column x0 - 1 + l; lanes 0 and 63 are
@@ -21,7 +24,14 @@ namespace lbmp {
 
 constexpr int kWave = 64;
 constexpr int kTileW = kWave - 2;     // output columns per wavefront strip
-constexpr int kWavesPerBlock = 4;     // 256-thread workgroups
+#ifndef LBMP_WAVES_PER_BLOCK
+#define LBMP_WAVES_PER_BLOCK 16
+#endif
+#ifndef LBMP_XCD_REMAP
+#define LBMP_XCD_REMAP 1
+#endif
+constexpr int kWavesPerBlock = LBMP_WAVES_PER_BLOCK;  // wavefronts (strips) per workgroup
+constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kDiagFields = 10;       // doubles per wave partial in the diagnostics pass
 
 enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2 };
@@ -32,7 +42,8 @@ enum : int { kFlagUnstable = 1, kFlagBadInput = 2 };
 struct StepConst {
     int nx, ny, pitch;          // pitch in elements
     int tiles_x, tiles_y, strip_rows;
-    long long plane;            // ny * pitch: elements per velocity plane
+    int band;                   // strips per tile band: consecutive tiles walk down `band` strips, then right
+    long long row_stride;       // 9 * pitch: elements per lattice row (all nine populations)
     float b4;                   // b / 4
     float RT;                   // R T
     float a;                    // attraction constant of Eq. (30)
@@ -48,44 +59,84 @@ struct StepConst {
 struct DiagConst {
     double in_cx, in_cy, in_r0, in_r1;
     double out_cx, out_cy, out_r0, out_r1;
+    double b4, RT, a;  // FP64 copies for the pressure of Eq. (30)
     int periodic_y;
 };
 
 // ---------------------------------------------------------------- storage codecs
+// Element access by 32-bit byte offset from a (wave-uniform) row pointer: the
+// compiler can then address with a scalar base and a 32-bit vector offset.
+// Valid because a padded row is limited to < 4 GiB (host validation).
+template <class T>
+__device__ __forceinline__ T& at(T* p, unsigned byte_off)
+{
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ const T& at(const T* p, unsigned byte_off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
+}
+
+#ifndef LBMP_NT_LOAD
+#define LBMP_NT_LOAD 0
+#endif
+#ifndef LBMP_NT_STORE
+#define LBMP_NT_STORE 0
+#endif
+template <class T>
+__device__ __forceinline__ T ld(const T* p, unsigned byte_off)
+{
+#if LBMP_NT_LOAD
+    return __builtin_nontemporal_load(&at(p, byte_off));
+#else
+    return at(p, byte_off);
+#endif
+}
+template <class T>
+__device__ __forceinline__ void st(T* p, unsigned byte_off, T v)
+{
+#if LBMP_NT_STORE
+    __builtin_nontemporal_store(v, &at(p, byte_off));
+#else
+    at(p, byte_off) = v;
+#endif
+}
+
 template <int S> struct Codec;
 
 template <> struct Codec<kStoreF32> {
     using T = float;
-    static __device__ __forceinline__ float load(const T* __restrict__ p, long long i, float) { return p[i]; }
-    static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float) { p[i] = v; }
-    static __device__ __forceinline__ void store_init(T* __restrict__ p, long long i, double v, double) {
-        p[i] = static_cast<float>(v);
+    static __device__ __forceinline__ float load(const T* __restrict__ p, unsigned b, float) { return ld(p, b); }
+    static __device__ __forceinline__ void store(T* __restrict__ p, unsigned b, float v, float) { st(p, b, v); }
+    static __device__ __forceinline__ void store_init(T* __restrict__ p, unsigned b, double v, double) {
+        at(p, b) = static_cast<float>(v);
     }
 };
 
 template <> struct Codec<kStoreF16> {
     using T = _Float16;
-    static __device__ __forceinline__ float load(const T* __restrict__ p, long long i, float o) {
-        return static_cast<float>(p[i]) + o;
+    static __device__ __forceinline__ float load(const T* __restrict__ p, unsigned b, float o) {
+        return static_cast<float>(ld(p, b)) + o;
     }
-    static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float o) {
-        p[i] = static_cast<_Float16>(v - o);  // round to nearest even
+    static __device__ __forceinline__ void store(T* __restrict__ p, unsigned b, float v, float o) {
+        st(p, b, static_cast<_Float16>(v - o));  // round to nearest even
     }
-    static __device__ __forceinline__ void store_init(T* __restrict__ p, long long i, double v, double o) {
-        p[i] = static_cast<_Float16>(static_cast<float>(v - o));
+    static __device__ __forceinline__ void store_init(T* __restrict__ p, unsigned b, double v, double o) {
+        at(p, b) = static_cast<_Float16>(static_cast<float>(v - o));
     }
 };
 
 template <> struct Codec<kStoreBF16> {
     using T = __bf16;
-    static __device__ __forceinline__ float load(const T* __restrict__ p, long long i, float o) {
-        return static_cast<float>(p[i]) + o;
+    static __device__ __forceinline__ float load(const T* __restrict__ p, unsigned b, float o) {
+        return static_cast<float>(ld(p, b)) + o;
     }
-    static __device__ __forceinline__ void store(T* __restrict__ p, long long i, float v, float o) {
-        p[i] = static_cast<__bf16>(v - o);    // round to nearest even
+    static __device__ __forceinline__ void store(T* __restrict__ p, unsigned b, float v, float o) {
+        st(p, b, static_cast<__bf16>(v - o));    // round to nearest even
     }
-    static __device__ __forceinline__ void store_init(T* __restrict__ p, long long i, double v, double o) {
-        p[i] = static_cast<__bf16>(static_cast<float>(v - o));
+    static __device__ __forceinline__ void store_init(T* __restrict__ p, unsigned b, double v, double o) {
+        at(p, b) = static_cast<__bf16>(static_cast<float>(v - o));
     }
 };
 
@@ -96,14 +147,17 @@ template <> struct Codec<kStoreBF16> {
 // Pull: f_a(x, y, t) = f*_a(x - e_a, t - 1).  At a wall (halfway bounce-back)
 // the population that would come from outside is the reversed one that left
 // the same site: f_a(x, t) = f*_abar(x, t - 1).
+// Row addresses are wave-uniform (scalar registers); each lane adds only its
+// 32-bit column offset, so every access is a scalar base plus a vector offset.
+// xm, xc, xp are byte offsets of columns x-1, x, x+1 within a row.
 template <int S, bool WALLS>
 __device__ __forceinline__ void pull_row(const typename Codec<S>::T* __restrict__ fin,
-                                         const StepConst& k, int y, int xm, int xc, int xp,
-                                         float f[9])
+                                         const StepConst& k, int y, unsigned xm, unsigned xc,
+                                         unsigned xp, float f[9])
 {
     using C = Codec<S>;
-    const long long P = k.plane;
-    const long long r0 = (long long)y * k.pitch;
+    using T = typename C::T;
+    const long long P = k.pitch;  // distance between the populations of one row
     int ya = y - 1, yb = y + 1;
     bool bot = false, top = false;
     if (WALLS) {
@@ -114,23 +168,22 @@ __device__ __forceinline__ void pull_row(const typename Codec<S>::T* __restrict_
         if (yb >= k.ny) yb -= k.ny;
     }
     // At a wall the three populations of a row group come from the reversed
-    // planes of the same site: select plane, row and column (wave-uniform planes
-    // and rows; the offsets w_a rho_ref of opposite directions are equal).
-    const long long ra = (long long)(bot ? y : ya) * k.pitch;
-    const long long rb = (long long)(top ? y : yb) * k.pitch;
-    const long long p2 = (bot ? 4 : 2) * P, p5 = (bot ? 7 : 5) * P, p6 = (bot ? 8 : 6) * P;
-    const long long p4 = (top ? 2 : 4) * P, p7 = (top ? 5 : 7) * P, p8 = (top ? 6 : 8) * P;
-    const int x5 = bot ? xc : xm, x6 = bot ? xc : xp;
-    const int x7 = top ? xc : xp, x8 = top ? xc : xm;
-    f[0] = C::load(fin, 0 * P + r0 + xc, k.off[0]);
-    f[1] = C::load(fin, 1 * P + r0 + xm, k.off[1]);
-    f[3] = C::load(fin, 3 * P + r0 + xp, k.off[3]);
-    f[2] = C::load(fin, p2 + ra + xc, k.off[2]);
-    f[5] = C::load(fin, p5 + ra + x5, k.off[5]);
-    f[6] = C::load(fin, p6 + ra + x6, k.off[6]);
-    f[4] = C::load(fin, p4 + rb + xc, k.off[4]);
-    f[7] = C::load(fin, p7 + rb + x7, k.off[7]);
-    f[8] = C::load(fin, p8 + rb + x8, k.off[8]);
+    // populations of the same site: select population, row and column (wave-uniform
+    // choices; the offsets w_a rho_ref of opposite directions are equal).
+    const T* r0 = fin + (long long)y * k.row_stride;
+    const T* ra = fin + (long long)(bot ? y : ya) * k.row_stride;
+    const T* rb = fin + (long long)(top ? y : yb) * k.row_stride;
+    const unsigned x5 = bot ? xc : xm, x6 = bot ? xc : xp;
+    const unsigned x7 = top ? xc : xp, x8 = top ? xc : xm;
+    f[0] = C::load(r0, xc, k.off[0]);
+    f[1] = C::load(r0 + 1 * P, xm, k.off[1]);
+    f[3] = C::load(r0 + 3 * P, xp, k.off[3]);
+    f[2] = C::load(ra + (bot ? 4 : 2) * P, xc, k.off[2]);
+    f[5] = C::load(ra + (bot ? 7 : 5) * P, x5, k.off[5]);
+    f[6] = C::load(ra + (bot ? 8 : 6) * P, x6, k.off[6]);
+    f[4] = C::load(rb + (top ? 2 : 4) * P, xc, k.off[4]);
+    f[7] = C::load(rb + (top ? 5 : 7) * P, x7, k.off[7]);
+    f[8] = C::load(rb + (top ? 6 : 8) * P, x8, k.off[8]);
 }
 
 __device__ __forceinline__ float density(const float f[9])
@@ -139,13 +192,55 @@ __device__ __forceinline__ float density(const float f[9])
     return f[0] + ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
 }
 
+// Eq. (30) in FP64 for the diagnostics reductions (the liquid pressure is a
+// small difference of two large terms).
+__device__ __forceinline__ double p_eos_f64(double rho, double b4, double RT, double a)
+{
+    const double eta = b4 * rho;
+    const double om = 1.0 - eta;
+    const double num = 1.0 + eta * (1.0 + eta * (1.0 - eta));
+    return rho * (RT * num / (om * om * om) - a * rho);
+}
+
+#ifndef LBMP_APPROX_DIV
+#define LBMP_APPROX_DIV 0
+#endif
+#ifndef LBMP_NEWTON_DIV
+#define LBMP_NEWTON_DIV 0
+#endif
+__device__ __forceinline__ float recip(float x)
+{
+#if LBMP_APPROX_DIV
+    return __builtin_amdgcn_rcpf(x);
+#elif LBMP_NEWTON_DIV
+    // hardware reciprocal refined by one Newton step
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+#else
+    return 1.0f / x;
+#endif
+}
+__device__ __forceinline__ float root(float x)
+{
+#if LBMP_APPROX_DIV
+    return __builtin_amdgcn_sqrtf(x);
+#elif LBMP_NEWTON_DIV
+    // x * rsq(x) refined by one Newton step on the square root
+    const float y = __builtin_amdgcn_rsqf(x);
+    const float s = x * y;
+    return fmaf(fmaf(-s, s, x), 0.5f * y, s);
+#else
+    return sqrtf(x);
+#endif
+}
+
 // Eq. (30) Carnahan-Starling pressure.
 __device__ __forceinline__ float p_eos(float rho, const StepConst& k)
 {
     const float eta = k.b4 * rho;
     const float om = 1.0f - eta;
     const float num = fmaf(eta, fmaf(eta, 1.0f - eta, 1.0f), 1.0f);  // 1 + eta + eta^2 - eta^3
-    const float inv = 1.0f / (om * om * om);  // correctly rounded (see pseudopotential)
+    const float inv = recip(om * om * om);
     return rho * fmaf(k.RT * num, inv, -k.a * rho);
 }
 
@@ -161,7 +256,7 @@ __device__ __forceinline__ float pseudopotential(float rho, const StepConst& k, 
     const float psi2 = k.two_over_G * (p_eos(rho, k) - rho * (1.0f / 3.0f));
     const bool ok = (psi2 > 0.0f) && (k.b4 * rho < 1.0f);
     bad |= !ok;
-    return ok ? sqrtf(psi2) : 0.0f;
+    return ok ? root(psi2) : 0.0f;
 }
 
 // Eq. (7) with w(1) = 1/3, w(2) = 1/12, written out per neighbour:
@@ -232,6 +327,23 @@ __device__ __forceinline__ void collide(float f[9], float rho, float vx, float v
     f[6] += c_dg - xp + yp - pxy;
     f[7] += c_dg - xp - yp + pxy;
     f[8] += c_dg + xp - yp - pxy;
+}
+
+// Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
+// b mod 8).  Renumber them so that each XCD receives one contiguous run of
+// tiles: neighbouring strips (which share halo rows, halo columns and partly
+// written cache lines at tile edges) then mostly meet in the same L2.  The map
+// is a permutation of block ids, so results do not depend on it.
+__device__ __forceinline__ int logical_block(int b, int nb)
+{
+#if LBMP_XCD_REMAP
+    const int per = nb / kNumXcd, rem = nb % kNumXcd;
+    const int xcd = b % kNumXcd, idx = b / kNumXcd;
+    return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
+#else
+    (void)nb;
+    return b;
+#endif
 }
 
 __device__ __forceinline__ float lane_from_left(float v) { return __shfl_up(v, 1, kWave); }

@@ -27,24 +27,36 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
 {
     using C = Codec<S>;
     const int lane = threadIdx.x & (kWave - 1);
-    const int tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    // the wave index is uniform across the wave: keep it (and every row address
+    // derived from it) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = logical_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
     if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
-    const int tx = tile % k.tiles_x;
-    const int ty = tile / k.tiles_x;
+    // Tiles are numbered in bands of `band` strips: within a band, consecutive
+    // tiles go down the strips first, so the wavefronts of one workgroup cover a
+    // small rectangle and share halo rows and columns in the CU's L1.
+    const int band0 = (tile / (k.tiles_x * k.band)) * k.band;
+    const int band_h = min(k.band, k.tiles_y - band0);
+    const int r = tile - band0 * k.tiles_x;
+    const int tx = r / band_h;
+    const int ty = band0 + r % band_h;
 
     // Column of this lane; lanes 0 and 63 are the psi halo.  Columns wrap in x.
     const int xs = tx * kTileW - 1 + lane;
     const bool live = (lane >= 1) && (lane <= kTileW) && (xs < k.nx);
-    int xc = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
-    if (xs > k.nx) xc = 0;  // beyond the right halo: in-range dummy column, never stored
-    const int xm = (xc == 0) ? k.nx - 1 : xc - 1;
-    const int xp = (xc == k.nx - 1) ? 0 : xc + 1;
+    int xci = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
+    if (xs > k.nx) xci = 0;  // beyond the right halo: in-range dummy column, never stored
+    // byte offsets of columns x, x-1, x+1 within a row
+    const unsigned eb = sizeof(typename C::T);
+    const unsigned xc = (unsigned)xci * eb;
+    const unsigned xm = (unsigned)((xci == 0) ? k.nx - 1 : xci - 1) * eb;
+    const unsigned xp = (unsigned)((xci == k.nx - 1) ? 0 : xci + 1) * eb;
 
     const int y0 = ty * k.strip_rows;
     const int y1 = min(y0 + k.strip_rows, k.ny);
 
     bool bad = false;
-    float f[9], fn[9];
+    float f[9], fn[9], fq[9];
 
     // psi of the row above the strip (y0 - 1), or its mirror at a wall
     float pm = 0.0f;
@@ -55,6 +67,9 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
         pm = pseudopotential(density(fn), k, bad);
     }
     pull_row<S, WALLS>(fin, k, y0, xm, xc, xp, f);
+    // row y0 + 1 is requested before row y0 is consumed (two rows in flight)
+    const bool has1 = !WALLS || y0 + 1 < k.ny;
+    if (has1) pull_row<S, WALLS>(fin, k, (y0 + 1 < k.ny) ? y0 + 1 : y0 + 1 - k.ny, xm, xc, xp, fn);
     float rc = density(f);
     float pc = pseudopotential(rc, k, bad);
     if (WALLS && y0 == 0) pm = pc;
@@ -67,11 +82,17 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
     }
 
     for (int y = y0; y < y1; ++y) {
-        int yn = y + 1;
+        // rows in flight: fn = row y + 1 (issued one iteration ago), fq = row y + 2
+        // (issued now, needed only by the next iteration's psi halo)
+        const bool has_n = !WALLS || y + 1 < k.ny;
+        const bool has_q = (y + 2 <= y1) && (!WALLS || y + 2 < k.ny);
+        if (has_q) {
+            int yq = y + 2;
+            if (yq >= k.ny) yq -= k.ny;
+            pull_row<S, WALLS>(fin, k, yq, xm, xc, xp, fq);
+        }
         float pp, rn = 0.0f;
-        if (!WALLS || yn < k.ny) {
-            if (yn >= k.ny) yn -= k.ny;
-            pull_row<S, WALLS>(fin, k, yn, xm, xc, xp, fn);
+        if (has_n) {
             rn = density(fn);
             pp = pseudopotential(rn, k, bad);
         } else {
@@ -83,20 +104,20 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
         force_stencil(pmL, pm, pmR, pcL, pc, pcR, ppL, pp, ppR, k, Fx, Fy, Fs2);
         const float jx = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));
         const float jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
-        const float inv_rho = 1.0f / rc;
+        const float inv_rho = recip(rc);
         const float vx = fmaf(0.5f, Fx, jx) * inv_rho;
         const float vy = fmaf(0.5f, Fy, jy) * inv_rho;
 
         if (MODE == kModeStep) {
             collide(f, rc, vx, vy, Fx, Fy, Fs2, k);
             if (live) {
-                const long long o = (long long)y * k.pitch + xc;
+                typename C::T* row = fout + (long long)y * k.row_stride;
 #pragma unroll
-                for (int a = 0; a < 9; ++a) C::store(fout, a * k.plane + o, f[a], k.off[a]);
+                for (int a = 0; a < 9; ++a) C::store(row + a * k.pitch, xc, f[a], k.off[a]);
             }
         } else if (MODE == kModeMoments) {
             if (live) {
-                const long long o = (long long)y * k.nx + xc;
+                const long long o = (long long)y * k.nx + xci;
                 if (rho_out) rho_out[o] = rc;
                 if (ux_out) ux_out[o] = vx;
                 if (uy_out) uy_out[o] = vy;
@@ -104,17 +125,17 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
         } else {
             if (live) {
                 const double r = rc;
-                const double p = p_eos(rc, k);
+                const double p = p_eos_f64(r, dg.b4, dg.RT, dg.a);
                 acc[0] += r;
                 acc[1] += r * (double)vx;
                 acc[2] += r * (double)vy;
-                double dx = fabs((double)xc - dg.in_cx);
+                double dx = fabs((double)xci - dg.in_cx);
                 dx = fmin(dx, (double)k.nx - dx);
                 double dy = fabs((double)y - dg.in_cy);
                 if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
                 double d = sqrt(dx * dx + dy * dy);
                 if (d >= dg.in_r0 && d < dg.in_r1) { acc[3] += p; acc[5] += r; acc[7] += 1.0; }
-                dx = fabs((double)xc - dg.out_cx);
+                dx = fabs((double)xci - dg.out_cx);
                 dx = fmin(dx, (double)k.nx - dx);
                 dy = fabs((double)y - dg.out_cy);
                 if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
@@ -129,7 +150,10 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
         pcL = ppL; pc = pp; pcR = ppR;
         rc = rn;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) f[a] = fn[a];
+        for (int a = 0; a < 9; ++a) {
+            f[a] = fn[a];
+            fn[a] = fq[a];
+        }
     }
 
     if (MODE == kModeDiag) {
@@ -211,26 +235,17 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
         const double ux = ux0 ? ux0[i] : 0.0, uy = uy0 ? uy0[i] : 0.0;
         const double eu = EX[a] * ux + EY[a] * uy;
         const double feq = W[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
-        C::store_init(fout, b * k.plane + (long long)y * k.pitch + x, feq, W[b] * rho_ref);
+        C::store_init(fout + (long long)y * k.row_stride + b * k.pitch, (unsigned)x * (unsigned)sizeof(typename C::T),
+                      feq, W[b] * rho_ref);
     }
 }
 
-// Each thread moves 4 x 16 B with all loads issued before the stores.
+// One 16-byte element per thread: the fastest plain copy form on gfx950.
 __global__ __launch_bounds__(256) void copy_probe(const float4* __restrict__ src,
                                                   float4* __restrict__ dst, long long n)
 {
-    const long long base = (long long)blockIdx.x * (256 * 4) + threadIdx.x;
-    float4 v[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const long long j = base + i * 256;
-        if (j < n) v[i] = src[j];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const long long j = base + i * 256;
-        if (j < n) dst[j] = v[i];
-    }
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -271,6 +286,23 @@ static hipError_t dispatch(int store, bool walls, const void* fin, void* fout, c
     default:
         return hipErrorInvalidValue;
     }
+}
+
+int step_blocks_per_cu(int store, bool walls)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define LBMP_OCC(S_, W_)                                                                              \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, d2q9_strip<S_, W_, kModeStep>,              \
+                                                     kWave * kWavesPerBlock, 0)
+    switch (store) {
+    case kStoreF32: if (walls) LBMP_OCC(kStoreF32, true); else LBMP_OCC(kStoreF32, false); break;
+    case kStoreF16: if (walls) LBMP_OCC(kStoreF16, true); else LBMP_OCC(kStoreF16, false); break;
+    case kStoreBF16: if (walls) LBMP_OCC(kStoreBF16, true); else LBMP_OCC(kStoreBF16, false); break;
+    default: break;
+    }
+#undef LBMP_OCC
+    return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
@@ -318,7 +350,7 @@ hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux
 
 hipError_t launch_copy_probe(const void* src, void* dst, long long n16, hipStream_t s)
 {
-    const long long blocks = (n16 + 1023) / 1024;
+    const long long blocks = (n16 + 255) / 256;
     if (blocks < 1 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(copy_probe, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float4*>(src), static_cast<float4*>(dst), n16);

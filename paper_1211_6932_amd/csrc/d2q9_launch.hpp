@@ -12,6 +12,9 @@ namespace lbmp {
 hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
                        int* flag, hipStream_t s);
 
+// Resident step workgroups per compute unit (0 if the query fails).
+int step_blocks_per_cu(int store, bool walls);
+
 // rho and v of the state in `fin` into unpadded [ny][nx] FP32 buffers (NULL allowed).
 hipError_t launch_moments(int store, bool walls, const void* fin, const StepConst& k, int* flag,
                           float* rho, float* ux, float* uy, hipStream_t s);

@@ -6,6 +6,7 @@
 // runs in the kernels of d2q9_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -32,7 +33,8 @@ lb_status hip_fail(hipError_t e, const char* what)
 
 constexpr size_t kAlign = 256;
 constexpr int kDiagStripRows = 32;
-constexpr int kDefaultStripRows = 8;
+constexpr int kMinStripRows = 3;
+constexpr int kDefaultBand = 1;
 constexpr int kDefaultGraphChunk = 32;
 constexpr int kMaxSide = 1 << 20;
 
@@ -80,6 +82,8 @@ lb_status validate(const lb_params* p)
     if (p->nx < 3 || p->ny < 3 || p->nx > kMaxSide || p->ny > kMaxSide)
         return fail(LB_EINVAL, "nx and ny must lie in [3, 2^20]");
     if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LB_EINVAL, "nx * ny exceeds 2^31 sites");
+    if ((long long)pitch_of(p->nx) * (p->store == LB_STORE_F32 ? 4 : 2) >= (1LL << 32))
+        return fail(LB_EINVAL, "a padded row must stay below 4 GiB");
     if (p->bc != LB_BC_PERIODIC && p->bc != LB_BC_WALLS_Y) return fail(LB_EINVAL, "unknown bc");
     if (p->store < LB_STORE_F32 || p->store > LB_STORE_BF16_OFFSET) return fail(LB_EINVAL, "unknown store");
     if (!finite_all({p->a, p->b, p->R, p->T, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta, p->s_j,
@@ -98,16 +102,17 @@ lb_status validate(const lb_params* p)
     return LB_OK;
 }
 
-lbmp::StepConst derive(const lb_params& p, int strip_rows)
+lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
 {
     lbmp::StepConst k{};
     k.nx = p.nx;
     k.ny = p.ny;
     k.pitch = pitch_of(p.nx);
     k.strip_rows = strip_rows;
+    k.band = band;
     k.tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
     k.tiles_y = (p.ny + strip_rows - 1) / strip_rows;
-    k.plane = (long long)p.ny * k.pitch;
+    k.row_stride = 9LL * k.pitch;
     k.b4 = (float)(p.b / 4.0);
     k.RT = (float)(p.R * p.T);
     k.a = (float)p.a;
@@ -126,6 +131,27 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows)
                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     for (int a = 0; a < 9; ++a) k.off[a] = p.store == LB_STORE_F32 ? 0.0f : (float)(w[a] * p.rho_ref);
     return k;
+}
+
+// Strip height for the step kernel.  Short strips are fastest on large grids
+// even though they re-read two halo rows per strip: the tiles are numbered
+// row-band by row-band, so the resident wavefronts work on a narrow band of
+// rows at any moment (good DRAM-page and last-level-cache locality, halo rows
+// shared by neighbouring strips while they are still cached).  Grids too small
+// to give every resident wavefront a strip of kMinStripRows rows use shorter
+// strips, down to 2 rows.
+int auto_strip_rows(const lb_params& p)
+{
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        return kMinStripRows;
+    const int nb = std::max(1, lbmp::step_blocks_per_cu(p.store, p.bc == LB_BC_WALLS_Y));
+    const long long resident = (long long)nb * lbmp::kWavesPerBlock * ncu;
+    const long long tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
+    const long long strips_wanted = (resident + tiles_x - 1) / tiles_x;
+    const long long h = std::max<long long>(2, p.ny / strips_wanted);
+    return (int)std::min<long long>(h, kMinStripRows);
 }
 
 }  // namespace
@@ -251,7 +277,7 @@ lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t work
     if (!c) return fail(LB_ENOMEM, "host allocation failed");
     c->p = *p;
     c->L = L;
-    c->k = derive(*p, kDefaultStripRows);
+    c->k = derive(*p, auto_strip_rows(*p), kDefaultBand);
     c->kd = derive(*p, kDiagStripRows);
     c->ws = static_cast<char*>(workspace);
     c->flag = reinterpret_cast<int*>(c->ws + L.flag_off);
@@ -329,6 +355,7 @@ lb_status lb_diagnostics(lb_ctx* c, const lb_region* in, const lb_region* outr, 
     if (c->poisoned) return fail(LB_ESTATE, "context poisoned by an earlier failure");
     lbmp::DiagConst dg{in->cx, in->cy, in->r_min, in->r_max,
                        outr->cx, outr->cy, outr->r_min, outr->r_max,
+                       c->p.b / 4.0, c->p.R * c->p.T, c->p.a,
                        c->p.bc == LB_BC_PERIODIC ? 1 : 0};
     hipError_t e = lbmp::launch_diag(c->p.store, c->p.bc == LB_BC_WALLS_Y, c->f[c->cur], c->kd,
                                      c->flag, dg, c->partial, c->dout, c->stream);
@@ -379,14 +406,18 @@ lb_status lb_check(lb_ctx* c)
 
 int64_t lb_time(const lb_ctx* c) { return c ? c->t : -1; }
 
+// The exported state is [9][ny][nx]; the stored one is [ny][9][pitch].
 lb_status lb_get_state(lb_ctx* c, void* dst)
 {
     if (!c || !dst) return fail(LB_EINVAL, "NULL argument");
     const size_t eb = elem_bytes(c->p.store);
-    hipError_t e = hipMemcpy2DAsync(dst, (size_t)c->p.nx * eb, c->f[c->cur], (size_t)c->k.pitch * eb,
-                                    (size_t)c->p.nx * eb, (size_t)9 * c->p.ny, hipMemcpyDeviceToDevice,
-                                    c->stream);
-    if (e != hipSuccess) return hip_fail(e, "lb_get_state copy");
+    const size_t nx = c->p.nx, ny = c->p.ny, pitch = c->k.pitch;
+    for (int a = 0; a < 9; ++a) {
+        hipError_t e = hipMemcpy2DAsync(static_cast<char*>(dst) + a * ny * nx * eb, nx * eb,
+                                        static_cast<const char*>(c->f[c->cur]) + a * pitch * eb, 9 * pitch * eb,
+                                        nx * eb, ny, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "lb_get_state copy");
+    }
     return LB_OK;
 }
 
@@ -395,23 +426,31 @@ lb_status lb_set_state(lb_ctx* c, const void* src, int64_t t)
     if (!c || !src) return fail(LB_EINVAL, "NULL argument");
     if (t < 0) return fail(LB_EINVAL, "t must be >= 0");
     const size_t eb = elem_bytes(c->p.store);
-    hipError_t e = hipMemcpy2DAsync(c->f[0], (size_t)c->k.pitch * eb, src, (size_t)c->p.nx * eb,
-                                    (size_t)c->p.nx * eb, (size_t)9 * c->p.ny, hipMemcpyDeviceToDevice,
-                                    c->stream);
-    if (e != hipSuccess) return hip_fail(e, "lb_set_state copy");
+    const size_t nx = c->p.nx, ny = c->p.ny, pitch = c->k.pitch;
+    for (int a = 0; a < 9; ++a) {
+        hipError_t e = hipMemcpy2DAsync(static_cast<char*>(c->f[0]) + a * pitch * eb, 9 * pitch * eb,
+                                        static_cast<const char*>(src) + a * ny * nx * eb, nx * eb,
+                                        nx * eb, ny, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "lb_set_state copy");
+    }
     c->cur = 0;
     c->t = t;
     return LB_OK;
 }
 
-lb_status lb_set_launch(lb_ctx* c, int32_t strip_rows, int32_t graph_chunk)
+lb_status lb_set_launch(lb_ctx* c, int32_t strip_rows, int32_t band, int32_t graph_chunk)
 {
     if (!c) return fail(LB_EINVAL, "ctx is NULL");
-    if (strip_rows < 0 || graph_chunk < 0) return fail(LB_EINVAL, "negative launch parameter");
+    if (strip_rows < -1 || band < -1 || graph_chunk < 0) return fail(LB_EINVAL, "invalid launch parameter");
     if (graph_chunk != 0 && (graph_chunk < 2 || graph_chunk % 2))
         return fail(LB_EINVAL, "graph_chunk must be even and >= 2");
     drop_graphs(c);
-    if (strip_rows > 0) c->k = derive(c->p, strip_rows);
+    int rows = c->k.strip_rows, bd = c->k.band;
+    if (strip_rows > 0) rows = strip_rows;
+    if (strip_rows == -1) rows = auto_strip_rows(c->p);
+    if (band > 0) bd = band;
+    if (band == -1) bd = kDefaultBand;
+    c->k = derive(c->p, rows, bd);
     if (graph_chunk > 0) c->graph_chunk = graph_chunk;
     return LB_OK;
 }

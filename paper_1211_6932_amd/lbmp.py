@@ -96,7 +96,7 @@ def load():
     L.lb_get_state.restype = ctypes.c_int
     L.lb_set_state.argtypes = [vp, vp, ctypes.c_int64]
     L.lb_set_state.restype = ctypes.c_int
-    L.lb_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.lb_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.lb_set_launch.restype = ctypes.c_int
     L.lb_destroy.argtypes = [vp]
     L.lb_destroy.restype = ctypes.c_int
@@ -188,8 +188,8 @@ def lb_set_state(ctx, src_ptr: int, t: int):
     return _check(load().lb_set_state(ctx, ctypes.c_void_p(src_ptr), int(t)), "lb_set_state")
 
 
-def lb_set_launch(ctx, strip_rows: int = 0, graph_chunk: int = 0):
-    return _check(load().lb_set_launch(ctx, int(strip_rows), int(graph_chunk)), "lb_set_launch")
+def lb_set_launch(ctx, strip_rows: int = 0, band: int = 0, graph_chunk: int = 0):
+    return _check(load().lb_set_launch(ctx, int(strip_rows), int(band), int(graph_chunk)), "lb_set_launch")
 
 
 def lb_destroy(ctx):
@@ -242,14 +242,19 @@ class Sim:
                                ux.data_ptr() if ux is not None else 0,
                                uy.data_ptr() if uy is not None else 0, self.stream.cuda_stream)
 
-    def __del__(self):
+    def close(self):
+        """Synchronise the stream and release the library context."""
         ctx = getattr(self, "ctx", None)
         if ctx is not None:
-            try:
-                self.stream.synchronize()
-            finally:
-                lb_destroy(ctx)
             self.ctx = None
+            self.stream.synchronize()
+            lb_destroy(ctx)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may already be gone
+            pass
 
     @property
     def t(self):
@@ -259,8 +264,8 @@ class Sim:
         lb_step(self.ctx, n)
         return self
 
-    def set_launch(self, strip_rows=0, graph_chunk=0):
-        lb_set_launch(self.ctx, strip_rows, graph_chunk)
+    def set_launch(self, strip_rows=0, band=0, graph_chunk=0):
+        lb_set_launch(self.ctx, strip_rows, band, graph_chunk)
 
     def moments(self):
         """(rho, ux, uy) FP32 device tensors [ny][nx] at the current time."""
