@@ -15,7 +15,6 @@ force, MRT collision with the improved forcing, store).  The metric is MLUPS
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -28,24 +27,18 @@ if ROOT not in sys.path:
 
 BYTES_PER_SITE = {"f32": 72, "f16": 36, "bf16": 36}
 PEAK_HBM_GBPS = 8000.0
-KERNEL_SOURCES = ["paper_1211_6932_amd/csrc/d2q9_core.hpp", "paper_1211_6932_amd/csrc/d2q9_kernels.hip"]
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(store, nsites):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source (else None)."""
+    """HBM bytes per step launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if it was taken on the current
+    kernel source and workload size (else None)."""
+    from paper_1211_6932_amd.prof import kernel_hash
+
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -158,6 +151,8 @@ def main():
     mlups = sites * args.steps / wall / 1e6
     bps = BYTES_PER_SITE[args.store]
     achieved = bps * sites / (kern_ms * 1e-3) / 1e9
+    tbytes = measured_traffic(args.store, sites)
+    traffic = None if tbytes is None else tbytes / (kern_ms * 1e-3) / 1e9
     log(f"{mlups:.0f} MLUPS, step {kern_ms:.4f} ms, {achieved:.0f} GB/s algorithmic, stable={stable}")
 
     copy_gbps = None
@@ -193,7 +188,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": measured_traffic(args.store, sites),
+            "frac": round(achieved / PEAK_HBM_GBPS, 4),
+            "traffic": None if traffic is None else round(traffic, 1),
+            "traffic_bytes_per_launch": tbytes, "algorithmic_bytes_per_launch": bps * sites,
             "bytes_per_site": bps, "kernel_ms": round(kern_ms, 5),
             "copy_probe_GBps": None if copy_gbps is None else round(copy_gbps, 1),
         },
