@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-BYTES_PER_SITE = {"f32": 72, "f16": 36, "bf16": 36}
+BYTES_PER_SITE = {"f32": 72, "f16": 36, "bf16": 36, "f16local": 44, "bf16local": 44}
 PEAK_HBM_GBPS = 8000.0
 
 
@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--store", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--store", default="f32", choices=sorted(BYTES_PER_SITE))
     ap.add_argument("--scale", type=int, default=4, help="splash geometry scale (4 -> 8192x4096)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -120,7 +120,7 @@ def main():
     lbmp.load()
     w = W.splash(scale=args.scale, Re=200)
     nx, ny = w.params["nx"], w.params["ny"]
-    rho_ref = w.info["rho_l"] if args.store != "f32" else 0.0
+    rho_ref = w.info["rho_l"] if args.store in ("f16", "bf16") else 0.0
     log(f"workload {w.name} store={args.store}: init")
     sim = lbmp.Sim(w.params, torch.from_numpy(np.asarray(w.rho0, np.float32)),
                    torch.from_numpy(np.asarray(w.ux0, np.float32)),
@@ -179,7 +179,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.store == "f32" else f"{args.store}-offset storage, f32 compute",
+        "dtype": "f32" if args.store == "f32" else f"{args.store} storage, f32 compute",
         "data": "synthetic",
         "config": {
             "workload": f"droplet splash on a thin film, {nx}x{ny}, walls in y, x periodic, "

@@ -55,10 +55,16 @@ typedef enum {
 } lb_bc;
 
 typedef enum {
-    LB_STORE_F32 = 0,          /* distributions stored as FP32 (72 B/site/step moved)     */
-    LB_STORE_F16_OFFSET = 1,   /* stored as FP16 of f_a - w_a rho_ref (36 B/site/step)    */
-    LB_STORE_BF16_OFFSET = 2   /* stored as BF16 of f_a - w_a rho_ref (36 B/site/step)    */
+    LB_STORE_F32 = 0,          /* distributions stored as FP32 (72 B/site/step moved)       */
+    LB_STORE_F16_OFFSET = 1,   /* FP16 of f_a - w_a rho_ref, one reference density for the
+                                  whole lattice (36 B/site/step)                             */
+    LB_STORE_BF16_OFFSET = 2,  /* BF16 of f_a - w_a rho_ref (36 B/site/step)                  */
+    LB_STORE_F16_LOCAL = 3,    /* FP16 of f_a - w_a rho(x) with the site's own density
+                                  rho(x) stored in FP32 beside them (44 B/site/step)         */
+    LB_STORE_BF16_LOCAL = 4    /* BF16 of f_a - w_a rho(x), rho(x) in FP32 (44 B/site/step)   */
 } lb_store;
+/* w_a are the D2Q9 lattice weights 4/9 (rest), 1/9 (axis), 1/36 (diagonal).
+ * Collision and force are computed in FP32 for every storage type. */
 
 /* Run parameters.  Rates are the inverse relaxation times 1/tau of Eq. (2).
  * The shear rate is per site: s_nu = 1/(3 nu + 1/2) with nu = nu_l where
@@ -77,7 +83,7 @@ typedef struct {
     double s_rho, s_e, s_zeta, s_j, s_q;   /* rates in (0, 2)                            */
     double nu_l, nu_g;       /* kinematic viscosities, > 0                               */
     double rho_switch;       /* density at which nu switches from nu_g to nu_l           */
-    double rho_ref;          /* reference density of the 16-bit offsets (ignored for F32) */
+    double rho_ref;          /* reference density of LB_STORE_*_OFFSET (ignored otherwise) */
 } lb_params;
 
 /* An annulus r_min <= d < r_max around (cx, cy); d uses the minimum image in
@@ -109,8 +115,9 @@ lb_status lb_validate_params(const lb_params* p);
  * Pure host function. */
 size_t lb_workspace_bytes(const lb_params* p);
 
-/* Bytes of one stored state (9 * nx * ny elements of the storage type), the
- * size of the buffers lb_get_state / lb_set_state copy.  Pure host function. */
+/* Bytes of one stored state, the size of the buffers lb_get_state /
+ * lb_set_state copy: 9 * nx * ny elements of the storage type, plus nx * ny FP32
+ * densities for the local-density encodings.  Pure host function. */
 size_t lb_state_bytes(const lb_params* p);
 
 /* Create a context and set the state at t = 0 to f_a = [M^-1 m_eq(rho0, u0)]_a,
@@ -151,9 +158,10 @@ int64_t lb_time(const lb_ctx* ctx);
 
 /* Checkpoint: copy the stored state (the post-collision distributions of
  * step t-1, exported as [9][ny][nx] in the storage type, velocity ordering
- * rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1)) to / from
- * a device buffer of lb_state_bytes bytes (asynchronous).  lb_set_state also
- * sets the time to t. */
+ * rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1); for the
+ * local-density encodings followed by the [ny][nx] FP32 densities) to / from a
+ * device buffer of lb_state_bytes bytes (asynchronous).  lb_set_state also sets
+ * the time to t. */
 lb_status lb_get_state(lb_ctx* ctx, void* dst);
 lb_status lb_set_state(lb_ctx* ctx, const void* src, int64_t t);
 

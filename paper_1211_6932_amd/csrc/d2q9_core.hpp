@@ -34,7 +34,7 @@ constexpr int kWavesPerBlock = LBMP_WAVES_PER_BLOCK;  // wavefronts (strips) per
 constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kDiagFields = 10;       // doubles per wave partial in the diagnostics pass
 
-enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2 };
+enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2, kStoreF16Local = 3, kStoreBF16Local = 4 };
 enum : int { kModeStep = 0, kModeMoments = 1, kModeDiag = 2 };
 enum : int { kFlagUnstable = 1, kFlagBadInput = 2 };
 
@@ -43,7 +43,7 @@ struct StepConst {
     int nx, ny, pitch;          // pitch in elements
     int tiles_x, tiles_y, strip_rows;
     int band;                   // strips per tile band: consecutive tiles walk down `band` strips, then right
-    long long row_stride;       // 9 * pitch: elements per lattice row (all nine populations)
+    long long row_stride;       // elements of the storage type per lattice row (9 or 11 pitches)
     float b4;                   // b / 4
     float RT;                   // R T
     float a;                    // attraction constant of Eq. (30)
@@ -103,42 +103,87 @@ __device__ __forceinline__ void st(T* p, unsigned byte_off, T v)
 #endif
 }
 
+// Lattice weight of population a (4/9 rest, 1/9 axis, 1/36 diagonal).
+__device__ __forceinline__ float lattice_weight(int a)
+{
+    return a == 0 ? 4.0f / 9.0f : (a < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+}
+
+// Codecs address one lattice row: `row` points at its start, `a` is the stored
+// population read or written, `col` the byte offset of the column for
+// elements of type T.  The nine population rows of a lattice row are `pitch`
+// elements apart.  store() receives 1/rho of the site (used by the
+// local-density encodings only).
 template <int S> struct Codec;
 
 template <> struct Codec<kStoreF32> {
     using T = float;
-    static __device__ __forceinline__ float load(const T* __restrict__ p, unsigned b, float) { return ld(p, b); }
-    static __device__ __forceinline__ void store(T* __restrict__ p, unsigned b, float v, float) { st(p, b, v); }
-    static __device__ __forceinline__ void store_init(T* __restrict__ p, unsigned b, double v, double) {
-        at(p, b) = static_cast<float>(v);
+    static constexpr int kRowSlots = 9;  // T-sized row slots per lattice row
+    static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
+        return ld(row + a * k.pitch, col);
+    }
+    static __device__ __forceinline__ void store(T* row, const StepConst& k, int a, unsigned col, float v, float) {
+        st(row + a * k.pitch, col, v);
+    }
+    static __device__ __forceinline__ void store_density(T*, const StepConst&, unsigned, float) {}
+    static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v, double) {
+        at(row + a * k.pitch, col) = static_cast<float>(v);
     }
 };
 
-template <> struct Codec<kStoreF16> {
-    using T = _Float16;
-    static __device__ __forceinline__ float load(const T* __restrict__ p, unsigned b, float o) {
-        return static_cast<float>(ld(p, b)) + o;
+// 16-bit offsets from the rest equilibrium of one fixed reference density:
+// stored h_a = f_a - w_a rho_ref (k.off[a] = w_a rho_ref).
+template <class H> struct CodecGlobal {
+    using T = H;
+    static constexpr int kRowSlots = 9;
+    static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
+        return static_cast<float>(ld(row + a * k.pitch, col)) + k.off[a];
     }
-    static __device__ __forceinline__ void store(T* __restrict__ p, unsigned b, float v, float o) {
-        st(p, b, static_cast<_Float16>(v - o));  // round to nearest even
+    static __device__ __forceinline__ void store(T* row, const StepConst& k, int a, unsigned col, float v, float) {
+        st(row + a * k.pitch, col, static_cast<T>(v - k.off[a]));  // round to nearest even
     }
-    static __device__ __forceinline__ void store_init(T* __restrict__ p, unsigned b, double v, double o) {
-        at(p, b) = static_cast<_Float16>(static_cast<float>(v - o));
+    static __device__ __forceinline__ void store_density(T*, const StepConst&, unsigned, float) {}
+    static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v, double) {
+        at(row + a * k.pitch, col) = static_cast<T>(static_cast<float>(v - (double)k.off[a]));
     }
 };
 
-template <> struct Codec<kStoreBF16> {
-    using T = __bf16;
-    static __device__ __forceinline__ float load(const T* __restrict__ p, unsigned b, float o) {
-        return static_cast<float>(ld(p, b)) + o;
+// 16-bit relative offsets from the rest equilibrium of the site's own
+// density: each lattice row stores g_a = f*_a / rho - w_a (nine 16-bit rows)
+// followed by rho in FP32 (two 16-bit slots per column), so f*_a = rho (w_a + g_a).
+// A pulled value is decoded with the density of the site it was streamed from.
+// Relative offsets keep the vapour values (rho ~ 1e-4) in the normal range of
+// FP16, where an absolute offset would fall into its subnormals.
+template <class H> struct CodecLocal {
+    using T = H;
+    static constexpr int kRowSlots = 11;
+    static __device__ __forceinline__ const float* dens(const T* row, const StepConst& k) {
+        return reinterpret_cast<const float*>(row + 9 * k.pitch);
     }
-    static __device__ __forceinline__ void store(T* __restrict__ p, unsigned b, float v, float o) {
-        st(p, b, static_cast<__bf16>(v - o));    // round to nearest even
+    static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
+        const float rho = ld(dens(row, k), 2u * col);
+        return rho * (lattice_weight(a) + static_cast<float>(ld(row + a * k.pitch, col)));
     }
-    static __device__ __forceinline__ void store_init(T* __restrict__ p, unsigned b, double v, double o) {
-        at(p, b) = static_cast<__bf16>(static_cast<float>(v - o));
+    static __device__ __forceinline__ void store(T* row, const StepConst& k, int a, unsigned col, float v,
+                                                 float inv_rho) {
+        st(row + a * k.pitch, col, static_cast<T>(fmaf(v, inv_rho, -lattice_weight(a))));
+    }
+    static __device__ __forceinline__ void store_density(T* row, const StepConst& k, unsigned col, float rho) {
+        st(reinterpret_cast<float*>(row + 9 * k.pitch), 2u * col, rho);
+    }
+    static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v,
+                                                      double rho) {
+        const double w = a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        const float r = static_cast<float>(rho);
+        at(row + a * k.pitch, col) = static_cast<T>(static_cast<float>(v / (double)r - w));
+        if (a == 0) at(reinterpret_cast<float*>(row + 9 * k.pitch), 2u * col) = r;
     }
 };
+
+template <> struct Codec<kStoreF16> : CodecGlobal<_Float16> {};
+template <> struct Codec<kStoreBF16> : CodecGlobal<__bf16> {};
+template <> struct Codec<kStoreF16Local> : CodecLocal<_Float16> {};
+template <> struct Codec<kStoreBF16Local> : CodecLocal<__bf16> {};
 
 // ---------------------------------------------------------------- streaming (Eq. 5)
 // Velocity ordering: 0 rest; 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1);
@@ -157,7 +202,6 @@ __device__ __forceinline__ void pull_row(const typename Codec<S>::T* __restrict_
 {
     using C = Codec<S>;
     using T = typename C::T;
-    const long long P = k.pitch;  // distance between the populations of one row
     int ya = y - 1, yb = y + 1;
     bool bot = false, top = false;
     if (WALLS) {
@@ -169,21 +213,21 @@ __device__ __forceinline__ void pull_row(const typename Codec<S>::T* __restrict_
     }
     // At a wall the three populations of a row group come from the reversed
     // populations of the same site: select population, row and column (wave-uniform
-    // choices; the offsets w_a rho_ref of opposite directions are equal).
+    // choices; opposite directions have equal lattice weights and offsets).
     const T* r0 = fin + (long long)y * k.row_stride;
     const T* ra = fin + (long long)(bot ? y : ya) * k.row_stride;
     const T* rb = fin + (long long)(top ? y : yb) * k.row_stride;
     const unsigned x5 = bot ? xc : xm, x6 = bot ? xc : xp;
     const unsigned x7 = top ? xc : xp, x8 = top ? xc : xm;
-    f[0] = C::load(r0, xc, k.off[0]);
-    f[1] = C::load(r0 + 1 * P, xm, k.off[1]);
-    f[3] = C::load(r0 + 3 * P, xp, k.off[3]);
-    f[2] = C::load(ra + (bot ? 4 : 2) * P, xc, k.off[2]);
-    f[5] = C::load(ra + (bot ? 7 : 5) * P, x5, k.off[5]);
-    f[6] = C::load(ra + (bot ? 8 : 6) * P, x6, k.off[6]);
-    f[4] = C::load(rb + (top ? 2 : 4) * P, xc, k.off[4]);
-    f[7] = C::load(rb + (top ? 5 : 7) * P, x7, k.off[7]);
-    f[8] = C::load(rb + (top ? 6 : 8) * P, x8, k.off[8]);
+    f[0] = C::load(r0, k, 0, xc);
+    f[1] = C::load(r0, k, 1, xm);
+    f[3] = C::load(r0, k, 3, xp);
+    f[2] = C::load(ra, k, bot ? 4 : 2, xc);
+    f[5] = C::load(ra, k, bot ? 7 : 5, x5);
+    f[6] = C::load(ra, k, bot ? 8 : 6, x6);
+    f[4] = C::load(rb, k, top ? 2 : 4, xc);
+    f[7] = C::load(rb, k, top ? 5 : 7, x7);
+    f[8] = C::load(rb, k, top ? 6 : 8, x8);
 }
 
 __device__ __forceinline__ float density(const float f[9])
@@ -206,7 +250,7 @@ __device__ __forceinline__ double p_eos_f64(double rho, double b4, double RT, do
 #define LBMP_APPROX_DIV 0
 #endif
 #ifndef LBMP_NEWTON_DIV
-#define LBMP_NEWTON_DIV 0
+#define LBMP_NEWTON_DIV 1
 #endif
 __device__ __forceinline__ float recip(float x)
 {

@@ -113,7 +113,8 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
             if (live) {
                 typename C::T* row = fout + (long long)y * k.row_stride;
 #pragma unroll
-                for (int a = 0; a < 9; ++a) C::store(row + a * k.pitch, xc, f[a], k.off[a]);
+                for (int a = 0; a < 9; ++a) C::store(row, k, a, xc, f[a], inv_rho);
+                C::store_density(row, k, xc, rc);
             }
         } else if (MODE == kModeMoments) {
             if (live) {
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
                                                  const float* __restrict__ ux0,
                                                  const float* __restrict__ uy0,
                                                  typename Codec<S>::T* __restrict__ fout,
-                                                 StepConst k, double rho_ref, int* __restrict__ flag)
+                                                 StepConst k, int* __restrict__ flag)
 {
     using C = Codec<S>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -235,8 +236,8 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
         const double ux = ux0 ? ux0[i] : 0.0, uy = uy0 ? uy0[i] : 0.0;
         const double eu = EX[a] * ux + EY[a] * uy;
         const double feq = W[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
-        C::store_init(fout + (long long)y * k.row_stride + b * k.pitch, (unsigned)x * (unsigned)sizeof(typename C::T),
-                      feq, W[b] * rho_ref);
+        C::store_init(fout + (long long)y * k.row_stride, k, b, (unsigned)x * (unsigned)sizeof(typename C::T),
+                      feq, (double)rho0[(long long)y * k.nx + x]);
     }
 }
 
@@ -283,6 +284,12 @@ static hipError_t dispatch(int store, bool walls, const void* fin, void* fout, c
     case kStoreBF16:
         return walls ? launch_mode<kStoreBF16, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
                      : launch_mode<kStoreBF16, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+    case kStoreF16Local:
+        return walls ? launch_mode<kStoreF16Local, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_mode<kStoreF16Local, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+    case kStoreBF16Local:
+        return walls ? launch_mode<kStoreBF16Local, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_mode<kStoreBF16Local, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
     default:
         return hipErrorInvalidValue;
     }
@@ -299,6 +306,8 @@ int step_blocks_per_cu(int store, bool walls)
     case kStoreF32: if (walls) LBMP_OCC(kStoreF32, true); else LBMP_OCC(kStoreF32, false); break;
     case kStoreF16: if (walls) LBMP_OCC(kStoreF16, true); else LBMP_OCC(kStoreF16, false); break;
     case kStoreBF16: if (walls) LBMP_OCC(kStoreBF16, true); else LBMP_OCC(kStoreBF16, false); break;
+    case kStoreF16Local: if (walls) LBMP_OCC(kStoreF16Local, true); else LBMP_OCC(kStoreF16Local, false); break;
+    case kStoreBF16Local: if (walls) LBMP_OCC(kStoreBF16Local, true); else LBMP_OCC(kStoreBF16Local, false); break;
     default: break;
     }
 #undef LBMP_OCC
@@ -331,17 +340,18 @@ hipError_t launch_diag(int store, bool walls, const void* fin, const StepConst& 
 }
 
 hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux0,
-                       const float* uy0, void* fout, const StepConst& k, double rho_ref, int* flag,
-                       hipStream_t s)
+                       const float* uy0, void* fout, const StepConst& k, int* flag, hipStream_t s)
 {
     dim3 grid((k.nx + 255) / 256, k.ny), block(256);
 #define LBMP_INIT(S_, W_)                                                                          \
     hipLaunchKernelGGL((d2q9_init<S_, W_>), grid, block, 0, s, rho0, ux0, uy0,                     \
-                       static_cast<typename Codec<S_>::T*>(fout), k, rho_ref, flag)
+                       static_cast<typename Codec<S_>::T*>(fout), k, flag)
     switch (store) {
     case kStoreF32: if (walls) LBMP_INIT(kStoreF32, true); else LBMP_INIT(kStoreF32, false); break;
     case kStoreF16: if (walls) LBMP_INIT(kStoreF16, true); else LBMP_INIT(kStoreF16, false); break;
     case kStoreBF16: if (walls) LBMP_INIT(kStoreBF16, true); else LBMP_INIT(kStoreBF16, false); break;
+    case kStoreF16Local: if (walls) LBMP_INIT(kStoreF16Local, true); else LBMP_INIT(kStoreF16Local, false); break;
+    case kStoreBF16Local: if (walls) LBMP_INIT(kStoreBF16Local, true); else LBMP_INIT(kStoreBF16Local, false); break;
     default: return hipErrorInvalidValue;
     }
 #undef LBMP_INIT

@@ -42,6 +42,12 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t elem_bytes(int store) { return store == LB_STORE_F32 ? 4 : 2; }
 
+bool local_density(int store) { return store == LB_STORE_F16_LOCAL || store == LB_STORE_BF16_LOCAL; }
+
+// storage-type row slots per lattice row: nine population rows, plus an FP32
+// density row (two 16-bit slots) for the local-density encodings
+int row_slots(int store) { return local_density(store) ? 11 : 9; }
+
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 struct Layout {
@@ -53,7 +59,7 @@ Layout layout_of(const lb_params& p)
 {
     Layout L{};
     const int pitch = pitch_of(p.nx);
-    L.buf_bytes = align_up((size_t)9 * p.ny * pitch * elem_bytes(p.store), kAlign);
+    L.buf_bytes = align_up((size_t)row_slots(p.store) * p.ny * pitch * elem_bytes(p.store), kAlign);
     const int tx = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
     const int ty = (p.ny + kDiagStripRows - 1) / kDiagStripRows;
     L.diag_tiles = tx * ty;
@@ -85,7 +91,7 @@ lb_status validate(const lb_params* p)
     if ((long long)pitch_of(p->nx) * (p->store == LB_STORE_F32 ? 4 : 2) >= (1LL << 32))
         return fail(LB_EINVAL, "a padded row must stay below 4 GiB");
     if (p->bc != LB_BC_PERIODIC && p->bc != LB_BC_WALLS_Y) return fail(LB_EINVAL, "unknown bc");
-    if (p->store < LB_STORE_F32 || p->store > LB_STORE_BF16_OFFSET) return fail(LB_EINVAL, "unknown store");
+    if (p->store < LB_STORE_F32 || p->store > LB_STORE_BF16_LOCAL) return fail(LB_EINVAL, "unknown store");
     if (!finite_all({p->a, p->b, p->R, p->T, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta, p->s_j,
                      p->s_q, p->nu_l, p->nu_g, p->rho_switch, p->rho_ref}))
         return fail(LB_EINVAL, "non-finite parameter");
@@ -98,7 +104,8 @@ lb_status validate(const lb_params* p)
         return fail(LB_EINVAL, "relaxation rates must lie in (0, 2)");
     if (!(p->nu_l > 0.0) || !(p->nu_g > 0.0)) return fail(LB_EINVAL, "viscosities must be > 0");
     if (!(p->rho_switch >= 0.0)) return fail(LB_EINVAL, "rho_switch must be >= 0");
-    if (p->store != LB_STORE_F32 && !(p->rho_ref >= 0.0)) return fail(LB_EINVAL, "rho_ref must be >= 0");
+    if ((p->store == LB_STORE_F16_OFFSET || p->store == LB_STORE_BF16_OFFSET) && !(p->rho_ref >= 0.0))
+        return fail(LB_EINVAL, "rho_ref must be >= 0");
     return LB_OK;
 }
 
@@ -112,7 +119,7 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
     k.band = band;
     k.tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
     k.tiles_y = (p.ny + strip_rows - 1) / strip_rows;
-    k.row_stride = 9LL * k.pitch;
+    k.row_stride = (long long)row_slots(p.store) * k.pitch;
     k.b4 = (float)(p.b / 4.0);
     k.RT = (float)(p.R * p.T);
     k.a = (float)p.a;
@@ -129,7 +136,8 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
     k.c_z = (float)(12.0 * p.sigma * G2 * p.s_zeta);
     static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-    for (int a = 0; a < 9; ++a) k.off[a] = p.store == LB_STORE_F32 ? 0.0f : (float)(w[a] * p.rho_ref);
+    const bool global16 = p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET;
+    for (int a = 0; a < 9; ++a) k.off[a] = global16 ? (float)(w[a] * p.rho_ref) : 0.0f;
     return k;
 }
 
@@ -257,7 +265,8 @@ size_t lb_workspace_bytes(const lb_params* p)
 size_t lb_state_bytes(const lb_params* p)
 {
     if (validate(p) != LB_OK) return 0;
-    return (size_t)9 * p->nx * p->ny * elem_bytes(p->store);
+    return (size_t)9 * p->nx * p->ny * elem_bytes(p->store) +
+           (local_density(p->store) ? (size_t)p->nx * p->ny * sizeof(float) : 0);
 }
 
 lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t workspace_bytes,
@@ -291,7 +300,7 @@ lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t work
     hipError_t e = hipMemsetAsync(c->flag, 0, kAlign, c->stream);
     if (e == hipSuccess)
         e = lbmp::launch_init(p->store, p->bc == LB_BC_WALLS_Y, rho0, ux0, uy0, c->f[0], c->k,
-                              p->store == LB_STORE_F32 ? 0.0 : p->rho_ref, c->flag, c->stream);
+                              c->flag, c->stream);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "init launch");
@@ -406,18 +415,36 @@ lb_status lb_check(lb_ctx* c)
 
 int64_t lb_time(const lb_ctx* c) { return c ? c->t : -1; }
 
-// The exported state is [9][ny][nx]; the stored one is [ny][9][pitch].
+// The exported state is [9][ny][nx] (then [ny][nx] FP32 densities for the
+// local-density encodings); the stored one is [ny][row_slots][pitch].
+static hipError_t copy_state(lb_ctx* c, void* dst, const void* src, bool out)
+{
+    const size_t eb = elem_bytes(c->p.store);
+    const size_t nx = c->p.nx, ny = c->p.ny, pitch = c->k.pitch;
+    const size_t row = (size_t)row_slots(c->p.store) * pitch * eb;
+    char* buf = static_cast<char*>(out ? const_cast<void*>(src) : dst);
+    char* ext = static_cast<char*>(out ? dst : const_cast<void*>(src));
+    hipError_t e = hipSuccess;
+    for (int a = 0; a < 9 && e == hipSuccess; ++a) {
+        char* b = buf + a * pitch * eb;
+        char* x = ext + a * ny * nx * eb;
+        e = out ? hipMemcpy2DAsync(x, nx * eb, b, row, nx * eb, ny, hipMemcpyDeviceToDevice, c->stream)
+                : hipMemcpy2DAsync(b, row, x, nx * eb, nx * eb, ny, hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (e == hipSuccess && local_density(c->p.store)) {
+        char* b = buf + 9 * pitch * eb;
+        char* x = ext + 9 * ny * nx * eb;
+        e = out ? hipMemcpy2DAsync(x, nx * 4, b, row, nx * 4, ny, hipMemcpyDeviceToDevice, c->stream)
+                : hipMemcpy2DAsync(b, row, x, nx * 4, nx * 4, ny, hipMemcpyDeviceToDevice, c->stream);
+    }
+    return e;
+}
+
 lb_status lb_get_state(lb_ctx* c, void* dst)
 {
     if (!c || !dst) return fail(LB_EINVAL, "NULL argument");
-    const size_t eb = elem_bytes(c->p.store);
-    const size_t nx = c->p.nx, ny = c->p.ny, pitch = c->k.pitch;
-    for (int a = 0; a < 9; ++a) {
-        hipError_t e = hipMemcpy2DAsync(static_cast<char*>(dst) + a * ny * nx * eb, nx * eb,
-                                        static_cast<const char*>(c->f[c->cur]) + a * pitch * eb, 9 * pitch * eb,
-                                        nx * eb, ny, hipMemcpyDeviceToDevice, c->stream);
-        if (e != hipSuccess) return hip_fail(e, "lb_get_state copy");
-    }
+    hipError_t e = copy_state(c, dst, c->f[c->cur], true);
+    if (e != hipSuccess) return hip_fail(e, "lb_get_state copy");
     return LB_OK;
 }
 
@@ -425,14 +452,8 @@ lb_status lb_set_state(lb_ctx* c, const void* src, int64_t t)
 {
     if (!c || !src) return fail(LB_EINVAL, "NULL argument");
     if (t < 0) return fail(LB_EINVAL, "t must be >= 0");
-    const size_t eb = elem_bytes(c->p.store);
-    const size_t nx = c->p.nx, ny = c->p.ny, pitch = c->k.pitch;
-    for (int a = 0; a < 9; ++a) {
-        hipError_t e = hipMemcpy2DAsync(static_cast<char*>(c->f[0]) + a * pitch * eb, 9 * pitch * eb,
-                                        static_cast<const char*>(src) + a * ny * nx * eb, nx * eb,
-                                        nx * eb, ny, hipMemcpyDeviceToDevice, c->stream);
-        if (e != hipSuccess) return hip_fail(e, "lb_set_state copy");
-    }
+    hipError_t e = copy_state(c, c->f[0], src, false);
+    if (e != hipSuccess) return hip_fail(e, "lb_set_state copy");
     c->cur = 0;
     c->t = t;
     return LB_OK;

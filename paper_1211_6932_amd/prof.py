@@ -76,7 +76,7 @@ def traffic(fetch_dir, write_dir, store, sites):
         scale = COPY_BYTES / (copy_kib * 1024.0)
         res[key] = dict(counter_kib_per_launch=step_kib, copy_counter_kib=copy_kib, scale=scale,
                         bytes_per_launch=step_kib * 1024.0 * scale)
-    bps = {"f32": 72, "f16": 36, "bf16": 36}[store]
+    bps = {"f32": 72, "f16": 36, "bf16": 36, "f16local": 44, "bf16local": 44}[store]
     total = res["read"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
     return dict(store=store, sites=sites, kernel_sha=kernel_hash(), bytes_per_launch=total,
                 algorithmic_bytes=bps * sites, ratio=total / (bps * sites), detail=res)

@@ -58,7 +58,7 @@ def test_validate_accepts_paper_parameters():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 2), ("ny", 0), ("nx", (1 << 20) + 1), ("bc", 2), ("store", 3), ("b", 0.0), ("T", -1.0),
+    ("nx", 2), ("ny", 0), ("nx", (1 << 20) + 1), ("bc", 2), ("store", 5), ("store", -1), ("b", 0.0), ("T", -1.0),
     ("G", 0.0), ("G", 1.0), ("sigma", -0.1), ("s_e", 0.0), ("s_e", 2.0), ("s_q", 2.5),
     ("s_rho", -1.0), ("s_j", 2.0), ("nu_l", 0.0), ("nu_g", -0.1), ("a", float("nan")),
     ("R", 0.0), ("T", float("inf")),
@@ -79,6 +79,9 @@ def test_sizes():
     assert ws >= 2 * 9 * 128 * 128 * 4 and ws % 256 == 0
     p.store = B.LB_STORE_F16_OFFSET
     assert B.lb_state_bytes(p) == 9 * 128 * 128 * 2
+    p.store = B.LB_STORE_F16_LOCAL  # 16-bit offsets plus the FP32 site densities
+    assert B.lb_state_bytes(p) == 9 * 128 * 128 * 2 + 128 * 128 * 4
+    assert B.lb_workspace_bytes(p) >= 2 * 11 * 128 * 128 * 2
     # ragged widths are padded to 64-element rows
     p2 = good()
     p2.nx, p2.ny = 67, 5

@@ -1,0 +1,141 @@
+"""Reduced-precision storage (16-bit offsets) against the FP64 oracle, through the C ABI.
+
+Encodings (collision and force stay FP32):
+  f16 / bf16            h_a = RNE16(f*_a - w_a rho_ref), one reference density;
+  f16local / bf16local  g_a = RNE16(f*_a / rho - w_a) with the site's rho in FP32.
+
+Bounds:
+  * one step from the same (decoded) state: each stored value is the oracle's
+    post-collision value rounded once to 16 bits, so
+      |decoded - oracle| <= 0.5 ulp16(encoded value) * scale + 2e-6 max|f|
+    (scale = 1 for the global offsets, rho for the relative local ones; the
+    second term is the FP32 arithmetic, as in the FP32 one-step test);
+  * at rest with rho = rho_ref (global) or any uniform rho (local) the stored
+    offsets vanish up to FP32 rounding of the weights (|offset| <= 1e-6, against
+    O(1e-2) offsets in a flow);
+  * f16local: Laplace pressure jump of an equilibrated droplet within 1 % of the
+    FP64 oracle (the accuracy target for reduced-precision storage)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import lbref as O
+from oracle import post
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1211_6932_amd.lbmp")
+
+WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+GLOBAL = ("f16", "bf16")
+LOCAL = ("f16local", "bf16local")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    B.load()
+    yield
+
+
+def f32(a):
+    return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def make_sim(w, store, strip_rows=0):
+    r, ux, uy = f32(w.rho0), f32(w.ux0), f32(w.uy0)
+    rho_ref = w.info.get("rho_l", 0.4) if store in GLOBAL else 0.0
+    s = B.Sim(w.params, torch.from_numpy(r), None if ux is None else torch.from_numpy(ux),
+              None if uy is None else torch.from_numpy(uy), store=store, rho_ref=rho_ref)
+    if strip_rows:
+        s.set_launch(strip_rows=strip_rows)
+    return s
+
+
+def raw_state(s, store):
+    """(encoded [9][ny][nx] as float64, densities [ny][nx] or None)."""
+    buf = s.get_state()
+    n = 9 * s.ny * s.nx
+    h16 = buf[: 2 * n].view(torch.float16 if store.startswith("f16") else torch.bfloat16)
+    enc = h16.float().cpu().numpy().astype(np.float64).reshape(9, s.ny, s.nx)
+    rho = None
+    if store in LOCAL:
+        rho = buf[2 * n:].view(torch.float32).cpu().numpy().astype(np.float64).reshape(s.ny, s.nx)
+    return enc, rho
+
+
+def decode(enc, rho, store, rho_ref):
+    if store in LOCAL:
+        return rho[None] * (WEIGHTS[:, None, None] + enc)
+    return enc + (WEIGHTS * rho_ref)[:, None, None]
+
+
+def ulp16(x, store):
+    x = np.abs(x)
+    if store.startswith("bf16"):
+        e = np.floor(np.log2(np.maximum(x, 1e-38)))
+        return 2.0 ** (e - 7)
+    e = np.floor(np.log2(np.maximum(x, 2.0 ** -14)))
+    return 2.0 ** (e - 10)
+
+
+@pytest.mark.parametrize("store", GLOBAL + LOCAL)
+@pytest.mark.parametrize("case", ["droplet_periodic", "splash_walls"])
+def test_one_step_is_the_oracle_rounded_once(store, case):
+    if case == "droplet_periodic":
+        w = W.stationary_droplet(n=96, R0=20)
+    else:
+        w = W.splash(nx=192, ny=96, Re=200)
+        w.info["R"] = 100
+    print(f"[gpu-case] precision one-step store={store} case={case}", flush=True)
+    rho_ref = w.info.get("rho_l", 0.4) if store in GLOBAL else 0.0
+    s = make_sim(w, store, strip_rows=16)
+    s.step(5)
+    e5, r5 = raw_state(s, store)
+    s.step(1)
+    e6, r6 = raw_state(s, store)
+    p = O.Params(**w.params)
+    f5 = O.stream(p, decode(e5, r5, store, rho_ref))
+    ny, nx = w.params["ny"], w.params["nx"]
+    ref = O.collide_at(p, f5, np.arange(nx * ny)).T.reshape(9, ny, nx)
+    got = decode(e6, r6, store, rho_ref)
+    if store in LOCAL:
+        enc_ref = ref / r6[None] - WEIGHTS[:, None, None]
+        bound = 0.5 * ulp16(enc_ref, store) * r6[None]
+    else:
+        bound = 0.5 * ulp16(ref - (WEIGHTS * rho_ref)[:, None, None], store)
+    bound = bound + 2e-6 * np.abs(ref).max()
+    excess = np.abs(got - ref) - bound
+    assert excess.max() <= 0.0, (store, case, float(excess.max()))
+
+
+@pytest.mark.parametrize("store", GLOBAL + LOCAL)
+def test_offsets_vanish_at_rest(store):
+    rho = 0.3
+    p = W.base_params(70, 20)
+    wl = W.Workload("uniform", p, np.full((20, 70), rho), info=dict(rho_l=rho))
+    s = make_sim(wl, store)
+    s.step(3)
+    enc, dens = raw_state(s, store)
+    assert np.abs(enc).max() <= 1e-6
+    if dens is not None:
+        assert np.abs(dens - rho).max() <= 1e-7
+
+
+def test_f16local_laplace_jump_within_one_percent():
+    """Droplet 96 x 96, R0 = 20, a = 0.5, T = 0.6 T_c, 3000 steps: the pressure jump
+    with FP16 relative-offset storage is within 1 % of the FP64 oracle's."""
+    w = W.stationary_droplet(n=96, R0=20)
+    o = O.State(O.Params(**w.params), f32(w.rho0).astype(np.float64)).step(3000)
+    lo = post.laplace(o.moments()[0], w.params, 20.0)
+    s = make_sim(w, "f16local")
+    s.step(3000)
+    s.check()
+    rho = s.moments()[0].cpu().numpy().astype(np.float64)
+    lg = post.laplace(rho, w.params, 20.0)
+    rel = lg["dp"] / lo["dp"] - 1.0
+    print(f"f16local Laplace dp {lg['dp']:.6e} vs oracle {lo['dp']:.6e}: {rel:+.3e}")
+    assert abs(rel) <= 0.01
+    assert abs(lg["rho_out"] / lo["rho_out"] - 1.0) <= 0.01
