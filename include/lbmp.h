@@ -176,6 +176,50 @@ lb_status lb_set_launch(lb_ctx* ctx, int32_t strip_rows, int32_t band, int32_t g
 /* Release the context and its graphs (not the caller's workspace). */
 lb_status lb_destroy(lb_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched lattices: many independent lattices (each with its own size and
+ * parameters, all sharing `store` and `bc`) advanced by one persistent launch.
+ * One workgroup owns one lattice for the whole launch and runs the same
+ * per-site arithmetic as lb_step, so each lattice's state is bitwise equal to
+ * running it alone.  Lattices are dispatched largest first.
+ * ---------------------------------------------------------------------- */
+typedef struct lb_batch lb_batch;
+
+/* Workspace bytes for n lattices with parameter blocks p[0..n-1] (0 if invalid:
+ * n < 1, a bad block, differing store/bc, or a store other than LB_STORE_F32 /
+ * LB_STORE_F16_LOCAL).  Pure host function. */
+size_t lb_batch_workspace_bytes(const lb_params* p, int32_t n);
+
+/* Create the batch on a caller-owned device workspace (256-byte aligned, at
+ * least lb_batch_workspace_bytes) and set every lattice to its t = 0 state.
+ * rho0, ux0, uy0 are host arrays of n device pointers to FP32 [ny_i][nx_i]
+ * fields; ux0/uy0 (or entries of them) may be NULL.  Synchronises the stream;
+ * LB_EINVAL names the first offending lattice in lb_last_error(). */
+lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* workspace,
+                        size_t workspace_bytes, const float* const* rho0, const float* const* ux0,
+                        const float* const* uy0, void* stream);
+
+/* Advance every lattice by nsteps (1 launch; asynchronous). */
+lb_status lb_batch_step(lb_batch* b, int64_t nsteps);
+
+/* Per-lattice access with the semantics of lb_moments / lb_diagnostics /
+ * lb_get_state (lattice index i in the order of lb_batch_init). */
+lb_status lb_batch_moments(lb_batch* b, int32_t i, float* rho, float* ux, float* uy);
+lb_status lb_batch_diagnostics(lb_batch* b, int32_t i, const lb_region* in, const lb_region* out,
+                               lb_diag* diag);
+lb_status lb_batch_get_state(lb_batch* b, int32_t i, void* dst);
+
+/* Synchronise; *unstable (may be NULL) receives the number of lattices that
+ * flagged an unstable site (LB_EUNSTABLE if any). */
+lb_status lb_batch_check(lb_batch* b, int32_t* unstable);
+
+/* Synchronise; seconds[i] (host array of n) = completion time of lattice i in
+ * the last lb_batch_step launch, measured from the earliest workgroup start. */
+lb_status lb_batch_times(lb_batch* b, double* seconds);
+
+/* Release the batch and its contexts (not the caller's workspace). */
+lb_status lb_batch_destroy(lb_batch* b);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* lb_last_error(void);
 

@@ -55,6 +55,14 @@ struct StepConst {
     float off[9];               // w_a rho_ref: offsets of the 16-bit storage (0 for FP32)
 };
 
+// One lattice of a batched launch: its constants, its two state buffers and
+// its unstable flag.
+struct BatchInstance {
+    StepConst k;
+    void* f[2];
+    int* flag;
+};
+
 // Diagnostics regions (annuli) and output.
 struct DiagConst {
     double in_cx, in_cy, in_r0, in_r1;

@@ -5,6 +5,7 @@
 //                     psi, force, velocity) and then, by MODE, collides and
 //                     stores (the time step), writes rho/v (moments), or
 //                     accumulates FP64 reductions (diagnostics).
+//   d2q9_batch        persistent multi-instance step (one workgroup per lattice)
 //   d2q9_init         equilibrium initial state, written "pre-streamed" so
 //                     that the first pull returns f_eq(rho0, u0)
 //   diag_finalize     fixed-order FP64 reduction of the per-wave partials
@@ -18,20 +19,17 @@ namespace lbmp {
 #define LBMP_STEP_WAVES_PER_EU 1
 #endif
 
+// One wavefront processes strip `tile` of the lattice described by `k`: pull,
+// density, psi, force and velocity for every row, then by MODE collide and
+// store (a time step), write rho/v (moments) or accumulate FP64 reductions.
 template <int S, bool WALLS, int MODE>
-__global__ __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
+__device__ __forceinline__ void strip_tile(
     const typename Codec<S>::T* __restrict__ fin, typename Codec<S>::T* __restrict__ fout,
-    StepConst k, int* __restrict__ flag, float* __restrict__ rho_out, float* __restrict__ ux_out,
-    float* __restrict__ uy_out, DiagConst dg, double* __restrict__ partial)
+    const StepConst& k, const int tile, const int lane, int* __restrict__ flag,
+    float* __restrict__ rho_out, float* __restrict__ ux_out, float* __restrict__ uy_out,
+    const DiagConst& dg, double* __restrict__ partial)
 {
     using C = Codec<S>;
-    const int lane = threadIdx.x & (kWave - 1);
-    // the wave index is uniform across the wave: keep it (and every row address
-    // derived from it) in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = logical_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
-    if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
     // Tiles are numbered in bands of `band` strips: within a band, consecutive
     // tiles go down the strips first, so the wavefronts of one workgroup cover a
     // small rectangle and share halo rows and columns in the CU's L1.
@@ -165,6 +163,52 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
         }
     }
     if (bad) flag[0] = kFlagUnstable;  // vector store from any flagging lane; all write the same value
+}
+
+template <int S, bool WALLS, int MODE>
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
+    const typename Codec<S>::T* __restrict__ fin, typename Codec<S>::T* __restrict__ fout,
+    StepConst k, int* __restrict__ flag, float* __restrict__ rho_out, float* __restrict__ ux_out,
+    float* __restrict__ uy_out, DiagConst dg, double* __restrict__ partial)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    // the wave index is uniform across the wave: keep it (and every row address
+    // derived from it) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = logical_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+    if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
+    strip_tile<S, WALLS, MODE>(fin, fout, k, tile, lane, flag, rho_out, ux_out, uy_out, dg, partial);
+}
+
+// Persistent multi-instance step: one workgroup owns one lattice and advances
+// it `steps` time steps; its 16 wavefronts share the strips of each step and
+// meet at a workgroup barrier between steps (the barrier orders the global
+// stores of step t before the loads of step t+1 for all waves of the CU).
+// Workgroups never wait for each other.  Each records the wall clock at its
+// start and end (for per-instance completion times).
+template <int S, bool WALLS>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_batch(
+    const BatchInstance* __restrict__ inst, int steps, int parity,
+    unsigned long long* __restrict__ clock_out)
+{
+    using T = typename Codec<S>::T;
+    const BatchInstance& I = inst[blockIdx.x];
+    const StepConst k = I.k;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntiles = k.tiles_x * k.tiles_y;
+    T* buf[2] = {reinterpret_cast<T*>(I.f[0]), reinterpret_cast<T*>(I.f[1])};
+    if (threadIdx.x == 0) clock_out[2 * blockIdx.x] = wall_clock64();
+    DiagConst dg{};
+    for (int s = 0; s < steps; ++s) {
+        const int cur = (parity + s) & 1;
+        for (int tile = wave; tile < ntiles; tile += kWavesPerBlock)
+            strip_tile<S, WALLS, kModeStep>(buf[cur], buf[cur ^ 1], k, tile, lane, I.flag, nullptr,
+                                            nullptr, nullptr, dg, nullptr);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) clock_out[2 * blockIdx.x + 1] = wall_clock64();
 }
 
 // Single-block, fixed-order reduction of per-wave partials (deterministic).
@@ -320,6 +364,22 @@ hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const
     DiagConst dg{};
     return dispatch<kModeStep>(store, walls, fin, fout, k, flag, nullptr, nullptr, nullptr, dg,
                                nullptr, s);
+}
+
+hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n, int steps, int parity,
+                        unsigned long long* clocks, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+#define LBMP_BATCH(S_, W_)                                                                         \
+    hipLaunchKernelGGL((d2q9_batch<S_, W_>), dim3(n), dim3(kWave * kWavesPerBlock), 0, s, inst,      \
+                       steps, parity, clocks)
+    switch (store) {
+    case kStoreF32: if (walls) LBMP_BATCH(kStoreF32, true); else LBMP_BATCH(kStoreF32, false); break;
+    case kStoreF16Local: if (walls) LBMP_BATCH(kStoreF16Local, true); else LBMP_BATCH(kStoreF16Local, false); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef LBMP_BATCH
+    return hipGetLastError();
 }
 
 hipError_t launch_moments(int store, bool walls, const void* fin, const StepConst& k, int* flag,

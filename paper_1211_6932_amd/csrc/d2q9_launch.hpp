@@ -12,6 +12,12 @@ namespace lbmp {
 hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
                        int* flag, hipStream_t s);
 
+// Persistent batched step: workgroup i advances lattice inst[i] by `steps`
+// steps starting from buffer `parity`; clocks[2i], clocks[2i+1] receive the
+// wall clock at the workgroup's start and end.  Stores: F32, F16 local.
+hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n, int steps, int parity,
+                        unsigned long long* clocks, hipStream_t s);
+
 // Resident step workgroups per compute unit (0 if the query fails).
 int step_blocks_per_cu(int store, bool walls);
 

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/lbmp.h"
 #include "d2q9_launch.hpp"
@@ -269,8 +270,14 @@ size_t lb_state_bytes(const lb_params* p)
            (local_density(p->store) ? (size_t)p->nx * p->ny * sizeof(float) : 0);
 }
 
-lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t workspace_bytes,
-                  const float* rho0, const float* ux0, const float* uy0, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Create a context on `workspace` and launch the initial state; with
+// sync == false the caller synchronises and checks the flag (batched init).
+lb_status init_ctx(lb_ctx** out, const lb_params* p, void* workspace, size_t workspace_bytes,
+                   const float* rho0, const float* ux0, const float* uy0, void* stream, bool sync)
 {
     if (!out) return fail(LB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -305,21 +312,34 @@ lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t work
         delete c;
         return hip_fail(e, "init launch");
     }
-    int hf = 0;
-    st = read_flag(c, &hf);
-    if (st != LB_OK) {
-        delete c;
-        return st;
-    }
-    if (hf & lbmp::kFlagBadInput) {
-        delete c;
-        return fail(LB_EINVAL, "rho0/u0 out of range (need finite, rho > 0, b rho/4 < 1, psi^2 > 0)");
+    if (sync) {
+        int hf = 0;
+        st = read_flag(c, &hf);
+        if (st != LB_OK) {
+            delete c;
+            return st;
+        }
+        if (hf & lbmp::kFlagBadInput) {
+            delete c;
+            return fail(LB_EINVAL, "rho0/u0 out of range (need finite, rho > 0, b rho/4 < 1, psi^2 > 0)");
+        }
     }
     c->cur = 0;
     c->t = 0;
     *out = c;
-    g_last_error.clear();
     return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t workspace_bytes,
+                  const float* rho0, const float* ux0, const float* uy0, void* stream)
+{
+    lb_status st = init_ctx(out, p, workspace, workspace_bytes, rho0, ux0, uy0, stream, true);
+    if (st == LB_OK) g_last_error.clear();
+    return st;
 }
 
 lb_status lb_step(lb_ctx* c, int64_t n)
@@ -485,6 +505,213 @@ lb_status lb_destroy(lb_ctx* c)
 }
 
 const char* lb_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ batched lattices
+
+struct lb_batch {
+    int n;
+    std::vector<lb_ctx*> inst;       // per-lattice contexts on slices of the workspace
+    std::vector<int> order;          // dispatch position -> lattice index (largest first)
+    lbmp::BatchInstance* desc;       // device descriptors in dispatch order
+    unsigned long long* clocks;      // device, 2 per workgroup
+    hipStream_t stream;
+    int store, bc;
+    bool poisoned;
+};
+
+namespace {
+
+size_t batch_header_bytes(int n)
+{
+    return align_up((size_t)n * sizeof(lbmp::BatchInstance), kAlign) + align_up((size_t)n * 16, kAlign);
+}
+
+lb_status validate_batch(const lb_params* p, int32_t n)
+{
+    if (!p || n < 1) return fail(LB_EINVAL, "need n >= 1 parameter blocks");
+    for (int i = 0; i < n; ++i) {
+        lb_status st = validate(p + i);
+        if (st != LB_OK) return fail(st, "lattice " + std::to_string(i) + ": " + g_last_error);
+        if (p[i].store != p[0].store || p[i].bc != p[0].bc)
+            return fail(LB_EINVAL, "all lattices of a batch share store and bc");
+    }
+    if (p[0].store != LB_STORE_F32 && p[0].store != LB_STORE_F16_LOCAL)
+        return fail(LB_EINVAL, "batched storage must be LB_STORE_F32 or LB_STORE_F16_LOCAL");
+    return LB_OK;
+}
+
+}  // namespace
+
+size_t lb_batch_workspace_bytes(const lb_params* p, int32_t n)
+{
+    if (validate_batch(p, n) != LB_OK) return 0;
+    size_t total = batch_header_bytes(n);
+    for (int i = 0; i < n; ++i) total += layout_of(p[i]).total;
+    return total;
+}
+
+lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* workspace,
+                        size_t workspace_bytes, const float* const* rho0, const float* const* ux0,
+                        const float* const* uy0, void* stream)
+{
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    lb_status st = validate_batch(p, n);
+    if (st != LB_OK) return st;
+    if (!workspace || !rho0) return fail(LB_EINVAL, "workspace and rho0 must be non-NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(LB_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < lb_batch_workspace_bytes(p, n))
+        return fail(LB_ENOMEM, "workspace smaller than lb_batch_workspace_bytes");
+
+    lb_batch* b = new (std::nothrow) lb_batch{};
+    if (!b) return fail(LB_ENOMEM, "host allocation failed");
+    b->n = n;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->store = p[0].store;
+    b->bc = p[0].bc;
+    char* ws = static_cast<char*>(workspace);
+    b->desc = reinterpret_cast<lbmp::BatchInstance*>(ws);
+    b->clocks = reinterpret_cast<unsigned long long*>(ws + align_up((size_t)n * sizeof(lbmp::BatchInstance), kAlign));
+    size_t off = batch_header_bytes(n);
+    b->inst.assign(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+        const size_t bytes = layout_of(p[i]).total;
+        st = init_ctx(&b->inst[i], p + i, ws + off, bytes, rho0[i], ux0 ? ux0[i] : nullptr,
+                      uy0 ? uy0[i] : nullptr, stream, false);
+        if (st != LB_OK) {
+            const std::string msg = g_last_error;
+            lb_batch_destroy(b);
+            return fail(st, "lattice " + std::to_string(i) + ": " + msg);
+        }
+        off += bytes;
+    }
+    // dispatch the largest lattices first (longest-processing-time order)
+    b->order.resize(n);
+    for (int i = 0; i < n; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return (long long)p[x].nx * p[x].ny > (long long)p[y].nx * p[y].ny;
+    });
+    std::vector<lbmp::BatchInstance> host(n);
+    for (int j = 0; j < n; ++j) {
+        lb_ctx* c = b->inst[b->order[j]];
+        host[j].k = c->k;
+        host[j].f[0] = c->f[0];
+        host[j].f[1] = c->f[1];
+        host[j].flag = c->flag;
+    }
+    hipError_t e = hipMemcpyAsync(b->desc, host.data(), n * sizeof(lbmp::BatchInstance), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        lb_batch_destroy(b);
+        return hip_fail(e, "batch descriptors");
+    }
+    for (int i = 0; i < n; ++i) {
+        int hf = 0;
+        st = read_flag(b->inst[i], &hf);
+        if (st == LB_OK && (hf & lbmp::kFlagBadInput))
+            st = fail(LB_EINVAL, "lattice " + std::to_string(i) + ": rho0/u0 out of range");
+        if (st != LB_OK) {
+            const std::string msg = g_last_error;
+            lb_batch_destroy(b);
+            return fail(st, msg);
+        }
+    }
+    *out = b;
+    g_last_error.clear();
+    return LB_OK;
+}
+
+lb_status lb_batch_step(lb_batch* b, int64_t nsteps)
+{
+    if (!b) return fail(LB_EINVAL, "batch is NULL");
+    if (b->poisoned) return fail(LB_ESTATE, "batch poisoned by an earlier failure");
+    if (nsteps < 0 || nsteps > (1LL << 30)) return fail(LB_EINVAL, "nsteps must lie in [0, 2^30]");
+    if (nsteps == 0) return LB_OK;
+    const int parity = b->inst[0]->cur;
+    hipError_t e = lbmp::launch_batch(b->store, b->bc == LB_BC_WALLS_Y, b->desc, b->n, (int)nsteps, parity,
+                                      b->clocks, b->stream);
+    if (e != hipSuccess) {
+        b->poisoned = true;
+        return hip_fail(e, "batch launch");
+    }
+    for (lb_ctx* c : b->inst) {
+        c->cur ^= (int)(nsteps & 1);
+        c->t += nsteps;
+    }
+    return LB_OK;
+}
+
+static lb_ctx* batch_member(lb_batch* b, int32_t i)
+{
+    if (!b || i < 0 || i >= b->n) return nullptr;
+    return b->inst[i];
+}
+
+lb_status lb_batch_moments(lb_batch* b, int32_t i, float* rho, float* ux, float* uy)
+{
+    lb_ctx* c = batch_member(b, i);
+    if (!c) return fail(LB_EINVAL, "no such lattice");
+    return lb_moments(c, rho, ux, uy);
+}
+
+lb_status lb_batch_diagnostics(lb_batch* b, int32_t i, const lb_region* in, const lb_region* outr, lb_diag* d)
+{
+    lb_ctx* c = batch_member(b, i);
+    if (!c) return fail(LB_EINVAL, "no such lattice");
+    return lb_diagnostics(c, in, outr, d);
+}
+
+lb_status lb_batch_get_state(lb_batch* b, int32_t i, void* dst)
+{
+    lb_ctx* c = batch_member(b, i);
+    if (!c) return fail(LB_EINVAL, "no such lattice");
+    return lb_get_state(c, dst);
+}
+
+lb_status lb_batch_check(lb_batch* b, int32_t* unstable)
+{
+    if (!b) return fail(LB_EINVAL, "batch is NULL");
+    int count = 0;
+    for (lb_ctx* c : b->inst) {
+        int hf = 0;
+        lb_status st = read_flag(c, &hf);
+        if (st != LB_OK) return st;
+        if (hf & lbmp::kFlagUnstable) {
+            ++count;
+            c->poisoned = true;
+        }
+    }
+    if (unstable) *unstable = count;
+    return count ? fail(LB_EUNSTABLE, std::to_string(count) + " lattice(s) flagged an unstable site") : LB_OK;
+}
+
+lb_status lb_batch_times(lb_batch* b, double* seconds)
+{
+    if (!b || !seconds) return fail(LB_EINVAL, "NULL argument");
+    std::vector<unsigned long long> h(2 * (size_t)b->n);
+    hipError_t e = hipMemcpyAsync(h.data(), b->clocks, h.size() * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    int dev = 0, khz = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return hip_fail(e, "batch clocks");
+    if (khz <= 0) return fail(LB_EHIP, "device reports no wall-clock rate");
+    unsigned long long t0 = h[0];
+    for (int j = 0; j < b->n; ++j) t0 = std::min(t0, h[2 * j]);
+    for (int j = 0; j < b->n; ++j) seconds[b->order[j]] = (double)(h[2 * j + 1] - t0) / (khz * 1e3);
+    return LB_OK;
+}
+
+lb_status lb_batch_destroy(lb_batch* b)
+{
+    if (!b) return LB_OK;
+    for (lb_ctx* c : b->inst)
+        if (c) lb_destroy(c);
+    delete b;
+    return LB_OK;
+}
 
 lb_status lb_copy_probe(const void* src, void* dst, size_t bytes, void* stream)
 {

@@ -60,6 +60,8 @@ EXPORTS = [
     "lb_validate_params", "lb_workspace_bytes", "lb_state_bytes", "lb_init", "lb_step", "lb_moments",
     "lb_diagnostics", "lb_check", "lb_time", "lb_get_state", "lb_set_state", "lb_set_launch",
     "lb_destroy", "lb_last_error", "lb_copy_probe",
+    "lb_batch_workspace_bytes", "lb_batch_init", "lb_batch_step", "lb_batch_moments",
+    "lb_batch_diagnostics", "lb_batch_get_state", "lb_batch_check", "lb_batch_times", "lb_batch_destroy",
 ]
 
 _lib = None
@@ -106,6 +108,26 @@ def load():
     L.lb_last_error.restype = ctypes.c_char_p
     L.lb_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.lb_copy_probe.restype = ctypes.c_int
+    vpp = ctypes.POINTER(vp)
+    L.lb_batch_workspace_bytes.argtypes = [P, ctypes.c_int32]
+    L.lb_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.lb_batch_init.argtypes = [ctypes.POINTER(vp), P, ctypes.c_int32, vp, ctypes.c_size_t, vpp, vpp, vpp, vp]
+    L.lb_batch_init.restype = ctypes.c_int
+    L.lb_batch_step.argtypes = [vp, ctypes.c_int64]
+    L.lb_batch_step.restype = ctypes.c_int
+    L.lb_batch_moments.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+    L.lb_batch_moments.restype = ctypes.c_int
+    L.lb_batch_diagnostics.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(lb_region), ctypes.POINTER(lb_region),
+                                       ctypes.POINTER(lb_diag)]
+    L.lb_batch_diagnostics.restype = ctypes.c_int
+    L.lb_batch_get_state.argtypes = [vp, ctypes.c_int32, vp]
+    L.lb_batch_get_state.restype = ctypes.c_int
+    L.lb_batch_check.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.lb_batch_check.restype = ctypes.c_int
+    L.lb_batch_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.lb_batch_times.restype = ctypes.c_int
+    L.lb_batch_destroy.argtypes = [vp]
+    L.lb_batch_destroy.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -207,6 +229,60 @@ def lb_copy_probe(src_ptr: int, dst_ptr: int, nbytes: int, stream: int):
                                        ctypes.c_void_p(stream or None)), "lb_copy_probe")
 
 
+def lb_batch_workspace_bytes(params_array, n: int) -> int:
+    return load().lb_batch_workspace_bytes(params_array, int(n))
+
+
+def lb_batch_init(params_array, n, workspace_ptr, workspace_bytes, rho0_ptrs, ux0_ptrs, uy0_ptrs, stream):
+    def arr(ptrs):
+        if ptrs is None:
+            return None
+        return (ctypes.c_void_p * n)(*[p or None for p in ptrs])
+    b = ctypes.c_void_p()
+    st = load().lb_batch_init(ctypes.byref(b), params_array, int(n), ctypes.c_void_p(workspace_ptr),
+                              workspace_bytes, arr(rho0_ptrs), arr(ux0_ptrs), arr(uy0_ptrs),
+                              ctypes.c_void_p(stream or None))
+    _check(st, "lb_batch_init")
+    return b
+
+
+def lb_batch_step(b, n: int):
+    return _check(load().lb_batch_step(b, int(n)), "lb_batch_step")
+
+
+def lb_batch_moments(b, i, rho_ptr, ux_ptr, uy_ptr):
+    return _check(load().lb_batch_moments(b, int(i), ctypes.c_void_p(rho_ptr or None),
+                                          ctypes.c_void_p(ux_ptr or None), ctypes.c_void_p(uy_ptr or None)),
+                  "lb_batch_moments")
+
+
+def lb_batch_diagnostics(b, i, region_in: lb_region, region_out: lb_region) -> lb_diag:
+    d = lb_diag()
+    _check(load().lb_batch_diagnostics(b, int(i), ctypes.byref(region_in), ctypes.byref(region_out),
+                                       ctypes.byref(d)), "lb_batch_diagnostics")
+    return d
+
+
+def lb_batch_get_state(b, i, dst_ptr):
+    return _check(load().lb_batch_get_state(b, int(i), ctypes.c_void_p(dst_ptr)), "lb_batch_get_state")
+
+
+def lb_batch_check(b):
+    n = ctypes.c_int32(0)
+    st = load().lb_batch_check(b, ctypes.byref(n))
+    return st, n.value
+
+
+def lb_batch_times(b, n):
+    out = (ctypes.c_double * n)()
+    _check(load().lb_batch_times(b, out), "lb_batch_times")
+    return list(out)
+
+
+def lb_batch_destroy(b):
+    return load().lb_batch_destroy(b)
+
+
 # -------------------------------------------------------------- torch convenience wrapper
 
 class Sim:
@@ -298,3 +374,82 @@ class Sim:
     def set_state(self, buf, t):
         lb_set_state(self.ctx, buf.data_ptr(), t)
         self.stream.synchronize()
+
+
+class Batch:
+    """Many independent lattices advanced together by one persistent launch."""
+
+    def __init__(self, params_list, rho0_list, ux0_list=None, uy0_list=None, store="f32", stream=None,
+                 device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("lbmp.Batch needs a ROCm GPU")
+        self.torch = torch
+        self.n = n = len(params_list)
+        self.params = (lb_params * n)(*[make_params(d, store) for d in params_list])
+        self.shapes = [(p.ny, p.nx) for p in self.params]
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+
+        def dev(t, shape):
+            if t is None:
+                return None
+            t = torch.as_tensor(t)
+            if tuple(t.shape) != shape:
+                raise ValueError(f"field shape {tuple(t.shape)} != {shape}")
+            return t.to(device=self.device, dtype=torch.float32).contiguous()
+
+        self._inputs = []
+        ptrs = {"rho": [], "ux": [], "uy": []}
+        for i in range(n):
+            for key, lst in (("rho", rho0_list), ("ux", ux0_list), ("uy", uy0_list)):
+                t = dev(None if lst is None else lst[i], self.shapes[i])
+                self._inputs.append(t)
+                ptrs[key].append(0 if t is None else t.data_ptr())
+        nbytes = lb_batch_workspace_bytes(self.params, n)
+        if nbytes == 0:
+            raise LbError(LB_EINVAL, "lb_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(self.stream):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            self.b = lb_batch_init(self.params, n, self.workspace.data_ptr(), nbytes, ptrs["rho"],
+                                   None if ux0_list is None else ptrs["ux"],
+                                   None if uy0_list is None else ptrs["uy"], self.stream.cuda_stream)
+        self._inputs = None
+
+    def close(self):
+        b = getattr(self, "b", None)
+        if b is not None:
+            self.b = None
+            self.stream.synchronize()
+            lb_batch_destroy(b)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass
+
+    def step(self, n):
+        lb_batch_step(self.b, n)
+        return self
+
+    def times(self):
+        return lb_batch_times(self.b, self.n)
+
+    def check(self):
+        return lb_batch_check(self.b)
+
+    def moments(self, i):
+        torch = self.torch
+        out = [torch.empty(self.shapes[i], dtype=torch.float32, device=self.device) for _ in range(3)]
+        lb_batch_moments(self.b, i, *[o.data_ptr() for o in out])
+        self.stream.synchronize()
+        return tuple(out)
+
+    def get_state(self, i, state_bytes):
+        torch = self.torch
+        buf = torch.empty(state_bytes, dtype=torch.uint8, device=self.device)
+        lb_batch_get_state(self.b, i, buf.data_ptr())
+        self.stream.synchronize()
+        return buf

@@ -109,3 +109,14 @@ def test_host_side_errors_need_no_gpu():
     assert L.lb_time(None) == -1
     assert L.lb_destroy(None) == B.LB_OK
     assert L.lb_copy_probe(None, None, 16, None) == B.LB_EINVAL
+
+
+def test_batch_workspace_sizing_is_pure_host():
+    a = B.make_params(W.stationary_droplet(n=64).params)
+    b = B.make_params(W.stationary_droplet(n=100).params)
+    arr = (B.lb_params * 2)(a, b)
+    total = B.lb_batch_workspace_bytes(arr, 2)
+    assert total >= B.lb_workspace_bytes(a) + B.lb_workspace_bytes(b)
+    assert B.lb_batch_workspace_bytes(arr, 0) == 0
+    b.bc = 1  # lattices of one batch share the boundary type
+    assert B.lb_batch_workspace_bytes((B.lb_params * 2)(a, b), 2) == 0

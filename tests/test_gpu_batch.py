@@ -1,0 +1,94 @@
+"""Batched multi-lattice launch through the C ABI: bitwise equal to single-lattice
+runs (same per-site arithmetic), parity bookkeeping across calls, per-lattice
+completion times, error handling."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1211_6932_amd.lbmp")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    B.load()
+    yield
+
+
+def f32(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32)))
+
+
+def mixed_lattices(bc=0):
+    """Different sizes (ragged, tiny, multi-tile), EOS parameters, shapes."""
+    ws = []
+    for k, (n, a, tb, R0, ell) in enumerate([(67, 0.5, 0.6, 12, False), (130, 0.25, 0.55, 30, True),
+                                             (64, 1.0, 0.8, 14, False), (96, 0.5, 0.7, 20, True),
+                                             (200, 0.25, 0.6, 40, False), (33, 0.5, 0.85, 6, False)]):
+        p = W.base_params(n, n + 7 * k, a=a, t_over_tc=tb, bc=bc)
+        rl, rg = W.coexistence(tb)
+        ny = n + 7 * k
+        if ell:
+            rho0 = W.ellipse_field(n, ny, R0, 1.2, rl, rg)
+        else:
+            rho0 = W.droplet_field(n, ny, R0, rl, rg, periodic_y=(bc == 0))
+        ws.append(W.Workload(f"l{k}", p, rho0))
+    return ws
+
+
+def single_state(w, store, steps):
+    s = B.Sim(w.params, f32(w.rho0), store=store)
+    s.step(steps)
+    st = s.get_state().cpu().numpy()
+    s.close()
+    return st
+
+
+@pytest.mark.parametrize("store,bc", [("f32", 0), ("f32", 1), ("f16local", 0)])
+def test_batch_is_bitwise_equal_to_single_runs(store, bc):
+    ws = mixed_lattices(bc)
+    print(f"[gpu-case] batch bitwise store={store} bc={bc} n={len(ws)}", flush=True)
+    b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws], store=store)
+    b.step(13).step(24)  # odd then even step counts across calls
+    assert b.check() == (B.LB_OK, 0)
+    for i, w in enumerate(ws):
+        p = B.make_params(w.params, store)
+        got = b.get_state(i, B.lb_state_bytes(p)).cpu().numpy()
+        assert np.array_equal(got, single_state(w, store, 37)), (store, bc, i)
+    b.close()
+
+
+def test_batch_times_and_moments():
+    ws = mixed_lattices()
+    b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws])
+    b.step(200)
+    t = np.array(b.times())
+    assert np.all(t > 0) and np.all(np.isfinite(t))
+    sizes = np.array([w.params["nx"] * w.params["ny"] for w in ws])
+    # the largest lattice cannot finish before the smallest one's whole run
+    assert t[sizes.argmax()] >= t[sizes.argmin()]
+    for i, w in enumerate(ws):
+        rho = b.moments(i)[0].cpu().numpy()
+        s = B.Sim(w.params, f32(w.rho0))
+        s.step(200)
+        assert np.array_equal(rho, s.moments()[0].cpu().numpy())
+        s.close()
+    b.close()
+
+
+def test_batch_rejects_bad_input_and_mixed_store():
+    ws = mixed_lattices()[:3]
+    bad = ws[2].rho0.copy()
+    bad[1, 1] = np.nan
+    with pytest.raises(B.LbError) as e:
+        B.Batch([w.params for w in ws], [f32(ws[0].rho0), f32(ws[1].rho0), f32(bad)])
+    assert e.value.status == B.LB_EINVAL and "lattice 2" in str(e.value)
+    params = (B.lb_params * 2)(B.make_params(ws[0].params, "f32"), B.make_params(ws[1].params, "f16local"))
+    assert B.lb_batch_workspace_bytes(params, 2) == 0
+    params = (B.lb_params * 1)(B.make_params(ws[0].params, "f16"))
+    assert B.lb_batch_workspace_bytes(params, 1) == 0
