@@ -112,9 +112,10 @@ def bench_batch(args):
     log(f"batch of {len(ws)} lattices, {sites} sites: init")
     b = lbmp.Batch([w.params for w in ws], [torch.from_numpy(np.asarray(w.rho0, np.float32)) for w in ws],
                    store=args.store)
+    b.set_launch(lbmp.LB_BATCH_PERSISTENT if args.batch_mode == "persistent" else lbmp.LB_BATCH_STEPWISE)
     b.step(args.warmup)
     b.stream.synchronize()
-    log(f"timed {args.steps} steps in one launch")
+    log(f"timed {args.steps} steps ({args.batch_mode})")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(args.steps)
@@ -122,7 +123,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     times = np.array(b.times())
-    st, n_unstable = b.check()
+    unstable = [b.diagnostics(i, 0.0, 0.0, 1.0, 2.0, raise_unstable=False)["unstable"] for i in range(len(ws))]
+    n_unstable = sum(1 for u in unstable if u)
     mlups = sites * args.steps / wall / 1e6
     bps = BYTES_PER_SITE[args.store]
     achieved = bps * sites * args.steps / wall / 1e9
@@ -134,13 +136,16 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f32" if args.store == "f32" else f"{args.store} storage, f32 compute",
         "data": "synthetic",
         "config": {"workload": f"{len(ws)} periodic droplet lattices (seed 1211), sides 64-512, "
-                               f"{sites} sites, one persistent launch", "store": args.store,
+                               f"{sites} sites", "batch_mode": args.batch_mode, "store": args.store,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "bytes_per_site": bps},
         "per_lattice_seconds": {"p50": float(np.percentile(times, 50)), "p99": float(np.percentile(times, 99)),
                                 "max": float(times.max()), "min": float(times.min())},
-        "checks": {"unstable_lattices": int(n_unstable)},
+        "checks": {"unstable_lattices": int(n_unstable),
+                   "unstable": [dict(i=i, side=ws[i].params["nx"], a=ws[i].params["a"],
+                                     t_over_tc=round(ws[i].info["t_over_tc"], 3), R0=round(ws[i].info["R0"], 1))
+                                for i in range(len(ws)) if unstable[i]]},
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -150,6 +155,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="splash", choices=["splash", "batch"])
     ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--batch-mode", default="stepwise", choices=["stepwise", "persistent"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)

@@ -178,10 +178,9 @@ lb_status lb_destroy(lb_ctx* ctx);
 
 /* ------------------------------------------------------------------------
  * Batched lattices: many independent lattices (each with its own size and
- * parameters, all sharing `store` and `bc`) advanced by one persistent launch.
- * One workgroup owns one lattice for the whole launch and runs the same
- * per-site arithmetic as lb_step, so each lattice's state is bitwise equal to
- * running it alone.  Lattices are dispatched largest first.
+ * parameters, all sharing `store` and `bc`) advanced together.  Every site runs
+ * the same arithmetic as lb_step, so each lattice's state is bitwise equal to
+ * running it alone.
  * ---------------------------------------------------------------------- */
 typedef struct lb_batch lb_batch;
 
@@ -193,13 +192,15 @@ size_t lb_batch_workspace_bytes(const lb_params* p, int32_t n);
 /* Create the batch on a caller-owned device workspace (256-byte aligned, at
  * least lb_batch_workspace_bytes) and set every lattice to its t = 0 state.
  * rho0, ux0, uy0 are host arrays of n device pointers to FP32 [ny_i][nx_i]
- * fields; ux0/uy0 (or entries of them) may be NULL.  Synchronises the stream;
+ * fields; ux0/uy0 (or entries of them) may be NULL.  The stream must not be the
+ * legacy default stream for graph capture (it then launches step by step).
+ * Synchronises the stream;
  * LB_EINVAL names the first offending lattice in lb_last_error(). */
 lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* workspace,
                         size_t workspace_bytes, const float* const* rho0, const float* const* ux0,
                         const float* const* uy0, void* stream);
 
-/* Advance every lattice by nsteps (1 launch; asynchronous). */
+/* Advance every lattice by nsteps (asynchronous). */
 lb_status lb_batch_step(lb_batch* b, int64_t nsteps);
 
 /* Per-lattice access with the semantics of lb_moments / lb_diagnostics /
@@ -214,8 +215,20 @@ lb_status lb_batch_get_state(lb_batch* b, int32_t i, void* dst);
 lb_status lb_batch_check(lb_batch* b, int32_t* unstable);
 
 /* Synchronise; seconds[i] (host array of n) = completion time of lattice i in
- * the last lb_batch_step launch, measured from the earliest workgroup start. */
+ * the last lb_batch_step call: from the earliest workgroup start (persistent
+ * mode), or the elapsed time of the whole call for every lattice (stepwise). */
 lb_status lb_batch_times(lb_batch* b, double* seconds);
+
+/* Launch mode of lb_batch_step:
+ *   LB_BATCH_STEPWISE   (default) one launch per time step over the tiles of all
+ *                       lattices together (captured in graphs); best throughput;
+ *                       lb_batch_times reports the same elapsed time for all;
+ *   LB_BATCH_PERSISTENT one launch per lb_batch_step call, one workgroup per
+ *                       lattice for all steps; per-lattice completion times.
+ * strip_rows: rows per wavefront strip (0 = the mode's default).  Synchronises
+ * the stream.  Results do not depend on either (bitwise). */
+enum { LB_BATCH_STEPWISE = 0, LB_BATCH_PERSISTENT = 1 };
+lb_status lb_batch_set_launch(lb_batch* b, int32_t mode, int32_t strip_rows);
 
 /* Release the batch and its contexts (not the caller's workspace). */
 lb_status lb_batch_destroy(lb_batch* b);

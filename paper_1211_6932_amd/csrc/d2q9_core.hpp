@@ -31,6 +31,10 @@ constexpr int kTileW = kWave - 2;     // output columns per wavefront strip
 #define LBMP_XCD_REMAP 1
 #endif
 constexpr int kWavesPerBlock = LBMP_WAVES_PER_BLOCK;  // wavefronts (strips) per workgroup
+#ifndef LBMP_BATCH_WAVES
+#define LBMP_BATCH_WAVES 16
+#endif
+constexpr int kBatchWaves = LBMP_BATCH_WAVES;  // wavefronts per workgroup (= per lattice) of a batch
 constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kDiagFields = 10;       // doubles per wave partial in the diagnostics pass
 

@@ -182,13 +182,13 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
 }
 
 // Persistent multi-instance step: one workgroup owns one lattice and advances
-// it `steps` time steps; its 16 wavefronts share the strips of each step and
+// it `steps` time steps; its kBatchWaves wavefronts share the strips of each step and
 // meet at a workgroup barrier between steps (the barrier orders the global
 // stores of step t before the loads of step t+1 for all waves of the CU).
 // Workgroups never wait for each other.  Each records the wall clock at its
 // start and end (for per-instance completion times).
 template <int S, bool WALLS>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_batch(
+__global__ __launch_bounds__(kWave * kBatchWaves) void d2q9_batch(
     const BatchInstance* __restrict__ inst, int steps, int parity,
     unsigned long long* __restrict__ clock_out)
 {
@@ -203,12 +203,37 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_batch(
     DiagConst dg{};
     for (int s = 0; s < steps; ++s) {
         const int cur = (parity + s) & 1;
-        for (int tile = wave; tile < ntiles; tile += kWavesPerBlock)
+        for (int tile = wave; tile < ntiles; tile += kBatchWaves)
             strip_tile<S, WALLS, kModeStep>(buf[cur], buf[cur ^ 1], k, tile, lane, I.flag, nullptr,
                                             nullptr, nullptr, dg, nullptr);
         __syncthreads();
     }
     if (threadIdx.x == 0) clock_out[2 * blockIdx.x + 1] = wall_clock64();
+}
+
+// Flat multi-instance step: one launch advances every lattice by one step.
+// Global tile g belongs to the lattice i with tile_start[i] <= g < tile_start[i+1];
+// wg_first[b] is the lattice of workgroup b's first tile, so each wavefront
+// finds its lattice by a short forward scan.  Launch shape as the single
+// lattice step (16 strips per workgroup, XCD-aware renumbering).
+template <int S, bool WALLS>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_batch_flat(
+    const BatchInstance* __restrict__ inst, const int* __restrict__ tile_start,
+    const int* __restrict__ wg_first, int ntotal, int parity)
+{
+    using T = typename Codec<S>::T;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int blk = logical_block(blockIdx.x, gridDim.x);
+    const int g = blk * kWavesPerBlock + wave;
+    if (g >= ntotal) return;
+    int i = wg_first[blk];
+    while (g >= tile_start[i + 1]) ++i;
+    const BatchInstance& I = inst[i];
+    const StepConst k = I.k;
+    DiagConst dg{};
+    strip_tile<S, WALLS, kModeStep>(reinterpret_cast<const T*>(I.f[parity]), reinterpret_cast<T*>(I.f[parity ^ 1]),
+                                    k, g - tile_start[i], lane, I.flag, nullptr, nullptr, nullptr, dg, nullptr);
 }
 
 // Single-block, fixed-order reduction of per-wave partials (deterministic).
@@ -371,7 +396,7 @@ hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n,
 {
     if (n <= 0) return hipSuccess;
 #define LBMP_BATCH(S_, W_)                                                                         \
-    hipLaunchKernelGGL((d2q9_batch<S_, W_>), dim3(n), dim3(kWave * kWavesPerBlock), 0, s, inst,      \
+    hipLaunchKernelGGL((d2q9_batch<S_, W_>), dim3(n), dim3(kWave * kBatchWaves), 0, s, inst,         \
                        steps, parity, clocks)
     switch (store) {
     case kStoreF32: if (walls) LBMP_BATCH(kStoreF32, true); else LBMP_BATCH(kStoreF32, false); break;
@@ -379,6 +404,23 @@ hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n,
     default: return hipErrorInvalidValue;
     }
 #undef LBMP_BATCH
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_flat(int store, bool walls, const BatchInstance* inst, const int* tile_start,
+                             const int* wg_first, int ntotal, int parity, hipStream_t s)
+{
+    if (ntotal <= 0) return hipSuccess;
+    const int blocks = (ntotal + kWavesPerBlock - 1) / kWavesPerBlock;
+#define LBMP_FLAT(S_, W_)                                                                          \
+    hipLaunchKernelGGL((d2q9_batch_flat<S_, W_>), dim3(blocks), dim3(kWave * kWavesPerBlock), 0, s, \
+                       inst, tile_start, wg_first, ntotal, parity)
+    switch (store) {
+    case kStoreF32: if (walls) LBMP_FLAT(kStoreF32, true); else LBMP_FLAT(kStoreF32, false); break;
+    case kStoreF16Local: if (walls) LBMP_FLAT(kStoreF16Local, true); else LBMP_FLAT(kStoreF16Local, false); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef LBMP_FLAT
     return hipGetLastError();
 }
 

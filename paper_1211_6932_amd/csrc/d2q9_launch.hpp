@@ -18,6 +18,12 @@ hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const
 hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n, int steps, int parity,
                         unsigned long long* clocks, hipStream_t s);
 
+// Flat batched step: one step of every lattice in one launch over the global
+// tile list (tile_start: n+1 prefix sums; wg_first: lattice of each
+// workgroup's first tile, indexed by the renumbered workgroup id).
+hipError_t launch_batch_flat(int store, bool walls, const BatchInstance* inst, const int* tile_start,
+                             const int* wg_first, int ntotal, int parity, hipStream_t s);
+
 // Resident step workgroups per compute unit (0 if the query fails).
 int step_blocks_per_cu(int store, bool walls);
 

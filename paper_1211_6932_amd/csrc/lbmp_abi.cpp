@@ -35,6 +35,8 @@ lb_status hip_fail(hipError_t e, const char* what)
 constexpr size_t kAlign = 256;
 constexpr int kDiagStripRows = 32;
 constexpr int kMinStripRows = 3;
+constexpr int kBatchPersistentRows = 24;  // measured best (one workgroup walks a whole lattice)
+constexpr int kBatchStepwiseRows = 2;     // measured best for the 512-lattice sweep
 constexpr int kDefaultBand = 1;
 constexpr int kDefaultGraphChunk = 32;
 constexpr int kMaxSide = 1 << 20;
@@ -510,6 +512,15 @@ const char* lb_last_error(void) { return g_last_error.c_str(); }
 
 struct lb_batch {
     int n;
+    int mode;                        // LB_BATCH_STEPWISE or LB_BATCH_PERSISTENT
+    int strip_rows;
+    int* tile_start;                 // device, n + 1 prefix sums of tiles (stepwise mode)
+    int* wg_first;                   // device, lattice of each workgroup's first tile
+    int ntotal;                      // total tiles of one step
+    size_t wg_capacity;              // entries available in wg_first
+    hipGraph_t graph[2];
+    hipGraphExec_t exec[2];
+    hipEvent_t ev[2];                // bracket the last lb_batch_step (stepwise mode)
     std::vector<lb_ctx*> inst;       // per-lattice contexts on slices of the workspace
     std::vector<int> order;          // dispatch position -> lattice index (largest first)
     lbmp::BatchInstance* desc;       // device descriptors in dispatch order
@@ -521,9 +532,96 @@ struct lb_batch {
 
 namespace {
 
-size_t batch_header_bytes(int n)
+// Upper bound of the workgroups of a stepwise launch (one-row strips).
+size_t batch_wg_capacity(const lb_params* p, int n)
 {
-    return align_up((size_t)n * sizeof(lbmp::BatchInstance), kAlign) + align_up((size_t)n * 16, kAlign);
+    size_t tiles = 0;
+    for (int i = 0; i < n; ++i) tiles += (size_t)((p[i].nx + lbmp::kTileW - 1) / lbmp::kTileW) * p[i].ny;
+    return (tiles + lbmp::kWavesPerBlock - 1) / lbmp::kWavesPerBlock + 1;
+}
+
+size_t batch_header_bytes(const lb_params* p, int n)
+{
+    return align_up((size_t)n * sizeof(lbmp::BatchInstance), kAlign) + align_up((size_t)n * 16, kAlign) +
+           align_up((size_t)(n + 1) * sizeof(int), kAlign) + align_up(batch_wg_capacity(p, n) * sizeof(int), kAlign);
+}
+
+int batch_default_rows(int mode) { return mode == LB_BATCH_PERSISTENT ? kBatchPersistentRows : kBatchStepwiseRows; }
+
+void drop_batch_graphs(lb_batch* b)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+        b->exec[i] = nullptr;
+        b->graph[i] = nullptr;
+    }
+}
+
+// Copy the per-lattice launch descriptors (dispatch order) and, for the
+// stepwise mode, the tile tables to the device.
+hipError_t write_batch_descriptors(lb_batch* b)
+{
+    drop_batch_graphs(b);
+    std::vector<lbmp::BatchInstance> host(b->n);
+    std::vector<int> start(b->n + 1, 0);
+    for (int j = 0; j < b->n; ++j) {
+        lb_ctx* c = b->inst[b->order[j]];
+        host[j].k = derive(c->p, b->strip_rows, 1);
+        host[j].f[0] = c->f[0];
+        host[j].f[1] = c->f[1];
+        host[j].flag = c->flag;
+        start[j + 1] = start[j] + host[j].k.tiles_x * host[j].k.tiles_y;
+    }
+    b->ntotal = start[b->n];
+    const int blocks = (b->ntotal + lbmp::kWavesPerBlock - 1) / lbmp::kWavesPerBlock;
+    if ((size_t)blocks > b->wg_capacity) return hipErrorInvalidValue;
+    std::vector<int> first(blocks);
+    for (int blk = 0, i = 0; blk < blocks; ++blk) {
+        const int g = blk * lbmp::kWavesPerBlock;
+        while (g >= start[i + 1]) ++i;
+        first[blk] = i;
+    }
+    hipError_t e = hipMemcpyAsync(b->desc, host.data(), b->n * sizeof(lbmp::BatchInstance),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->tile_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess && blocks > 0)
+        e = hipMemcpyAsync(b->wg_first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    return e;
+}
+
+hipError_t batch_flat_launch(lb_batch* b, int parity)
+{
+    return lbmp::launch_batch_flat(b->store, b->bc == LB_BC_WALLS_Y, b->desc, b->tile_start, b->wg_first,
+                                   b->ntotal, parity, b->stream);
+}
+
+lb_status build_batch_graph(lb_batch* b, int from)
+{
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < kDefaultGraphChunk && le == hipSuccess; ++i) le = batch_flat_launch(b, from ^ (i & 1));
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "batch launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph[from] = g;
+    b->exec[from] = x;
+    return LB_OK;
 }
 
 lb_status validate_batch(const lb_params* p, int32_t n)
@@ -545,7 +643,7 @@ lb_status validate_batch(const lb_params* p, int32_t n)
 size_t lb_batch_workspace_bytes(const lb_params* p, int32_t n)
 {
     if (validate_batch(p, n) != LB_OK) return 0;
-    size_t total = batch_header_bytes(n);
+    size_t total = batch_header_bytes(p, n);
     for (int i = 0; i < n; ++i) total += layout_of(p[i]).total;
     return total;
 }
@@ -570,9 +668,21 @@ lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* wor
     b->store = p[0].store;
     b->bc = p[0].bc;
     char* ws = static_cast<char*>(workspace);
-    b->desc = reinterpret_cast<lbmp::BatchInstance*>(ws);
-    b->clocks = reinterpret_cast<unsigned long long*>(ws + align_up((size_t)n * sizeof(lbmp::BatchInstance), kAlign));
-    size_t off = batch_header_bytes(n);
+    size_t hoff = 0;
+    b->desc = reinterpret_cast<lbmp::BatchInstance*>(ws + hoff);
+    hoff += align_up((size_t)n * sizeof(lbmp::BatchInstance), kAlign);
+    b->clocks = reinterpret_cast<unsigned long long*>(ws + hoff);
+    hoff += align_up((size_t)n * 16, kAlign);
+    b->tile_start = reinterpret_cast<int*>(ws + hoff);
+    hoff += align_up((size_t)(n + 1) * sizeof(int), kAlign);
+    b->wg_first = reinterpret_cast<int*>(ws + hoff);
+    b->wg_capacity = batch_wg_capacity(p, n);
+    b->mode = LB_BATCH_STEPWISE;
+    if (hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess) {
+        lb_batch_destroy(b);
+        return fail(LB_EHIP, "hipEventCreate");
+    }
+    size_t off = batch_header_bytes(p, n);
     b->inst.assign(n, nullptr);
     for (int i = 0; i < n; ++i) {
         const size_t bytes = layout_of(p[i]).total;
@@ -591,17 +701,8 @@ lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* wor
     std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
         return (long long)p[x].nx * p[x].ny > (long long)p[y].nx * p[y].ny;
     });
-    std::vector<lbmp::BatchInstance> host(n);
-    for (int j = 0; j < n; ++j) {
-        lb_ctx* c = b->inst[b->order[j]];
-        host[j].k = c->k;
-        host[j].f[0] = c->f[0];
-        host[j].f[1] = c->f[1];
-        host[j].flag = c->flag;
-    }
-    hipError_t e = hipMemcpyAsync(b->desc, host.data(), n * sizeof(lbmp::BatchInstance), hipMemcpyHostToDevice,
-                                  b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    b->strip_rows = batch_default_rows(b->mode);
+    hipError_t e = write_batch_descriptors(b);
     if (e != hipSuccess) {
         lb_batch_destroy(b);
         return hip_fail(e, "batch descriptors");
@@ -628,9 +729,31 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps)
     if (b->poisoned) return fail(LB_ESTATE, "batch poisoned by an earlier failure");
     if (nsteps < 0 || nsteps > (1LL << 30)) return fail(LB_EINVAL, "nsteps must lie in [0, 2^30]");
     if (nsteps == 0) return LB_OK;
-    const int parity = b->inst[0]->cur;
-    hipError_t e = lbmp::launch_batch(b->store, b->bc == LB_BC_WALLS_Y, b->desc, b->n, (int)nsteps, parity,
-                                      b->clocks, b->stream);
+    int parity = b->inst[0]->cur;
+    hipError_t e = hipSuccess;
+    if (b->mode == LB_BATCH_PERSISTENT) {
+        e = lbmp::launch_batch(b->store, b->bc == LB_BC_WALLS_Y, b->desc, b->n, (int)nsteps, parity, b->clocks,
+                               b->stream);
+    } else {
+        e = hipEventRecord(b->ev[0], b->stream);
+        int64_t left = nsteps;
+        while (e == hipSuccess && b->stream != nullptr && left >= kDefaultGraphChunk) {
+            if (!b->exec[parity]) {
+                lb_status st = build_batch_graph(b, parity);
+                if (st != LB_OK) {
+                    b->poisoned = true;
+                    return st;
+                }
+            }
+            e = hipGraphLaunch(b->exec[parity], b->stream);
+            left -= kDefaultGraphChunk;  // even: the parity is unchanged
+        }
+        for (; e == hipSuccess && left > 0; --left) {
+            e = batch_flat_launch(b, parity);
+            parity ^= 1;
+        }
+        if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
+    }
     if (e != hipSuccess) {
         b->poisoned = true;
         return hip_fail(e, "batch launch");
@@ -689,6 +812,14 @@ lb_status lb_batch_check(lb_batch* b, int32_t* unstable)
 lb_status lb_batch_times(lb_batch* b, double* seconds)
 {
     if (!b || !seconds) return fail(LB_EINVAL, "NULL argument");
+    if (b->mode == LB_BATCH_STEPWISE) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(b->ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev[0], b->ev[1]);
+        if (e != hipSuccess) return hip_fail(e, "batch events");
+        for (int i = 0; i < b->n; ++i) seconds[i] = ms * 1e-3;
+        return LB_OK;
+    }
     std::vector<unsigned long long> h(2 * (size_t)b->n);
     hipError_t e = hipMemcpyAsync(h.data(), b->clocks, h.size() * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, b->stream);
@@ -704,9 +835,24 @@ lb_status lb_batch_times(lb_batch* b, double* seconds)
     return LB_OK;
 }
 
+lb_status lb_batch_set_launch(lb_batch* b, int32_t mode, int32_t strip_rows)
+{
+    if (!b) return fail(LB_EINVAL, "batch is NULL");
+    if (mode != LB_BATCH_STEPWISE && mode != LB_BATCH_PERSISTENT) return fail(LB_EINVAL, "unknown batch mode");
+    if (strip_rows < 0) return fail(LB_EINVAL, "strip_rows must be >= 0");
+    b->mode = mode;
+    b->strip_rows = strip_rows ? strip_rows : batch_default_rows(mode);
+    hipError_t e = write_batch_descriptors(b);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptors");
+    return LB_OK;
+}
+
 lb_status lb_batch_destroy(lb_batch* b)
 {
     if (!b) return LB_OK;
+    drop_batch_graphs(b);
+    for (int i = 0; i < 2; ++i)
+        if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
     for (lb_ctx* c : b->inst)
         if (c) lb_destroy(c);
     delete b;

@@ -61,7 +61,8 @@ EXPORTS = [
     "lb_diagnostics", "lb_check", "lb_time", "lb_get_state", "lb_set_state", "lb_set_launch",
     "lb_destroy", "lb_last_error", "lb_copy_probe",
     "lb_batch_workspace_bytes", "lb_batch_init", "lb_batch_step", "lb_batch_moments",
-    "lb_batch_diagnostics", "lb_batch_get_state", "lb_batch_check", "lb_batch_times", "lb_batch_destroy",
+    "lb_batch_diagnostics", "lb_batch_get_state", "lb_batch_check", "lb_batch_times", "lb_batch_set_launch",
+    "lb_batch_destroy",
 ]
 
 _lib = None
@@ -126,6 +127,8 @@ def load():
     L.lb_batch_check.restype = ctypes.c_int
     L.lb_batch_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.lb_batch_times.restype = ctypes.c_int
+    L.lb_batch_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.lb_batch_set_launch.restype = ctypes.c_int
     L.lb_batch_destroy.argtypes = [vp]
     L.lb_batch_destroy.restype = ctypes.c_int
     _lib = L
@@ -256,10 +259,11 @@ def lb_batch_moments(b, i, rho_ptr, ux_ptr, uy_ptr):
                   "lb_batch_moments")
 
 
-def lb_batch_diagnostics(b, i, region_in: lb_region, region_out: lb_region) -> lb_diag:
+def lb_batch_diagnostics(b, i, region_in: lb_region, region_out: lb_region, raise_unstable=True) -> lb_diag:
     d = lb_diag()
-    _check(load().lb_batch_diagnostics(b, int(i), ctypes.byref(region_in), ctypes.byref(region_out),
-                                       ctypes.byref(d)), "lb_batch_diagnostics")
+    st = load().lb_batch_diagnostics(b, int(i), ctypes.byref(region_in), ctypes.byref(region_out), ctypes.byref(d))
+    if st != LB_OK and (raise_unstable or st != LB_EUNSTABLE):
+        raise LbError(st, "lb_batch_diagnostics")
     return d
 
 
@@ -277,6 +281,13 @@ def lb_batch_times(b, n):
     out = (ctypes.c_double * n)()
     _check(load().lb_batch_times(b, out), "lb_batch_times")
     return list(out)
+
+
+LB_BATCH_STEPWISE, LB_BATCH_PERSISTENT = 0, 1
+
+
+def lb_batch_set_launch(b, mode: int, strip_rows: int = 0):
+    return _check(load().lb_batch_set_launch(b, int(mode), int(strip_rows)), "lb_batch_set_launch")
 
 
 def lb_batch_destroy(b):
@@ -437,8 +448,17 @@ class Batch:
     def times(self):
         return lb_batch_times(self.b, self.n)
 
+    def set_launch(self, mode=0, strip_rows=0):
+        """mode: LB_BATCH_STEPWISE (0) or LB_BATCH_PERSISTENT (1)."""
+        lb_batch_set_launch(self.b, mode, strip_rows)
+
     def check(self):
         return lb_batch_check(self.b)
+
+    def diagnostics(self, i, cx, cy, r_in, r_out0, r_out1=math.inf, raise_unstable=True):
+        """Reductions of lattice i (see Sim.diagnostics)."""
+        return lb_batch_diagnostics(self.b, i, lb_region(cx, cy, 0.0, r_in), lb_region(cx, cy, r_out0, r_out1),
+                                    raise_unstable).as_dict()
 
     def moments(self, i):
         torch = self.torch

@@ -49,24 +49,32 @@ def single_state(w, store, steps):
     return st
 
 
+@pytest.mark.parametrize("mode", [B.LB_BATCH_STEPWISE, B.LB_BATCH_PERSISTENT])
 @pytest.mark.parametrize("store,bc", [("f32", 0), ("f32", 1), ("f16local", 0)])
-def test_batch_is_bitwise_equal_to_single_runs(store, bc):
+def test_batch_is_bitwise_equal_to_single_runs(store, bc, mode):
     ws = mixed_lattices(bc)
-    print(f"[gpu-case] batch bitwise store={store} bc={bc} n={len(ws)}", flush=True)
+    print(f"[gpu-case] batch bitwise store={store} bc={bc} mode={mode} n={len(ws)}", flush=True)
     b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws], store=store)
+    b.set_launch(mode)
     b.step(13).step(24)  # odd then even step counts across calls
+    b.set_launch(mode, 5)
+    b.step(34)  # crosses a captured-graph chunk in the stepwise mode
     assert b.check() == (B.LB_OK, 0)
     for i, w in enumerate(ws):
         p = B.make_params(w.params, store)
         got = b.get_state(i, B.lb_state_bytes(p)).cpu().numpy()
-        assert np.array_equal(got, single_state(w, store, 37)), (store, bc, i)
+        assert np.array_equal(got, single_state(w, store, 71)), (store, bc, mode, i)
     b.close()
 
 
 def test_batch_times_and_moments():
     ws = mixed_lattices()
     b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws])
-    b.step(200)
+    b.step(100)
+    t = np.array(b.times())  # stepwise: the elapsed time of the call, for every lattice
+    assert np.all(t > 0) and np.all(t == t[0])
+    b.set_launch(B.LB_BATCH_PERSISTENT)
+    b.step(100)
     t = np.array(b.times())
     assert np.all(t > 0) and np.all(np.isfinite(t))
     sizes = np.array([w.params["nx"] * w.params["ny"] for w in ws])
