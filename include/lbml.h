@@ -1,0 +1,105 @@
+/*
+ * lbml.h -- C ABI of the learned droplet initialiser in liblbmp.so.
+ *
+ * The paper initialises a droplet with the tanh profile of Eq. (31) between
+ * the Maxwell coexistence densities (Sec. IV.A) and lets the lattice relax to
+ * its own equilibrium: interface shape, bulk densities shifted by the
+ * droplet's Laplace pressure (Sec. IV.B) and the residual spurious currents
+ * (Sec. IV.B, Table I).  This part replaces
+ * the tanh profile by the relaxed profile predicted by a small network trained
+ * on profiles that the lattice itself produced, so that a run starts close to
+ * its equilibrium.  The tanh profile stays the fallback; the lattice run
+ * judges the prediction.
+ *
+ * Network: 4 features (a, T/T_c, R, nu_g/nu_l), standardised with a mean and
+ * standard deviation fixed at lbml_init -> 3 hidden layers of 256 units with
+ * the exact GELU, x/2 (1 + erf(x / sqrt 2)) -> 128 linear outputs
+ * y_k = log rho(r_k), r_k = R + (k - 63.5) / 2, k = 0..127 (radial samples
+ * across the interface, 64 lattice units wide).  Matrix products take bf16
+ * operands (weights, layer inputs, output and pre-activation gradients) and
+ * accumulate in FP32 on the matrix cores; master weights, biases, activations
+ * before rounding, gradients and Adam moments are FP32.  Loss: mean squared
+ * error over batch and outputs.
+ *
+ * Parameter vector (FP32, 165,760 values, in this order):
+ *   W1[256][4] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] W4[128][256] b4[128]
+ *
+ * Conventions: as in lbmp.h (lb_status results, lb_last_error(), caller-owned
+ * device buffers, asynchronous on the net's stream unless stated).
+ */
+#ifndef LBML_H
+#define LBML_H
+
+#include "lbmp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { LBML_IN = 4, LBML_HIDDEN = 256, LBML_OUT = 128, LBML_PARAMS = 165760 };
+
+typedef struct lbml_net lbml_net; /* opaque host-side handle */
+
+/* Device workspace for batches of up to max_batch samples (pure host; 0 if
+ * max_batch is not a positive multiple of 32 or exceeds 2^20). */
+size_t lbml_workspace_bytes(int32_t max_batch);
+
+/* Create a network in `workspace` (device, 256-byte aligned, at least
+ * lbml_workspace_bytes(max_batch) bytes, owned by the caller and used until
+ * lbml_destroy).  theta0: device [LBML_PARAMS] FP32 initial parameters.
+ * mu, sd: host [4] feature means and standard deviations (sd > 0).
+ * Adam moments and step counter start at zero.  Synchronises the stream. */
+lb_status lbml_init(lbml_net** out, int32_t max_batch, void* workspace, size_t workspace_bytes,
+                    const float* theta0, const double* mu, const double* sd, void* stream);
+
+/* theta: device [LBML_PARAMS] FP32.  set also refreshes the bf16 weights and
+ * keeps the Adam state. */
+lb_status lbml_set_params(lbml_net* net, const float* theta);
+lb_status lbml_get_params(lbml_net* net, float* theta);
+
+/* y (device [B][128] FP32) = network(x), x device [B][4] raw features.
+ * B: multiple of 16, at most max_batch. */
+lb_status lbml_forward(lbml_net* net, const float* x, int32_t B, float* y);
+
+/* Forward and backward over one batch: loss (device, 1 float; may be NULL) =
+ * mean squared error against target (device [B][128]); the gradient is kept
+ * in the net and copied to grad (device [LBML_PARAMS]) if grad != NULL.
+ * B: multiple of 32, at most max_batch. */
+lb_status lbml_loss_grad(lbml_net* net, const float* x, const float* target, int32_t B, float* loss,
+                         float* grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * gradient of the last lbml_loss_grad, then refresh the bf16 weights. */
+lb_status lbml_adam(lbml_net* net, float lr);
+
+/* lbml_loss_grad followed by lbml_adam. */
+lb_status lbml_train_step(lbml_net* net, const float* x, const float* target, int32_t B, float lr,
+                          float* loss);
+
+/* Release the handle (not the caller's workspace). */
+lb_status lbml_destroy(lbml_net* net);
+
+/* Radial profile of a density field (device [ny][nx] FP32, periodic):
+ * logrho[k] (device [128]) = log of the mean over 256 equally spaced angles of
+ * the bilinearly interpolated density at distance r_k from (cx, cy).
+ * Asynchronous on `stream`. */
+lb_status lbml_profile_extract(const float* rho, int32_t nx, int32_t ny, double cx, double cy, double R,
+                               float* logrho, void* stream);
+
+/* Initial density field from a radial profile (device [128]): rho0(x, y) =
+ * exp of logrho linearly interpolated at the minimum-image distance of (x, y)
+ * from (cx, cy), held at the end values outside r_0..r_127.  rho0: device
+ * [ny][nx] FP32.  Asynchronous on `stream`. */
+lb_status lbml_profile_to_rho0(const float* logrho, double R, double cx, double cy, int32_t nx, int32_t ny,
+                               float* rho0, void* stream);
+
+/* Building block, exported for tests: C[M][N] (device FP32, row stride ldc) =
+ * sum_k A(m, k) B(k, n) with bf16 device operands A(m, k) = A[m sam + k sak]
+ * and B(k, n) = B[k sbk + n sbn].  M, N multiples of 16, K a multiple of 32. */
+lb_status lbml_gemm_bf16(const void* A, int64_t sam, int64_t sak, const void* B, int64_t sbk, int64_t sbn,
+                         float* C, int32_t ldc, int32_t M, int32_t N, int32_t K, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBML_H */

@@ -210,6 +210,13 @@ lb_status lb_batch_diagnostics(lb_batch* b, int32_t i, const lb_region* in, cons
                                lb_diag* diag);
 lb_status lb_batch_get_state(lb_batch* b, int32_t i, void* dst);
 
+/* Diagnostics of every lattice in one call (one synchronisation):
+ * in[i], out[i] are the regions of lattice i, diag[i] its result (host arrays
+ * of n).  Lattices that flagged an unstable site get diag[i].unstable = 1 and
+ * keep stepping (their fields are meaningless); the call then returns
+ * LB_EUNSTABLE after filling every entry. */
+lb_status lb_batch_diagnostics_all(lb_batch* b, const lb_region* in, const lb_region* out, lb_diag* diag);
+
 /* Synchronise; *unstable (may be NULL) receives the number of lattices that
  * flagged an unstable site (LB_EUNSTABLE if any). */
 lb_status lb_batch_check(lb_batch* b, int32_t* unstable);

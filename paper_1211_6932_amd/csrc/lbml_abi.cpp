@@ -1,0 +1,310 @@
+// lbml_abi.cpp -- extern "C" entry points of the learned initialiser
+// (declared in include/lbml.h): workspace layout, forward / backward / Adam
+// sequencing of the kernels in lbml_kernels.hip, argument checks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <new>
+#include <string>
+
+#include "lbml.h"
+#include "lbml_launch.hpp"
+
+namespace lbmp {
+lb_status abi_fail(lb_status st, const std::string& msg);
+lb_status abi_hip_fail(hipError_t e, const char* what);
+}  // namespace lbmp
+
+namespace {
+
+using lbmp::abi_fail;
+using lbmp::abi_hip_fail;
+
+constexpr size_t kAlign = 256;
+constexpr int kLayers = 4;
+constexpr int kIn[kLayers] = {lbml::kIn, lbml::kHidden, lbml::kHidden, lbml::kHidden};
+constexpr int kInPadded[kLayers] = {lbml::kInPad, lbml::kHidden, lbml::kHidden, lbml::kHidden};
+constexpr int kOutN[kLayers] = {lbml::kHidden, lbml::kHidden, lbml::kHidden, lbml::kOut};
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// offsets of W_i and b_i in the flat parameter vector
+constexpr size_t w_off(int i)
+{
+    size_t o = 0;
+    for (int j = 0; j < i; ++j) o += (size_t)kOutN[j] * kIn[j] + kOutN[j];
+    return o;
+}
+constexpr size_t b_off(int i) { return w_off(i) + (size_t)kOutN[i] * kIn[i]; }
+static_assert(w_off(kLayers) == LBML_PARAMS, "parameter count");
+
+struct Layout {
+    size_t theta, m, v, grad, norm, loss, wb[kLayers], x16, z[kLayers], h[kLayers - 1], c, dz[2], total;
+};
+
+Layout layout_of(int B)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align_up(bytes);
+        return at;
+    };
+    const size_t P = LBML_PARAMS * sizeof(float);
+    L.theta = take(P);
+    L.m = take(P);
+    L.v = take(P);
+    L.grad = take(P);
+    L.norm = take(2 * lbml::kIn * sizeof(float));
+    L.loss = take(sizeof(float));
+    for (int i = 0; i < kLayers; ++i) L.wb[i] = take((size_t)kOutN[i] * kInPadded[i] * 2);
+    L.x16 = take((size_t)B * lbml::kInPad * 2);
+    for (int i = 0; i < kLayers; ++i) L.z[i] = take((size_t)B * kOutN[i] * 4);
+    for (int i = 0; i < kLayers - 1; ++i) L.h[i] = take((size_t)B * lbml::kHidden * 2);
+    // GEMM scratch: [B][256] activations or gradients, or the padded [256][32] first-layer weight gradient
+    L.c = take((size_t)B * lbml::kHidden * 4);
+    L.dz[0] = take((size_t)B * lbml::kHidden * 2);
+    L.dz[1] = take((size_t)B * lbml::kHidden * 2);
+    L.total = o;
+    return L;
+}
+
+bool batch_ok(int32_t B) { return B >= 32 && B % 32 == 0 && B <= (1 << 20); }
+
+}  // namespace
+
+struct lbml_net {
+    int max_batch = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout L{};
+    long long t = 0;  // Adam steps taken
+    bool have_grad = false;
+
+    float* f(size_t off) { return reinterpret_cast<float*>(ws + off); }
+    __bf16* h16(size_t off) { return reinterpret_cast<__bf16*>(ws + off); }
+};
+
+namespace {
+
+hipError_t refresh_bf16(lbml_net* n)
+{
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < kLayers && e == hipSuccess; ++i)
+        e = lbml::launch_to_bf16(n->f(n->L.theta) + w_off(i), n->h16(n->L.wb[i]), kOutN[i], kIn[i], kInPadded[i],
+                                 n->stream);
+    return e;
+}
+
+// Forward pass; the output layer writes y (FP32 [B][128]).
+hipError_t forward(lbml_net* n, const float* x, int B, float* y)
+{
+    hipError_t e = lbml::launch_pack_input(x, n->f(n->L.norm), n->f(n->L.norm) + lbml::kIn, n->h16(n->L.x16), B,
+                                           n->stream);
+    const __bf16* hin = n->h16(n->L.x16);
+    for (int i = 0; i < kLayers && e == hipSuccess; ++i) {
+        const int K = kInPadded[i], N = kOutN[i];
+        e = lbml::gemm(hin, K, 1, n->h16(n->L.wb[i]), 1, K, n->f(n->L.c), N, B, N, K, n->stream);
+        if (e != hipSuccess) break;
+        const bool last = i == kLayers - 1;
+        float* z = last ? y : n->f(n->L.z[i]);
+        __bf16* hout = last ? nullptr : n->h16(n->L.h[i]);
+        e = lbml::launch_bias_act(n->f(n->L.c), n->f(n->L.theta) + b_off(i), z, hout, B, N, n->stream);
+        hin = hout;
+    }
+    return e;
+}
+
+hipError_t backward(lbml_net* n, const float* target, int B, float* loss)
+{
+    float* grad = n->f(n->L.grad);
+    const float* y = n->f(n->L.z[kLayers - 1]);
+    int cur = 0;
+    hipError_t e = lbml::launch_mse_grad(y, target, n->h16(n->L.dz[cur]), loss, B, lbml::kOut, n->stream);
+    for (int i = kLayers - 1; i >= 0 && e == hipSuccess; --i) {
+        const int Kp = kInPadded[i], N = kOutN[i];
+        const __bf16* dz = n->h16(n->L.dz[cur]);
+        const __bf16* hin = i > 0 ? n->h16(n->L.h[i - 1]) : n->h16(n->L.x16);
+        // dW_i[N][Kp] = dZ^T H_in
+        float* dw = i > 0 ? grad + w_off(i) : n->f(n->L.c);
+        e = lbml::gemm(dz, 1, N, hin, Kp, 1, dw, Kp, N, Kp, B, n->stream);
+        if (e == hipSuccess && i == 0) e = lbml::launch_copy_cols(dw, Kp, grad + w_off(0), N, kIn[0], n->stream);
+        if (e == hipSuccess) e = lbml::launch_bias_grad(dz, grad + b_off(i), B, N, n->stream);
+        if (e != hipSuccess || i == 0) break;
+        // dH_{i-1}[B][Kp] = dZ W_i, then dZ_{i-1} = bf16(dH * GELU'(Z_{i-1}))
+        e = lbml::gemm(dz, N, 1, n->h16(n->L.wb[i]), Kp, 1, n->f(n->L.c), Kp, B, Kp, N, n->stream);
+        if (e == hipSuccess)
+            e = lbml::launch_gelu_back(n->f(n->L.c), n->f(n->L.z[i - 1]), n->h16(n->L.dz[cur ^ 1]), B * Kp,
+                                       n->stream);
+        cur ^= 1;
+    }
+    return e;
+}
+
+lb_status check_net(lbml_net* n, int32_t B, bool train)
+{
+    if (!n) return abi_fail(LB_EINVAL, "net is NULL");
+    if (B <= 0 || B > n->max_batch || B % (train ? 32 : 16))
+        return abi_fail(LB_EINVAL, std::string("batch must be a positive multiple of ") + (train ? "32" : "16") +
+                                       " not above max_batch");
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbml_workspace_bytes(int32_t max_batch)
+{
+    if (!batch_ok(max_batch)) return 0;
+    return layout_of(max_batch).total;
+}
+
+lb_status lbml_init(lbml_net** out, int32_t max_batch, void* workspace, size_t workspace_bytes,
+                    const float* theta0, const double* mu, const double* sd, void* stream)
+{
+    if (!out) return abi_fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!batch_ok(max_batch)) return abi_fail(LB_EINVAL, "max_batch must be a positive multiple of 32, <= 2^20");
+    if (!workspace || !theta0 || !mu || !sd) return abi_fail(LB_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return abi_fail(LB_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < lbml_workspace_bytes(max_batch))
+        return abi_fail(LB_ENOMEM, "workspace smaller than lbml_workspace_bytes");
+    float norm[2 * lbml::kIn];
+    for (int k = 0; k < lbml::kIn; ++k) {
+        if (!std::isfinite(mu[k]) || !std::isfinite(sd[k]) || !(sd[k] > 0.0))
+            return abi_fail(LB_EINVAL, "feature mean must be finite and standard deviation positive");
+        norm[k] = (float)mu[k];
+        norm[lbml::kIn + k] = (float)(1.0 / sd[k]);
+    }
+    lbml_net* n = new (std::nothrow) lbml_net{};
+    if (!n) return abi_fail(LB_ENOMEM, "host allocation failed");
+    n->max_batch = max_batch;
+    n->stream = static_cast<hipStream_t>(stream);
+    n->ws = static_cast<char*>(workspace);
+    n->L = layout_of(max_batch);
+    const size_t P = LBML_PARAMS * sizeof(float);
+    hipError_t e = hipMemcpyAsync(n->f(n->L.theta), theta0, P, hipMemcpyDeviceToDevice, n->stream);
+    if (e == hipSuccess) e = lbml::launch_fill(n->ws + n->L.m, P, n->stream);
+    if (e == hipSuccess) e = lbml::launch_fill(n->ws + n->L.v, P, n->stream);
+    if (e == hipSuccess) e = lbml::launch_fill(n->ws + n->L.grad, P, n->stream);
+    if (e == hipSuccess) e = lbml::launch_fill(n->ws + n->L.wb[0], (size_t)lbml::kHidden * lbml::kInPad * 2, n->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(n->f(n->L.norm), norm, sizeof(norm), hipMemcpyHostToDevice, n->stream);
+    if (e == hipSuccess) e = refresh_bf16(n);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    if (e != hipSuccess) {
+        delete n;
+        return abi_hip_fail(e, "lbml_init");
+    }
+    *out = n;
+    return LB_OK;
+}
+
+lb_status lbml_set_params(lbml_net* n, const float* theta)
+{
+    if (!n || !theta) return abi_fail(LB_EINVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(n->f(n->L.theta), theta, LBML_PARAMS * sizeof(float), hipMemcpyDeviceToDevice,
+                                  n->stream);
+    if (e == hipSuccess) e = refresh_bf16(n);
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_set_params");
+}
+
+lb_status lbml_get_params(lbml_net* n, float* theta)
+{
+    if (!n || !theta) return abi_fail(LB_EINVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(theta, n->f(n->L.theta), LBML_PARAMS * sizeof(float), hipMemcpyDeviceToDevice,
+                                  n->stream);
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_get_params");
+}
+
+lb_status lbml_forward(lbml_net* n, const float* x, int32_t B, float* y)
+{
+    lb_status st = check_net(n, B, false);
+    if (st != LB_OK) return st;
+    if (!x || !y) return abi_fail(LB_EINVAL, "NULL argument");
+    hipError_t e = forward(n, x, B, y);
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_forward");
+}
+
+lb_status lbml_loss_grad(lbml_net* n, const float* x, const float* target, int32_t B, float* loss, float* grad)
+{
+    lb_status st = check_net(n, B, true);
+    if (st != LB_OK) return st;
+    if (!x || !target) return abi_fail(LB_EINVAL, "NULL argument");
+    hipError_t e = forward(n, x, B, n->f(n->L.z[kLayers - 1]));
+    if (e == hipSuccess) e = backward(n, target, B, loss ? loss : n->f(n->L.loss));
+    if (e == hipSuccess && grad)
+        e = hipMemcpyAsync(grad, n->f(n->L.grad), LBML_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, n->stream);
+    if (e != hipSuccess) return abi_hip_fail(e, "lbml_loss_grad");
+    n->have_grad = true;
+    return LB_OK;
+}
+
+lb_status lbml_adam(lbml_net* n, float lr)
+{
+    if (!n) return abi_fail(LB_EINVAL, "net is NULL");
+    if (!n->have_grad) return abi_fail(LB_ESTATE, "no gradient: call lbml_loss_grad first");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return abi_fail(LB_EINVAL, "learning rate must be positive");
+    const double b1 = 0.9, b2 = 0.999;
+    const long long t = n->t + 1;
+    const float c1 = (float)(1.0 - std::pow(b1, (double)t)), c2 = (float)(1.0 - std::pow(b2, (double)t));
+    hipError_t e = lbml::launch_adam(n->f(n->L.theta), n->f(n->L.m), n->f(n->L.v), n->f(n->L.grad), LBML_PARAMS, lr,
+                                     (float)b1, (float)b2, 1e-8f, c1, c2, n->stream);
+    if (e == hipSuccess) e = refresh_bf16(n);
+    if (e != hipSuccess) return abi_hip_fail(e, "lbml_adam");
+    n->t = t;
+    return LB_OK;
+}
+
+lb_status lbml_train_step(lbml_net* n, const float* x, const float* target, int32_t B, float lr, float* loss)
+{
+    lb_status st = lbml_loss_grad(n, x, target, B, loss, nullptr);
+    return st == LB_OK ? lbml_adam(n, lr) : st;
+}
+
+lb_status lbml_destroy(lbml_net* n)
+{
+    delete n;
+    return LB_OK;
+}
+
+lb_status lbml_profile_extract(const float* rho, int32_t nx, int32_t ny, double cx, double cy, double R,
+                               float* logrho, void* stream)
+{
+    if (!rho || !logrho) return abi_fail(LB_EINVAL, "NULL argument");
+    if (nx < 2 || ny < 2 || (long long)nx * ny > (1LL << 31)) return abi_fail(LB_EINVAL, "bad lattice size");
+    if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(R) || R < 0.0 || R > 1e6)
+        return abi_fail(LB_EINVAL, "centre and radius must be finite, 0 <= R <= 1e6");
+    hipError_t e = lbml::launch_profile_extract(rho, nx, ny, cx, cy, R, logrho, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_extract");
+}
+
+lb_status lbml_profile_to_rho0(const float* logrho, double R, double cx, double cy, int32_t nx, int32_t ny,
+                               float* rho0, void* stream)
+{
+    if (!rho0 || !logrho) return abi_fail(LB_EINVAL, "NULL argument");
+    if (nx < 1 || ny < 1 || ny > 65535 || (long long)nx * ny > (1LL << 31))
+        return abi_fail(LB_EINVAL, "bad lattice size");
+    if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(R) || R < 0.0 || R > 1e6)
+        return abi_fail(LB_EINVAL, "centre and radius must be finite, 0 <= R <= 1e6");
+    hipError_t e = lbml::launch_profile_to_rho0(logrho, R, cx, cy, nx, ny, rho0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_to_rho0");
+}
+
+lb_status lbml_gemm_bf16(const void* A, int64_t sam, int64_t sak, const void* B, int64_t sbk, int64_t sbn, float* C,
+                         int32_t ldc, int32_t M, int32_t N, int32_t K, void* stream)
+{
+    if (!A || !B || !C) return abi_fail(LB_EINVAL, "NULL argument");
+    if (M <= 0 || N <= 0 || K <= 0 || M % 16 || N % 16 || K % 32)
+        return abi_fail(LB_EINVAL, "M, N must be positive multiples of 16 and K of 32");
+    if (ldc < N) return abi_fail(LB_EINVAL, "ldc < N");
+    hipError_t e = lbml::gemm(static_cast<const __bf16*>(A), sam, sak, static_cast<const __bf16*>(B), sbk, sbn, C,
+                              ldc, M, N, K, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_gemm_bf16");
+}
+
+}  // extern "C"

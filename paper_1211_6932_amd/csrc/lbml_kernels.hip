@@ -1,0 +1,289 @@
+// lbml_kernels.hip -- gfx950 kernels of the learned droplet initialiser: a
+// 4 -> 256 -> 256 -> 256 -> 128 MLP with bf16 matrix-core products (FP32
+// accumulation, FP32 master weights, Adam), plus the two profile kernels that
+// connect it to the lattice (radial log-density samples <-> density field).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbml_launch.hpp"
+
+namespace lbml {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// C[M][N] (FP32, row stride ldc) = sum_k A(m, k) B(k, n) with A(m, k) at
+// A[m * sam + k * sak] and B(k, n) at B[k * sbk + n * sbn] (bf16).  One
+// wavefront per 16 x 16 tile of C, K consumed 32 at a time by
+// v_mfma_f32_16x16x32_bf16: lane l holds row (or column) l % 16 and the eight
+// consecutive k values 8 (l / 16) .. 8 (l / 16) + 7 of each operand; the
+// accumulator holds rows 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16.
+// M, N multiples of 16 and K a multiple of 32 (checked by the launcher).
+__global__ __launch_bounds__(256) void gemm_bf16(const __bf16* __restrict__ A, long long sam,
+                                                 long long sak, const __bf16* __restrict__ B,
+                                                 long long sbk, long long sbn, float* __restrict__ C,
+                                                 int ldc, int M, int N, int K)
+{
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tiles_n = N / 16;
+    if (tile >= (M / 16) * tiles_n) return;
+    const int m0 = (tile / tiles_n) * 16, n0 = (tile % tiles_n) * 16;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            a[i] = A[(long long)(m0 + r) * sam + (long long)(k0 + kq + i) * sak];
+            b[i] = B[(long long)(k0 + kq + i) * sbk + (long long)(n0 + r) * sbn];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) C[(long long)(m0 + (lane >> 4) * 4 + i) * ldc + n0 + r] = acc[i];
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_prime(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// x [B][4] raw features -> bf16 [B][32]: standardised (x - mu) / sd, then
+// zero-padded to the matrix-core depth.
+__global__ void pack_input(const float* __restrict__ x, const float* __restrict__ mu,
+                           const float* __restrict__ inv_sd, __bf16* __restrict__ x16, int B)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * kInPad) return;
+    const int m = i / kInPad, k = i % kInPad;
+    x16[i] = static_cast<__bf16>(k < kIn ? (x[m * kIn + k] - mu[k]) * inv_sd[k] : 0.0f);
+}
+
+__global__ void fill_zero(unsigned int* __restrict__ p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Z = C + b; H = bf16(GELU(Z))  (hidden layers), or Y = C + b (output layer, H == nullptr).
+__global__ void bias_act(const float* __restrict__ C, const float* __restrict__ bias, float* __restrict__ Z,
+                         __bf16* __restrict__ H, int B, int N)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * N) return;
+    const float z = C[i] + bias[i % N];
+    Z[i] = z;
+    if (H) H[i] = static_cast<__bf16>(gelu(z));
+}
+
+// dY = bf16(2 (Y - T) / (B N)); loss = mean (Y - T)^2, one workgroup, fixed order.
+__global__ __launch_bounds__(1024) void mse_grad(const float* __restrict__ Y, const float* __restrict__ T,
+                                                 __bf16* __restrict__ dY, float* __restrict__ loss, int B, int N)
+{
+    __shared__ float part[1024];
+    const float scale = 2.0f / (float)(B * N);
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < B * N; i += 1024) {
+        const float d = Y[i] - T[i];
+        dY[i] = static_cast<__bf16>(scale * d);
+        acc += d * d;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss) loss[0] = part[0] / (float)(B * N);
+}
+
+// dZ = bf16(dH * GELU'(Z)).
+__global__ void gelu_back(const float* __restrict__ dH, const float* __restrict__ Z, __bf16* __restrict__ dZ,
+                          int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dZ[i] = static_cast<__bf16>(dH[i] * gelu_prime(Z[i]));
+}
+
+// db[n] = sum_m dZ[m][n] (sequential in m: deterministic).
+__global__ void bias_grad(const __bf16* __restrict__ dZ, float* __restrict__ db, int B, int N)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float acc = 0.0f;
+    for (int m = 0; m < B; ++m) acc += static_cast<float>(dZ[(long long)m * N + n]);
+    db[n] = acc;
+}
+
+// dst[n][k] = src[n][k] for k < cols (drops the zero padding of the first layer).
+__global__ void copy_cols(const float* __restrict__ src, int lds, float* __restrict__ dst, int rows, int cols)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < rows * cols) dst[i] = src[(i / cols) * lds + i % cols];
+}
+
+// Adam on the FP32 master parameters, then refresh the bf16 copies of the
+// weights (first-layer weights into their zero-padded rows).
+__global__ void adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                     const float* __restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
+                     float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void to_bf16(const float* __restrict__ src, __bf16* __restrict__ dst, int rows, int cols, int ldd)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < rows * cols) dst[(i / cols) * ldd + i % cols] = static_cast<__bf16>(src[i]);
+}
+
+// ---------------------------------------------------------------- profiles
+// Sample radii r_k = R + (k - 63.5) * 0.5, k = 0..127 (a 64-cell window
+// centred on the interface).
+
+// logrho[k] = log(mean over 256 angles of the bilinearly interpolated density
+// at distance r_k from (cx, cy)), periodic lattice.  One thread per sample.
+__global__ void profile_extract(const float* __restrict__ rho, int nx, int ny, double cx, double cy, double R,
+                                float* __restrict__ logrho)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kOut) return;
+    const double r = R + (k - 63.5) * 0.5;
+    double acc = 0.0;
+    for (int j = 0; j < kAngles; ++j) {
+        const double th = 2.0 * 3.14159265358979323846 * j / kAngles;
+        const double x = cx + r * cos(th), y = cy + r * sin(th);
+        const double xf = floor(x), yf = floor(y);
+        const double fx = x - xf, fy = y - yf;
+        // periodic wrap of the lower corner, then of its right / upper neighbour
+        long long xi = (long long)xf % nx, yi = (long long)yf % ny;
+        const int x0 = (int)(xi < 0 ? xi + nx : xi), y0 = (int)(yi < 0 ? yi + ny : yi);
+        const int x1 = x0 + 1 < nx ? x0 + 1 : 0, y1 = y0 + 1 < ny ? y0 + 1 : 0;
+        const double v = (1 - fx) * (1 - fy) * rho[(long long)y0 * nx + x0] + fx * (1 - fy) * rho[(long long)y0 * nx + x1] +
+                         (1 - fx) * fy * rho[(long long)y1 * nx + x0] + fx * fy * rho[(long long)y1 * nx + x1];
+        acc += v;
+    }
+    logrho[k] = (float)log(acc / kAngles);
+}
+
+// rho0(x, y) = exp(linear interpolation of logrho at the minimum-image distance
+// from (cx, cy)), held constant outside the sampled window.
+__global__ void profile_to_rho0(const float* __restrict__ logrho, double R, double cx, double cy, int nx, int ny,
+                                float* __restrict__ rho0)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= nx) return;
+    double dx = fabs(x - cx), dy = fabs(y - cy);
+    dx = fmin(dx, nx - dx);
+    dy = fmin(dy, ny - dy);
+    const double s = (sqrt(dx * dx + dy * dy) - R) * 2.0 + 63.5;  // fractional sample index
+    double v;
+    if (s <= 0.0) v = logrho[0];
+    else if (s >= kOut - 1) v = logrho[kOut - 1];
+    else {
+        const int i = (int)s;
+        const double f = s - i;
+        v = (1.0 - f) * logrho[i] + f * logrho[i + 1];
+    }
+    rho0[(long long)y * nx + x] = (float)exp(v);
+}
+
+// ---------------------------------------------------------------- launchers
+
+static unsigned grid1(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t gemm(const __bf16* A, long long sam, long long sak, const __bf16* B, long long sbk, long long sbn,
+                float* C, int ldc, int M, int N, int K, hipStream_t s)
+{
+    if (M % 16 || N % 16 || K % 32 || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
+    const long long tiles = (long long)(M / 16) * (N / 16);
+    hipLaunchKernelGGL(gemm_bf16, dim3(grid1(tiles, 4)), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N,
+                       K);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input(const float* x, const float* mu, const float* inv_sd, __bf16* x16, int B,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(pack_input, dim3(grid1((long long)B * kInPad, 256)), dim3(256), 0, s, x, mu, inv_sd, x16, B);
+    return hipGetLastError();
+}
+
+// bytes must be a multiple of 4
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_zero, dim3(grid1((long long)n, 256)), dim3(256), 0, s, static_cast<unsigned int*>(p), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bias_act(const float* C, const float* b, float* Z, __bf16* H, int B, int N, hipStream_t s)
+{
+    hipLaunchKernelGGL(bias_act, dim3(grid1((long long)B * N, 256)), dim3(256), 0, s, C, b, Z, H, B, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse_grad(const float* Y, const float* T, __bf16* dY, float* loss, int B, int N, hipStream_t s)
+{
+    hipLaunchKernelGGL(mse_grad, dim3(1), dim3(1024), 0, s, Y, T, dY, loss, B, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_gelu_back(const float* dH, const float* Z, __bf16* dZ, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(gelu_back, dim3(grid1(n, 256)), dim3(256), 0, s, dH, Z, dZ, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bias_grad(const __bf16* dZ, float* db, int B, int N, hipStream_t s)
+{
+    hipLaunchKernelGGL(bias_grad, dim3(grid1(N, 256)), dim3(256), 0, s, dZ, db, B, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(const float* src, int lds, float* dst, int rows, int cols, hipStream_t s)
+{
+    hipLaunchKernelGGL(copy_cols, dim3(grid1((long long)rows * cols, 256)), dim3(256), 0, s, src, lds, dst, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(adam, dim3(grid1(n, 256)), dim3(256), 0, s, p, m, v, g, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* src, __bf16* dst, int rows, int cols, int ldd, hipStream_t s)
+{
+    hipLaunchKernelGGL(to_bf16, dim3(grid1((long long)rows * cols, 256)), dim3(256), 0, s, src, dst, rows, cols, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_extract(const float* rho, int nx, int ny, double cx, double cy, double R, float* logrho,
+                                  hipStream_t s)
+{
+    hipLaunchKernelGGL(profile_extract, dim3(1), dim3(kOut), 0, s, rho, nx, ny, cx, cy, R, logrho);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_to_rho0(const float* logrho, double R, double cx, double cy, int nx, int ny, float* rho0,
+                                  hipStream_t s)
+{
+    hipLaunchKernelGGL(profile_to_rho0, dim3(grid1(nx, 256), ny), dim3(256), 0, s, logrho, R, cx, cy, nx, ny, rho0);
+    return hipGetLastError();
+}
+
+}  // namespace lbml

@@ -167,6 +167,13 @@ int auto_strip_rows(const lb_params& p)
 
 }  // namespace
 
+namespace lbmp {
+// Error reporting shared with the learned-initialiser entry points (the same
+// thread-local message is behind lb_last_error()).
+lb_status abi_fail(lb_status st, const std::string& msg) { return fail(st, msg); }
+lb_status abi_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace lbmp
+
 struct lb_ctx {
     lb_params p;
     Layout L;
@@ -380,26 +387,18 @@ lb_status lb_moments(lb_ctx* c, float* rho, float* ux, float* uy)
     return LB_OK;
 }
 
-lb_status lb_diagnostics(lb_ctx* c, const lb_region* in, const lb_region* outr, lb_diag* d)
+static lbmp::DiagConst diag_const(const lb_ctx* c, const lb_region* in, const lb_region* outr)
 {
-    if (!c || !in || !outr || !d) return fail(LB_EINVAL, "NULL argument");
-    if (c->poisoned) return fail(LB_ESTATE, "context poisoned by an earlier failure");
-    lbmp::DiagConst dg{in->cx, in->cy, in->r_min, in->r_max,
-                       outr->cx, outr->cy, outr->r_min, outr->r_max,
-                       c->p.b / 4.0, c->p.R * c->p.T, c->p.a,
-                       c->p.bc == LB_BC_PERIODIC ? 1 : 0};
-    hipError_t e = lbmp::launch_diag(c->p.store, c->p.bc == LB_BC_WALLS_Y, c->f[c->cur], c->kd,
-                                     c->flag, dg, c->partial, c->dout, c->stream);
-    double h[lbmp::kDiagFields];
-    int hf = 0;
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(&hf, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-        c->poisoned = true;
-        return hip_fail(e, "diagnostics");
-    }
+    return lbmp::DiagConst{in->cx, in->cy, in->r_min, in->r_max,
+                           outr->cx, outr->cy, outr->r_min, outr->r_max,
+                           c->p.b / 4.0, c->p.R * c->p.T, c->p.a,
+                           c->p.bc == LB_BC_PERIODIC ? 1 : 0};
+}
+
+// Host lb_diag from the finalised sums [mass, mom_x, mom_y, sum p_in, sum p_out,
+// sum rho_in, sum rho_out, n_in, n_out, max|u|] and the device flag word.
+static void fill_diag(const lb_ctx* c, const double* h, int hf, lb_diag* d)
+{
     std::memset(d, 0, sizeof(*d));
     d->mass = h[0];
     d->mom_x = h[1];
@@ -414,6 +413,25 @@ lb_status lb_diagnostics(lb_ctx* c, const lb_region* in, const lb_region* outr, 
     d->max_u = h[9];
     d->unstable = hf & lbmp::kFlagUnstable;
     d->step = c->t;
+}
+
+lb_status lb_diagnostics(lb_ctx* c, const lb_region* in, const lb_region* outr, lb_diag* d)
+{
+    if (!c || !in || !outr || !d) return fail(LB_EINVAL, "NULL argument");
+    if (c->poisoned) return fail(LB_ESTATE, "context poisoned by an earlier failure");
+    hipError_t e = lbmp::launch_diag(c->p.store, c->p.bc == LB_BC_WALLS_Y, c->f[c->cur], c->kd, c->flag,
+                                     diag_const(c, in, outr), c->partial, c->dout, c->stream);
+    double h[lbmp::kDiagFields];
+    int hf = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hf, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return hip_fail(e, "diagnostics");
+    }
+    fill_diag(c, h, hf, d);
     if (d->unstable) {
         c->poisoned = true;
         return fail(LB_EUNSTABLE, "unstable site (non-finite rho or psi^2 <= 0) since init");
@@ -783,6 +801,45 @@ lb_status lb_batch_diagnostics(lb_batch* b, int32_t i, const lb_region* in, cons
     lb_ctx* c = batch_member(b, i);
     if (!c) return fail(LB_EINVAL, "no such lattice");
     return lb_diagnostics(c, in, outr, d);
+}
+
+lb_status lb_batch_diagnostics_all(lb_batch* b, const lb_region* in, const lb_region* outr, lb_diag* d)
+{
+    if (!b || !in || !outr || !d) return fail(LB_EINVAL, "NULL argument");
+    if (b->poisoned) return fail(LB_ESTATE, "batch poisoned by an earlier failure");
+    const int n = b->n;
+    std::vector<double> h((size_t)n * lbmp::kDiagFields, 0.0);
+    std::vector<int> hf(n, 0);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        lb_ctx* c = b->inst[i];
+        if (!c->poisoned)
+            e = lbmp::launch_diag(c->p.store, c->p.bc == LB_BC_WALLS_Y, c->f[c->cur], c->kd, c->flag,
+                                  diag_const(c, in + i, outr + i), c->partial, c->dout, b->stream);
+    }
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        lb_ctx* c = b->inst[i];
+        if (c->poisoned) continue;
+        e = hipMemcpyAsync(&h[(size_t)i * lbmp::kDiagFields], c->dout, lbmp::kDiagFields * sizeof(double),
+                           hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hf[i], c->flag, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        b->poisoned = true;
+        return hip_fail(e, "batch diagnostics");
+    }
+    int bad = 0;
+    for (int i = 0; i < n; ++i) {
+        lb_ctx* c = b->inst[i];
+        fill_diag(c, &h[(size_t)i * lbmp::kDiagFields], hf[i], d + i);
+        if (c->poisoned || d[i].unstable) {
+            d[i].unstable = 1;
+            c->poisoned = true;
+            ++bad;
+        }
+    }
+    return bad ? fail(LB_EUNSTABLE, std::to_string(bad) + " lattice(s) flagged an unstable site") : LB_OK;
 }
 
 lb_status lb_batch_get_state(lb_batch* b, int32_t i, void* dst)

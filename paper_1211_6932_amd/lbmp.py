@@ -62,8 +62,12 @@ EXPORTS = [
     "lb_destroy", "lb_last_error", "lb_copy_probe",
     "lb_batch_workspace_bytes", "lb_batch_init", "lb_batch_step", "lb_batch_moments",
     "lb_batch_diagnostics", "lb_batch_get_state", "lb_batch_check", "lb_batch_times", "lb_batch_set_launch",
-    "lb_batch_destroy",
+    "lb_batch_destroy", "lb_batch_diagnostics_all",
+    "lbml_workspace_bytes", "lbml_init", "lbml_set_params", "lbml_get_params", "lbml_forward",
+    "lbml_loss_grad", "lbml_adam", "lbml_train_step", "lbml_destroy", "lbml_profile_extract",
+    "lbml_profile_to_rho0", "lbml_gemm_bf16",
 ]
+LBML_IN, LBML_HIDDEN, LBML_OUT, LBML_PARAMS = 4, 256, 128, 165760
 
 _lib = None
 
@@ -131,6 +135,29 @@ def load():
     L.lb_batch_set_launch.restype = ctypes.c_int
     L.lb_batch_destroy.argtypes = [vp]
     L.lb_batch_destroy.restype = ctypes.c_int
+    L.lb_batch_diagnostics_all.argtypes = [vp, ctypes.POINTER(lb_region), ctypes.POINTER(lb_region),
+                                           ctypes.POINTER(lb_diag)]
+    L.lb_batch_diagnostics_all.restype = ctypes.c_int
+    i32, i64, f32, f64, dp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.POINTER(
+        ctypes.c_double)
+    sigs = {
+        "lbml_workspace_bytes": ([i32], ctypes.c_size_t),
+        "lbml_init": ([ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, dp, dp, vp], ctypes.c_int),
+        "lbml_set_params": ([vp, vp], ctypes.c_int),
+        "lbml_get_params": ([vp, vp], ctypes.c_int),
+        "lbml_forward": ([vp, vp, i32, vp], ctypes.c_int),
+        "lbml_loss_grad": ([vp, vp, vp, i32, vp, vp], ctypes.c_int),
+        "lbml_adam": ([vp, f32], ctypes.c_int),
+        "lbml_train_step": ([vp, vp, vp, i32, f32, vp], ctypes.c_int),
+        "lbml_destroy": ([vp], ctypes.c_int),
+        "lbml_profile_extract": ([vp, i32, i32, f64, f64, f64, vp, vp], ctypes.c_int),
+        "lbml_profile_to_rho0": ([vp, f64, f64, f64, i32, i32, vp, vp], ctypes.c_int),
+        "lbml_gemm_bf16": ([vp, i64, i64, vp, i64, i64, vp, i32, i32, i32, i32, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
     _lib = L
     return L
 
@@ -267,6 +294,18 @@ def lb_batch_diagnostics(b, i, region_in: lb_region, region_out: lb_region, rais
     return d
 
 
+def lb_batch_diagnostics_all(b, regions_in, regions_out):
+    """Returns (status, list of lb_diag); status LB_EUNSTABLE still fills every entry."""
+    n = len(regions_in)
+    rin = (lb_region * n)(*regions_in)
+    rout = (lb_region * n)(*regions_out)
+    out = (lb_diag * n)()
+    st = load().lb_batch_diagnostics_all(b, rin, rout, out)
+    if st not in (LB_OK, LB_EUNSTABLE):
+        raise LbError(st, "lb_batch_diagnostics_all")
+    return st, list(out)
+
+
 def lb_batch_get_state(b, i, dst_ptr):
     return _check(load().lb_batch_get_state(b, int(i), ctypes.c_void_p(dst_ptr)), "lb_batch_get_state")
 
@@ -292,6 +331,68 @@ def lb_batch_set_launch(b, mode: int, strip_rows: int = 0):
 
 def lb_batch_destroy(b):
     return load().lb_batch_destroy(b)
+
+
+def _vp(x):
+    return ctypes.c_void_p(x or None)
+
+
+def lbml_workspace_bytes(max_batch: int) -> int:
+    return load().lbml_workspace_bytes(int(max_batch))
+
+
+def lbml_init(max_batch, workspace_ptr, workspace_bytes, theta0_ptr, mu, sd, stream):
+    net = ctypes.c_void_p()
+    mu_a = (ctypes.c_double * 4)(*[float(v) for v in mu])
+    sd_a = (ctypes.c_double * 4)(*[float(v) for v in sd])
+    _check(load().lbml_init(ctypes.byref(net), int(max_batch), _vp(workspace_ptr), int(workspace_bytes),
+                            _vp(theta0_ptr), mu_a, sd_a, _vp(stream)), "lbml_init")
+    return net
+
+
+def lbml_set_params(net, theta_ptr):
+    return _check(load().lbml_set_params(net, _vp(theta_ptr)), "lbml_set_params")
+
+
+def lbml_get_params(net, theta_ptr):
+    return _check(load().lbml_get_params(net, _vp(theta_ptr)), "lbml_get_params")
+
+
+def lbml_forward(net, x_ptr, B, y_ptr):
+    return _check(load().lbml_forward(net, _vp(x_ptr), int(B), _vp(y_ptr)), "lbml_forward")
+
+
+def lbml_loss_grad(net, x_ptr, target_ptr, B, loss_ptr, grad_ptr):
+    return _check(load().lbml_loss_grad(net, _vp(x_ptr), _vp(target_ptr), int(B), _vp(loss_ptr), _vp(grad_ptr)),
+                  "lbml_loss_grad")
+
+
+def lbml_adam(net, lr):
+    return _check(load().lbml_adam(net, float(lr)), "lbml_adam")
+
+
+def lbml_train_step(net, x_ptr, target_ptr, B, lr, loss_ptr):
+    return _check(load().lbml_train_step(net, _vp(x_ptr), _vp(target_ptr), int(B), float(lr), _vp(loss_ptr)),
+                  "lbml_train_step")
+
+
+def lbml_destroy(net):
+    return load().lbml_destroy(net)
+
+
+def lbml_profile_extract(rho_ptr, nx, ny, cx, cy, R, logrho_ptr, stream):
+    return _check(load().lbml_profile_extract(_vp(rho_ptr), int(nx), int(ny), float(cx), float(cy), float(R),
+                                              _vp(logrho_ptr), _vp(stream)), "lbml_profile_extract")
+
+
+def lbml_profile_to_rho0(logrho_ptr, R, cx, cy, nx, ny, rho0_ptr, stream):
+    return _check(load().lbml_profile_to_rho0(_vp(logrho_ptr), float(R), float(cx), float(cy), int(nx), int(ny),
+                                              _vp(rho0_ptr), _vp(stream)), "lbml_profile_to_rho0")
+
+
+def lbml_gemm_bf16(A_ptr, sam, sak, B_ptr, sbk, sbn, C_ptr, ldc, M, N, K, stream):
+    return _check(load().lbml_gemm_bf16(_vp(A_ptr), int(sam), int(sak), _vp(B_ptr), int(sbk), int(sbn), _vp(C_ptr),
+                                        int(ldc), int(M), int(N), int(K), _vp(stream)), "lbml_gemm_bf16")
 
 
 # -------------------------------------------------------------- torch convenience wrapper
@@ -460,6 +561,13 @@ class Batch:
         return lb_batch_diagnostics(self.b, i, lb_region(cx, cy, 0.0, r_in), lb_region(cx, cy, r_out0, r_out1),
                                     raise_unstable).as_dict()
 
+    def diagnostics_all(self, regions_in, regions_out):
+        """Reductions of every lattice in one call: lists of (cx, cy, r_min, r_max).
+        Returns a list of dicts (unstable lattices carry unstable = 1)."""
+        _, ds = lb_batch_diagnostics_all(self.b, [lb_region(*r) for r in regions_in],
+                                         [lb_region(*r) for r in regions_out])
+        return [d.as_dict() for d in ds]
+
     def moments(self, i):
         torch = self.torch
         out = [torch.empty(self.shapes[i], dtype=torch.float32, device=self.device) for _ in range(3)]
@@ -473,3 +581,83 @@ class Batch:
         lb_batch_get_state(self.b, i, buf.data_ptr())
         self.stream.synchronize()
         return buf
+
+
+class Net:
+    """The initialiser network on the current ROCm device (torch supplies the
+    workspace, parameters and stream).  Features: [B][4] raw (a, T/T_c, R,
+    nu_g/nu_l); outputs [B][128] log-density samples."""
+
+    def __init__(self, theta0, mu, sd, max_batch=4096, stream=None, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("lbmp.Net needs a ROCm GPU")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.max_batch = int(max_batch)
+        theta0 = torch.as_tensor(theta0).to(device=self.device, dtype=torch.float32).contiguous()
+        if theta0.numel() != LBML_PARAMS:
+            raise ValueError(f"theta0 has {theta0.numel()} values, expected {LBML_PARAMS}")
+        nbytes = lbml_workspace_bytes(self.max_batch)
+        if nbytes == 0:
+            raise ValueError("max_batch must be a positive multiple of 32")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.loss_buf = torch.zeros(1, dtype=torch.float32, device=self.device)
+        with torch.cuda.stream(self.stream):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            self.net = lbml_init(self.max_batch, self.workspace.data_ptr(), nbytes, theta0.data_ptr(), mu, sd,
+                                 self.stream.cuda_stream)
+
+    def close(self):
+        net = getattr(self, "net", None)
+        if net is not None:
+            self.net = None
+            self.stream.synchronize()
+            lbml_destroy(net)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass
+
+    def _dev(self, t, cols):
+        t = self.torch.as_tensor(t).to(device=self.device, dtype=self.torch.float32).contiguous()
+        if t.dim() != 2 or t.shape[1] != cols:
+            raise ValueError(f"expected [B][{cols}], got {tuple(t.shape)}")
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        return t
+
+    def forward(self, x):
+        x = self._dev(x, LBML_IN)
+        y = self.torch.empty((x.shape[0], LBML_OUT), dtype=self.torch.float32, device=self.device)
+        lbml_forward(self.net, x.data_ptr(), x.shape[0], y.data_ptr())
+        self.stream.synchronize()
+        return y
+
+    def loss_grad(self, x, target):
+        x, target = self._dev(x, LBML_IN), self._dev(target, LBML_OUT)
+        g = self.torch.empty(LBML_PARAMS, dtype=self.torch.float32, device=self.device)
+        lbml_loss_grad(self.net, x.data_ptr(), target.data_ptr(), x.shape[0], self.loss_buf.data_ptr(), g.data_ptr())
+        self.stream.synchronize()
+        return float(self.loss_buf.item()), g
+
+    def train_step(self, x, target, lr, sync=True):
+        """x, target: device tensors already in place (no copies when they are)."""
+        lbml_train_step(self.net, x.data_ptr(), target.data_ptr(), x.shape[0], lr, self.loss_buf.data_ptr())
+        if sync:
+            self.stream.synchronize()
+            return float(self.loss_buf.item())
+        return None
+
+    def params(self):
+        th = self.torch.empty(LBML_PARAMS, dtype=self.torch.float32, device=self.device)
+        lbml_get_params(self.net, th.data_ptr())
+        self.stream.synchronize()
+        return th
+
+    def set_params(self, theta):
+        theta = self.torch.as_tensor(theta).to(device=self.device, dtype=self.torch.float32).contiguous()
+        lbml_set_params(self.net, theta.data_ptr())
+        self.stream.synchronize()

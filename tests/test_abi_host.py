@@ -11,19 +11,22 @@ import workloads as W
 from paper_1211_6932_amd import lbmp as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbmp.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbmp.h", "lbml.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(lb\w*)\s*\(", text, flags=re.M)
+    names = []
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names += re.findall(r"^[A-Za-z_][\w\s\*]*?\b(lb\w*)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for must in ("lb_init", "lb_step", "lb_moments", "lb_diagnostics", "lb_destroy"):
+    for must in ("lb_init", "lb_step", "lb_moments", "lb_diagnostics", "lb_destroy", "lb_batch_init",
+                 "lb_batch_diagnostics_all", "lbml_init", "lbml_forward", "lbml_train_step",
+                 "lbml_profile_to_rho0"):
         assert must in names
 
 
@@ -120,3 +123,33 @@ def test_batch_workspace_sizing_is_pure_host():
     assert B.lb_batch_workspace_bytes(arr, 0) == 0
     b.bc = 1  # lattices of one batch share the boundary type
     assert B.lb_batch_workspace_bytes((B.lb_params * 2)(a, b), 2) == 0
+
+
+def test_learned_initialiser_host_checks():
+    L = B.load()
+    vp = ctypes.c_void_p
+    assert B.lbml_workspace_bytes(0) == 0 and B.lbml_workspace_bytes(48) == 0 and B.lbml_workspace_bytes(-32) == 0
+    ws = B.lbml_workspace_bytes(64)
+    assert ws > 4 * B.LBML_PARAMS * 4 and ws % 256 == 0
+    assert B.lbml_workspace_bytes(128) > ws
+    net = vp()
+    mu = (ctypes.c_double * 4)(0, 0, 0, 0)
+    sd = (ctypes.c_double * 4)(1, 1, 1, 1)
+    bad_sd = (ctypes.c_double * 4)(1, 0, 1, 1)
+    assert L.lbml_init(None, 64, vp(256), ws, vp(256), mu, sd, None) == B.LB_EINVAL
+    assert L.lbml_init(ctypes.byref(net), 48, vp(256), ws, vp(256), mu, sd, None) == B.LB_EINVAL
+    assert L.lbml_init(ctypes.byref(net), 64, vp(264), ws, vp(256), mu, sd, None) == B.LB_EINVAL
+    assert L.lbml_init(ctypes.byref(net), 64, vp(256), ws - 256, vp(256), mu, sd, None) == B.LB_ENOMEM
+    assert L.lbml_init(ctypes.byref(net), 64, vp(256), ws, vp(256), mu, bad_sd, None) == B.LB_EINVAL
+    assert L.lbml_init(ctypes.byref(net), 64, vp(256), ws, None, mu, sd, None) == B.LB_EINVAL
+    assert B.lb_last_error() != ""
+    assert L.lbml_forward(None, vp(256), 16, vp(256)) == B.LB_EINVAL
+    assert L.lbml_loss_grad(None, vp(256), vp(256), 32, None, None) == B.LB_EINVAL
+    assert L.lbml_adam(None, 1e-3) == B.LB_EINVAL
+    assert L.lbml_destroy(None) == B.LB_OK
+    assert L.lbml_gemm_bf16(vp(256), 32, 1, vp(256), 16, 1, vp(256), 16, 16, 16, 48, None) == B.LB_EINVAL
+    assert L.lbml_gemm_bf16(vp(256), 32, 1, vp(256), 16, 1, vp(256), 8, 16, 16, 32, None) == B.LB_EINVAL
+    assert L.lbml_profile_extract(vp(256), 1, 64, 0.0, 0.0, 10.0, vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_extract(vp(256), 64, 64, float("nan"), 0.0, 10.0, vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_to_rho0(vp(256), -1.0, 0.0, 0.0, 64, 64, vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_to_rho0(None, 10.0, 0.0, 0.0, 64, 64, vp(256), None) == B.LB_EINVAL

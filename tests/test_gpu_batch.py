@@ -89,6 +89,24 @@ def test_batch_times_and_moments():
     b.close()
 
 
+def test_batch_diagnostics_all_equals_per_lattice_calls():
+    print("[gpu-case] batch diagnostics_all", flush=True)
+    ws = mixed_lattices()
+    b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws])
+    b.step(57)
+    rin, rout = [], []
+    for w in ws:
+        cx, cy = (w.params["nx"] - 1) / 2, (w.params["ny"] - 1) / 2
+        rin.append((cx, cy, 0.0, 3.0))
+        rout.append((cx, cy, 0.45 * min(w.params["nx"], w.params["ny"]), float("inf")))
+    got = b.diagnostics_all(rin, rout)
+    for i in range(len(ws)):
+        one = b.diagnostics(i, rin[i][0], rin[i][1], rin[i][3], rout[i][2])
+        assert got[i] == one, i
+        assert got[i]["step"] == 57 and got[i]["unstable"] == 0
+    b.close()
+
+
 def test_batch_rejects_bad_input_and_mixed_store():
     ws = mixed_lattices()[:3]
     bad = ws[2].rho0.copy()

@@ -1,0 +1,200 @@
+"""Learned-initialiser kernels through the C ABI against the FP64 oracles
+(oracle/mlp.py with the same bf16 operand roundings, oracle/profile.py).
+
+Tolerances:
+  * matrix-core product on small integers: exact (every product and partial sum
+    is an integer below 2^24, exact in bf16 inputs and FP32 accumulation);
+  * forward outputs: relative Frobenius 2e-4 (FP32 accumulation over K <= 256 is
+    about 1e-5; a bf16 rounding that lands on the other side of a tie moves one
+    activation by 2^-8 relative, rarely);
+  * gradients, per parameter block: relative Frobenius 1e-3;
+  * Adam: FP32 arithmetic of the same update, 1e-6 lr absolute;
+  * profile kernels: FP64 geometry on FP32 data, 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp as M
+from oracle import profile as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1211_6932_amd.lbmp")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    B.load()
+    yield
+
+
+def bf16_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).cuda()
+
+
+@pytest.mark.parametrize("M_,N_,K_,a_t,b_t", [(16, 16, 32, False, False), (48, 80, 96, False, False),
+                                              (48, 80, 96, True, False), (64, 32, 256, False, True),
+                                              (32, 256, 64, True, True)])
+def test_gemm_lane_layout_exact(M_, N_, K_, a_t, b_t):
+    print(f"[gpu-case] gemm M={M_} N={N_} K={K_} a_t={a_t} b_t={b_t}", flush=True)
+    rng = np.random.default_rng(M_ + N_ + K_)
+    A = rng.integers(-8, 9, (M_, K_))
+    Bm = rng.integers(-8, 9, (K_, N_))
+    ref = (A @ Bm).astype(np.float64)
+    # operand storage: A as [M][K] or transposed [K][M]; B as [K][N] or [N][K]
+    a_dev = bf16_dev(A.T if a_t else A)
+    b_dev = bf16_dev(Bm.T if b_t else Bm)
+    sam, sak = (1, M_) if a_t else (K_, 1)
+    sbk, sbn = (1, K_) if b_t else (N_, 1)
+    ldc = N_ + 16
+    C = torch.full((M_, ldc), -7.0, dtype=torch.float32, device="cuda")
+    B.lbml_gemm_bf16(a_dev.data_ptr(), sam, sak, b_dev.data_ptr(), sbk, sbn, C.data_ptr(), ldc, M_, N_, K_, 0)
+    torch.cuda.synchronize()
+    got = C.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[:, :N_], ref)
+    assert np.all(got[:, N_:] == -7.0)  # the padding columns of C are not touched
+
+
+def features(n, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.choice([0.25, 0.5, 1.0], n), rng.uniform(0.5, 0.85, n), rng.uniform(10, 150, n),
+                     rng.uniform(1, 15, n)], axis=1)
+
+
+def standardise(X, mu, sd):
+    return (X - mu) / sd
+
+
+def theta32(seed):
+    return M.init_params(seed).astype(np.float32).astype(np.float64)
+
+
+def blocks(v):
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in M.SHAPES])
+    return [v[offs[i]:offs[i + 1]] for i in range(len(offs) - 1)]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def make_net(theta, X, max_batch=256):
+    mu, sd = X.mean(0), X.std(0) + 1e-3
+    return B.Net(torch.from_numpy(theta.astype(np.float32)), mu, sd, max_batch=max_batch), mu, sd
+
+
+@pytest.mark.parametrize("batch", [16, 48, 256])
+def test_forward_matches_oracle(batch):
+    print(f"[gpu-case] lbml forward B={batch}", flush=True)
+    th = theta32(1)
+    X = features(batch, 11)
+    net, mu, sd = make_net(th, X)
+    y = net.forward(torch.from_numpy(X.astype(np.float32))).cpu().numpy().astype(np.float64)
+    net.close()
+    ref, _ = M.forward(th, standardise(X.astype(np.float32).astype(np.float64), mu, sd), bf16=True)
+    assert rel(y, ref) < 2e-4, rel(y, ref)
+
+
+@pytest.mark.parametrize("batch", [32, 96])
+def test_gradients_match_oracle(batch):
+    print(f"[gpu-case] lbml gradients B={batch}", flush=True)
+    th = theta32(2)
+    X = features(batch, 12)
+    T = np.random.default_rng(13).normal(-2.0, 1.0, (batch, 128)).astype(np.float32).astype(np.float64)
+    net, mu, sd = make_net(th, X)
+    loss, g = net.loss_grad(torch.from_numpy(X.astype(np.float32)), torch.from_numpy(T.astype(np.float32)))
+    net.close()
+    g = g.cpu().numpy().astype(np.float64)
+    Xs = standardise(X.astype(np.float32).astype(np.float64), mu, sd)
+    loss_ref, g_ref = M.loss_and_grad(th, Xs, T, bf16=True)
+    assert abs(loss - loss_ref) <= 1e-4 * loss_ref
+    for i, (gb, rb) in enumerate(zip(blocks(g), blocks(g_ref))):
+        assert rel(gb, rb) < 1e-3, (M.SHAPES[i], rel(gb, rb))
+    # the bf16 operand rounding itself stays a small perturbation of the FP64 gradient
+    _, g64 = M.loss_and_grad(th, Xs, T, bf16=False)
+    assert rel(g, g64) < 3e-2
+
+
+def test_adam_matches_oracle():
+    print("[gpu-case] lbml adam", flush=True)
+    th = theta32(3)
+    X = features(64, 14)
+    T = np.random.default_rng(15).normal(-2.0, 1.0, (64, 128))
+    net, mu, sd = make_net(th, X)
+    _, g = net.loss_grad(torch.from_numpy(X.astype(np.float32)), torch.from_numpy(T.astype(np.float32)))
+    g = g.cpu().numpy().astype(np.float64)
+    lr = 1e-3
+    p, m, v = th.copy(), np.zeros_like(th), np.zeros_like(th)
+    for t in (1, 2, 3):  # the same stored gradient three times: exercises the bias corrections
+        B.lbml_adam(net.net, lr)
+        p, m, v = M.adam_step(p, m, v, g, t, lr)
+    got = net.params().cpu().numpy().astype(np.float64)
+    net.close()
+    assert np.abs(got - p).max() < 1e-6 * lr + 2e-7 * np.abs(p).max()
+
+
+def test_training_reduces_the_loss():
+    """Fit tanh-profile targets (Eq. (31) shape, widths by a) with the device training step."""
+    print("[gpu-case] lbml training", flush=True)
+    X = features(256, 16)
+    r = (np.arange(128) - 63.5) * 0.5
+    T = np.empty((256, 128))
+    for i, (a, tb, R, _) in enumerate(X):
+        rl, rg = W.coexistence(tb)
+        T[i] = np.log(W.tanh_profile(r, rl, rg, W=5.0 * math.sqrt(0.5 / a)))
+    th = M.init_params(4)
+    net, _, _ = make_net(th, X)
+    x = torch.from_numpy(X.astype(np.float32)).cuda()
+    t = torch.from_numpy(T.astype(np.float32)).cuda()
+    first = net.train_step(x, t, 1e-3)
+    for _ in range(400):
+        last = net.train_step(x, t, 1e-3, sync=False)
+    last = net.train_step(x, t, 1e-3)
+    net.close()
+    assert np.isfinite(last) and last < 0.02 * first, (first, last)
+
+
+def test_profile_extract_matches_oracle():
+    print("[gpu-case] lbml profile extract", flush=True)
+    nx, ny = 150, 124
+    rl, rg = W.coexistence(0.6)
+    rng = np.random.default_rng(5)
+    rho = W.droplet_field(nx, ny, 30.0, rl, rg, cx=70.3, cy=60.8) * (1 + 0.01 * rng.standard_normal((ny, nx)))
+    rho = rho.astype(np.float32)
+    out = torch.empty(128, dtype=torch.float32, device="cuda")
+    for (cx, cy, R) in [(70.3, 60.8, 30.0), (10.0, 3.5, 20.0), (149.9, 123.9, 70.0)]:  # ragged wrap cases
+        B.lbml_profile_extract(torch.from_numpy(rho).cuda().data_ptr(), nx, ny, cx, cy, R, out.data_ptr(), 0)
+        torch.cuda.synchronize()
+        ref = P.extract(rho.astype(np.float64), cx, cy, R)
+        assert np.abs(out.cpu().numpy() - ref).max() < 1e-6
+
+
+def test_profile_to_rho0_matches_oracle():
+    print("[gpu-case] lbml profile to rho0", flush=True)
+    logrho = np.linspace(-0.7, -5.0, 128) + 0.05 * np.cos(np.arange(128))
+    lr_dev = torch.from_numpy(logrho.astype(np.float32)).cuda()
+    for (nx, ny, cx, cy, R) in [(256, 256, 127.5, 127.5, 50.0), (67, 301, 10.25, 290.0, 12.0)]:
+        out = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+        B.lbml_profile_to_rho0(lr_dev.data_ptr(), R, cx, cy, nx, ny, out.data_ptr(), 0)
+        torch.cuda.synchronize()
+        ref = P.to_rho0(logrho.astype(np.float32).astype(np.float64), R, cx, cy, nx, ny)
+        assert np.abs(out.cpu().numpy() / ref - 1).max() < 1e-6
+
+
+def test_entry_points_reject_bad_batches():
+    X = features(64, 17)
+    net, _, _ = make_net(theta32(5), X, max_batch=64)
+    x = torch.zeros((64, 4), dtype=torch.float32, device="cuda")
+    y = torch.zeros((64, 128), dtype=torch.float32, device="cuda")
+    L = B.load()
+    assert L.lbml_forward(net.net, B._vp(x.data_ptr()), 8, B._vp(y.data_ptr())) == B.LB_EINVAL
+    assert L.lbml_forward(net.net, B._vp(x.data_ptr()), 80, B._vp(y.data_ptr())) == B.LB_EINVAL
+    assert L.lbml_loss_grad(net.net, B._vp(x.data_ptr()), B._vp(y.data_ptr()), 48, None, None) == B.LB_EINVAL
+    assert L.lbml_adam(net.net, 1e-3) == B.LB_ESTATE  # no gradient yet
+    net.close()
