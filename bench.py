@@ -12,10 +12,19 @@ force, MRT collision with the improved forcing, store).  The metric is MLUPS
 
     python bench.py [--steps K] [--warmup W] [--store f32|f16|bf16|f16local|bf16local] [--no-cpu-baseline]
     python bench.py --workload batch [--instances 512] [--steps 10000]
+    python bench.py --workload learned [--train-runs 4096] [--eval-droplets 256] [--relax-steps 30000]
 
 The batch workload advances 512 independent droplet lattices (seed 1211: sides 64-512,
 a in {0.25, 0.5, 1}, T/Tc in [0.5, 0.85], half of them elliptic) in one persistent launch
 and reports aggregate MLUPS and the p50 / p99 per-lattice completion times.
+
+The learned workload runs the droplet-initialiser protocol: 4096 tanh-started
+droplets on 256 x 256 lattices (seed 1212) relax for 30,000 steps; the network
+trains on their least-squares profiles on the device; 256 held-out droplets
+(seed 1213) start from tanh and from the network and run 30,000 steps together.
+The value is the median per-droplet ratio of steps to spurious-current
+convergence (tanh / learned); the strict variant (pressure jump within 1 % as
+well) and the final-state errors are reported beside it.
 """
 from __future__ import annotations
 
@@ -151,9 +160,62 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1211_6932_amd import initialiser as I
+    from paper_1211_6932_amd import lbmp
+
+    torch.cuda.set_device(0)
+    lbmp.load()
+    train_ws = W.learned_train_instances(n=args.train_runs, side_lo=256, side_hi=256)
+    sites = sum(w.params["nx"] * w.params["ny"] for w in train_ws)
+    t0 = time.perf_counter()
+    X, base, T, kept = I.generate(train_ws, args.relax_steps, every=1000, log=log)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, losses = I.train(X, base, T, steps=args.train_steps, log=log)
+    t_train = time.perf_counter() - t0
+    eval_ws = W.learned_eval_instances(n=args.eval_droplets, side=256)
+    t0 = time.perf_counter()
+    res, _ = I.evaluate(net, eval_ws, steps=args.relax_steps, every=50, log=log)
+    t_eval = time.perf_counter() - t0
+    net.close()
+    u, strict = res["summary"]["u"], res["summary"]["strict"]
+    gen_gbps = BYTES_PER_SITE["f32"] * sites * args.relax_steps / t_gen / 1e9
+    out = {
+        "metric": "steps to spurious-current convergence, tanh start / learned start (median per droplet)",
+        "value": round(u.get("median_ratio", float("nan")), 3), "unit": "x", "n_gpus": 1,
+        "steps": args.relax_steps, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network (f32 accumulate), f32 lattice",
+        "data": "synthetic",
+        "config": {"workload": f"learned droplet initialiser: {args.train_runs} training runs and "
+                               f"{args.eval_droplets} held-out droplets on 256x256, {args.relax_steps} steps",
+                   "parallelism": "single GPU"},
+        "spurious_current": u, "strict": strict,
+        "ratio_of_medians": round(u.get("ratio_of_medians", float("nan")), 3),
+        "wall_seconds": {"training_runs": round(t_gen, 2), "training": round(t_train, 2),
+                         "inference_and_placement": round(res["infer_seconds"], 3),
+                         "evaluation_runs": round(t_eval, 2)},
+        "training": {"profiles": int(X.shape[0]), "dropped_unstable": int((~kept).sum()),
+                     "final_loss": losses[-1][1], "steps": args.train_steps},
+        "roofline": {"bound": "hbm", "achieved": round(gen_gbps, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(gen_gbps / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "kernel": "batched lattice step during the training runs (72 B/site)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="splash", choices=["splash", "batch"])
+    ap.add_argument("--workload", default="splash", choices=["splash", "batch", "learned"])
+    ap.add_argument("--train-runs", type=int, default=4096)
+    ap.add_argument("--eval-droplets", type=int, default=256)
+    ap.add_argument("--relax-steps", type=int, default=30000)
+    ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--batch-mode", default="stepwise", choices=["stepwise", "persistent"])
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +234,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "learned":
+        return bench_learned(args)
 
     import numpy as np
     import torch

@@ -57,41 +57,61 @@ lb_status lbml_init(lbml_net** out, int32_t max_batch, void* workspace, size_t w
 lb_status lbml_set_params(lbml_net* net, const float* theta);
 lb_status lbml_get_params(lbml_net* net, float* theta);
 
-/* y (device [B][128] FP32) = network(x), x device [B][4] raw features.
+/* y (device [B][128] FP32) = network(x) + base, x device [B][4] raw
+ * features, base device [B][128] or NULL (zero): the network can learn a
+ * correction to a known profile, such as the tanh start of Eq. (31).
  * B: multiple of 16, at most max_batch. */
-lb_status lbml_forward(lbml_net* net, const float* x, int32_t B, float* y);
+lb_status lbml_forward(lbml_net* net, const float* x, const float* base, int32_t B, float* y);
 
 /* Forward and backward over one batch: loss (device, 1 float; may be NULL) =
- * mean squared error against target (device [B][128]); the gradient is kept
- * in the net and copied to grad (device [LBML_PARAMS]) if grad != NULL.
- * B: multiple of 32, at most max_batch. */
-lb_status lbml_loss_grad(lbml_net* net, const float* x, const float* target, int32_t B, float* loss,
-                         float* grad);
+ * mean squared error of network(x) + base against target (device [B][128]);
+ * the gradient is kept in the net and copied to grad (device [LBML_PARAMS])
+ * if grad != NULL.  B: multiple of 32, at most max_batch. */
+lb_status lbml_loss_grad(lbml_net* net, const float* x, const float* base, const float* target, int32_t B,
+                         float* loss, float* grad);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
  * gradient of the last lbml_loss_grad, then refresh the bf16 weights. */
 lb_status lbml_adam(lbml_net* net, float lr);
 
 /* lbml_loss_grad followed by lbml_adam. */
-lb_status lbml_train_step(lbml_net* net, const float* x, const float* target, int32_t B, float lr,
-                          float* loss);
+lb_status lbml_train_step(lbml_net* net, const float* x, const float* base, const float* target, int32_t B,
+                          float lr, float* loss);
 
 /* Release the handle (not the caller's workspace). */
 lb_status lbml_destroy(lbml_net* net);
 
-/* Radial profile of a density field (device [ny][nx] FP32, periodic):
- * logrho[k] (device [128]) = log of the mean over 256 equally spaced angles of
- * the bilinearly interpolated density at distance r_k from (cx, cy).
+/* Profiles.  A profile L (device [128] FP32) defines the density field
+ * rho(x, y) = exp((1 - t) L_j + t L_{j+1}), where d is the minimum-image
+ * distance of (x, y) from the centre (cx, cy), s = (d - r_0) / 0.5 clamped to
+ * [0, 127], j = min(floor(s), 126), t = s - j: linear interpolation in d,
+ * end values held inside r_0 and beyond r_127.
+ *
+ * lbml_profile_extract: the profile whose field best fits the density field
+ * rho (device [ny][nx] FP32, periodic) in least squares of log density over
+ * all sites, plus 1e-4 sum_k (L_{k+1} - L_k)^2 (a weak smoothness term that
+ * only matters where no site falls, r_k < 0).  FP64 normal equations, summed
+ * in a fixed order (bitwise reproducible), solved by tridiagonal elimination.
+ * scratch: device, 8-byte aligned, at least lbml_profile_scratch_bytes(ny).
  * Asynchronous on `stream`. */
+size_t lbml_profile_scratch_bytes(int32_t ny);
 lb_status lbml_profile_extract(const float* rho, int32_t nx, int32_t ny, double cx, double cy, double R,
-                               float* logrho, void* stream);
+                               void* scratch, size_t scratch_bytes, float* logrho, void* stream);
 
-/* Initial density field from a radial profile (device [128]): rho0(x, y) =
- * exp of logrho linearly interpolated at the minimum-image distance of (x, y)
- * from (cx, cy), held at the end values outside r_0..r_127.  rho0: device
- * [ny][nx] FP32.  Asynchronous on `stream`. */
+/* lbml_profile_to_rho0: the field of a profile, into rho0 (device [ny][nx]
+ * FP32).  Asynchronous on `stream`. */
 lb_status lbml_profile_to_rho0(const float* logrho, double R, double cx, double cy, int32_t nx, int32_t ny,
                                float* rho0, void* stream);
+
+/* lbml_profile_to_rho0_mass: the field of the profile moved outwards by the
+ * distance delta (|delta| <= 8, bisection, FP64 site sums in a fixed order) at
+ * which its total mass sum rho0 equals `mass`, for instance the mass of the
+ * tanh start of the same droplet, so that both starts relax to the same
+ * equilibrium.  shift: device, 2 doubles, receives (delta, achieved mass);
+ * delta is clamped to [-8, 8] if the mass is not reachable.  One workgroup
+ * does the search: cost ~60 passes over the lattice.  Asynchronous. */
+lb_status lbml_profile_to_rho0_mass(const float* logrho, double R, double cx, double cy, int32_t nx, int32_t ny,
+                                    double mass, double* shift, float* rho0, void* stream);
 
 /* Building block, exported for tests: C[M][N] (device FP32, row stride ldc) =
  * sum_k A(m, k) B(k, n) with bf16 device operands A(m, k) = A[m sam + k sak]

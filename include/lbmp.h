@@ -120,8 +120,10 @@ size_t lb_workspace_bytes(const lb_params* p);
  * densities for the local-density encodings.  Pure host function. */
 size_t lb_state_bytes(const lb_params* p);
 
-/* Create a context and set the state at t = 0 to f_a = [M^-1 m_eq(rho0, u0)]_a,
- * the equilibrium of Eq. (3) at every site.
+/* Create a context and set the state at t = 0 to f_a = [M^-1 m_eq(rho0, u_eq)]_a,
+ * the equilibrium of Eq. (3) at every site, taken at u_eq = u0 - F / (2 rho0)
+ * with F the Eq. (7) force of the initial density field (FP64).  u0 is thus
+ * the Eq. (6) fluid velocity: lb_moments at t = 0 returns (rho0, u0).
  *   workspace        device buffer of at least workspace_bytes (lb_workspace_bytes),
  *                    256-byte aligned, owned by the caller and used by the context
  *                    until lb_destroy.

@@ -271,45 +271,18 @@ static inline size_t IDX(const lbref_params *p, int a, int y, int x)
 
 static inline int wrap(int i, int n) { return ((i % n) + n) % n; }
 
-/* Initial state: f = M^-1 m_eq(rho0, u0) at every site (post-streaming, t = 0).
- * u0 may be NULL (zero velocity). */
-int lbref_init(const lbref_params *p, const double *rho0, const double *ux0,
-               const double *uy0, double *f)
-{
-    int st = validate(p);
-    if (st) return st;
-    ensure_minv();
-    for (int y = 0; y < p->ny; ++y)
-        for (int x = 0; x < p->nx; ++x) {
-            size_t i = (size_t)y * p->nx + x;
-            double meq[Q];
-            moment_equilibrium(rho0[i], ux0 ? ux0[i] : 0.0, uy0 ? uy0[i] : 0.0, meq);
-            for (int a = 0; a < Q; ++a) {
-                double acc = 0.0;
-                for (int k = 0; k < Q; ++k) acc += MINV[a][k] * meq[k];
-                f[IDX(p, a, y, x)] = acc;
-            }
-        }
-    return LBREF_OK;
-}
-
-/* Density, pseudopotential, force and velocity of the post-streaming state f
- * (Eqs. 6, 7, 24, 30).  Any output pointer may be NULL except rho/psi2
- * scratch, which are allocated here when NULL.  Returns LBREF_EUNSTABLE if
- * some site has a non-finite density or psi^2 <= 0. */
-static int fields(const lbref_params *p, const double *f, double *rho,
-                  double *psi, double *Fx, double *Fy, double *vx, double *vy)
+/* Eq. (30) + Eq. (24): psi at every site of a density field.  Returns
+ * LBREF_EUNSTABLE (psi set to 0 there) if some site has a non-finite density,
+ * b rho / 4 >= 1 or psi^2 <= 0. */
+static int psi_of(const lbref_params *p, const double *rho, double *psi)
 {
     const int nx = p->nx, ny = p->ny;
     int bad = 0;
-    /* Eq. (6) density, Eq. (30) + Eq. (24) pseudopotential. */
 #pragma omp parallel for reduction(| : bad)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t i = (size_t)y * nx + x;
-            double r = 0.0;
-            for (int a = 0; a < Q; ++a) r += f[IDX(p, a, y, x)];
-            rho[i] = r;
+            double r = rho[i];
             double eta = p->b * r / 4.0;
             double s2 = lbref_psi2(p, r);
             if (!isfinite(r) || !(eta < 1.0) || !(s2 > 0.0)) {
@@ -319,9 +292,14 @@ static int fields(const lbref_params *p, const double *f, double *rho,
                 psi[i] = sqrt(s2);
             }
         }
-    if (bad) return LBREF_EUNSTABLE;
-    /* Eq. (7): F = -G psi(x) sum_a w(|e_a|^2) psi(x + e_a) e_a over the eight
-     * neighbours.  Walls: psi beyond a wall equals the adjacent fluid row. */
+    return bad ? LBREF_EUNSTABLE : LBREF_OK;
+}
+
+/* Eq. (7): F = -G psi(x) sum_a w(|e_a|^2) psi(x + e_a) e_a over the eight
+ * neighbours.  Walls: psi beyond a wall equals the adjacent fluid row. */
+static void force_of(const lbref_params *p, const double *psi, double *Fx, double *Fy)
+{
+    const int nx = p->nx, ny = p->ny;
 #pragma omp parallel for
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -339,21 +317,96 @@ static int fields(const lbref_params *p, const double *f, double *rho,
                 sx += w * ps * EX[a];
                 sy += w * ps * EY[a];
             }
-            double fx = -p->G * psi[i] * sx;
-            double fy = -p->G * psi[i] * sy;
-            if (Fx) Fx[i] = fx;
-            if (Fy) Fy[i] = fy;
-            if (vx || vy) {
+            Fx[i] = -p->G * psi[i] * sx;
+            Fy[i] = -p->G * psi[i] * sy;
+        }
+}
+
+/* Initial state (post-streaming, t = 0): f = M^-1 m_eq(rho0, u_eq) at every
+ * site.  u0 (NULL = zero) is the Eq. (6) fluid velocity, so the equilibrium
+ * is taken at u_eq = u0 - F / (2 rho0) with F the Eq. (7) force of the
+ * initial density field: then sum e f + F/2 = rho0 u0 and the moments at
+ * t = 0 return (rho0, u0).  LBREF_EINVAL if rho0 gives an invalid psi. */
+int lbref_init(const lbref_params *p, const double *rho0, const double *ux0,
+               const double *uy0, double *f)
+{
+    int st = validate(p);
+    if (st) return st;
+    ensure_minv();
+    const size_t n = (size_t)p->nx * p->ny;
+    double *psi = (double *)malloc(n * sizeof(double));
+    double *Fx = (double *)malloc(n * sizeof(double));
+    double *Fy = (double *)malloc(n * sizeof(double));
+    if (!psi || !Fx || !Fy) {
+        free(psi); free(Fx); free(Fy);
+        return LBREF_ENOMEM;
+    }
+    st = psi_of(p, rho0, psi);
+    if (st) {
+        free(psi); free(Fx); free(Fy);
+        return LBREF_EINVAL;
+    }
+    force_of(p, psi, Fx, Fy);
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            size_t i = (size_t)y * p->nx + x;
+            double ux = (ux0 ? ux0[i] : 0.0) - Fx[i] / (2.0 * rho0[i]);
+            double uy = (uy0 ? uy0[i] : 0.0) - Fy[i] / (2.0 * rho0[i]);
+            double meq[Q];
+            moment_equilibrium(rho0[i], ux, uy, meq);
+            for (int a = 0; a < Q; ++a) {
+                double acc = 0.0;
+                for (int k = 0; k < Q; ++k) acc += MINV[a][k] * meq[k];
+                f[IDX(p, a, y, x)] = acc;
+            }
+        }
+    free(psi); free(Fx); free(Fy);
+    return LBREF_OK;
+}
+
+/* Density, pseudopotential, force and velocity of the post-streaming state f
+ * (Eqs. 6, 7, 24, 30).  Any output pointer may be NULL except rho/psi2
+ * scratch, which are allocated here when NULL.  Returns LBREF_EUNSTABLE if
+ * some site has a non-finite density or psi^2 <= 0. */
+static int fields(const lbref_params *p, const double *f, double *rho,
+                  double *psi, double *Fx, double *Fy, double *vx, double *vy)
+{
+    const int nx = p->nx, ny = p->ny;
+    /* Eq. (6) density */
+#pragma omp parallel for
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double r = 0.0;
+            for (int a = 0; a < Q; ++a) r += f[IDX(p, a, y, x)];
+            rho[(size_t)y * nx + x] = r;
+        }
+    if (psi_of(p, rho, psi)) return LBREF_EUNSTABLE;
+    const size_t n = (size_t)nx * ny;
+    double *fx = Fx ? Fx : (double *)malloc(n * sizeof(double));
+    double *fy = Fy ? Fy : (double *)malloc(n * sizeof(double));
+    if (!fx || !fy) {
+        if (!Fx) free(fx);
+        if (!Fy) free(fy);
+        return LBREF_ENOMEM;
+    }
+    force_of(p, psi, fx, fy);
+    if (vx || vy) {
+#pragma omp parallel for
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t i = (size_t)y * nx + x;
                 double jx = 0.0, jy = 0.0;
                 for (int a = 0; a < Q; ++a) {
                     double fa = f[IDX(p, a, y, x)];
                     jx += EX[a] * fa;
                     jy += EY[a] * fa;
                 }
-                if (vx) vx[i] = (jx + 0.5 * fx) / rho[i];
-                if (vy) vy[i] = (jy + 0.5 * fy) / rho[i];
+                if (vx) vx[i] = (jx + 0.5 * fx[i]) / rho[i];
+                if (vy) vy[i] = (jy + 0.5 * fy[i]) / rho[i];
             }
-        }
+    }
+    if (!Fx) free(fx);
+    if (!Fy) free(fy);
     return LBREF_OK;
 }
 

@@ -71,8 +71,9 @@ def init_params(seed=0):
     return np.concatenate(parts)
 
 
-def forward(theta, X, bf16=False):
-    """Returns (Y, cache).  X: [B][4] standardised inputs."""
+def forward(theta, X, bf16=False, base=None):
+    """Returns (Y, cache), Y = network(X) + base.  X: [B][4] standardised inputs;
+    base: [B][128] or None (a known profile the network corrects)."""
     r = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     layers = unpack(np.asarray(theta, dtype=np.float64))
     H = r(X)
@@ -84,16 +85,17 @@ def forward(theta, X, bf16=False):
             H = r(gelu(Z))
             cache["H"].append(H)
         else:
-            H = Z
+            H = Z if base is None else Z + np.asarray(base, dtype=np.float64)
     return H, cache
 
 
-def loss_and_grad(theta, X, T, bf16=False):
-    """MSE loss and its gradient with respect to the flat parameter vector."""
+def loss_and_grad(theta, X, T, bf16=False, base=None):
+    """MSE loss of network(X) + base against T and its gradient with respect to the
+    flat parameter vector (base does not depend on the parameters)."""
     r = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     theta = np.asarray(theta, dtype=np.float64)
     layers = unpack(theta)
-    Y, cache = forward(theta, X, bf16)
+    Y, cache = forward(theta, X, bf16, base)
     B, n_out = Y.shape
     diff = Y - T
     loss = float((diff ** 2).sum() / (B * n_out))

@@ -68,6 +68,11 @@ struct BatchInstance {
 };
 
 // Diagnostics regions (annuli) and output.
+// FP64 parameters of the initial-state kernel (Eqs. (7), (24), (30)).
+struct InitConst {
+    double b4, RT, a, G;
+};
+
 struct DiagConst {
     double in_cx, in_cy, in_r0, in_r1;
     double out_cx, out_cy, out_r0, out_r1;

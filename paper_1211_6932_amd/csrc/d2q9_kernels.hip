@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
                                                  const float* __restrict__ ux0,
                                                  const float* __restrict__ uy0,
                                                  typename Codec<S>::T* __restrict__ fout,
-                                                 StepConst k, int* __restrict__ flag)
+                                                 StepConst k, InitConst ic, int* __restrict__ flag)
 {
     using C = Codec<S>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -290,19 +290,56 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
         if (!bad) pseudopotential(r, k, bad);
         if (bad) flag[0] = kFlagBadInput;
     }
+    // psi (FP64) on the 5 x 5 block around (x, y): the force of Eq. (7) at the
+    // nine sites this one pulls from.  Rows beyond a wall take the adjacent
+    // fluid row; they are read only by sites inside the lattice.
+    double psi[5][5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        int yy = y + j - 2;
+        if (WALLS) yy = yy < 0 ? 0 : (yy >= k.ny ? k.ny - 1 : yy);
+        else yy = yy < 0 ? yy + k.ny : (yy >= k.ny ? yy - k.ny : yy);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            int xx = x + i - 2;
+            xx = xx < 0 ? xx + k.nx : (xx >= k.nx ? xx - k.nx : xx);
+            const double r = rho0[(long long)yy * k.nx + xx];
+            const double s2 = 2.0 * (p_eos_f64(r, ic.b4, ic.RT, ic.a) - r / 3.0) / ic.G;
+            psi[j][i] = s2 > 0.0 ? sqrt(s2) : 0.0;
+        }
+    }
 #pragma unroll
     for (int b = 0; b < 9; ++b) {
-        int xs = x + EX[b];
-        xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
-        int ys = y + EY[b];
+        // pre-streamed: slot b of (x, y) holds what the first pull of direction b
+        // reads, the equilibrium of the upstream site (or of this site's
+        // opposite direction at a wall)
+        int dx = EX[b], dy = EY[b];
         int a = b;
+        int ys = y + dy;
         if (ys < 0 || ys >= k.ny) {
-            if (WALLS) { xs = x; ys = y; a = OPP[b]; }
+            if (WALLS) { dx = 0; dy = 0; a = OPP[b]; }
             else ys = ys < 0 ? ys + k.ny : ys - k.ny;
         }
+        if (WALLS) ys = y + dy;
+        int xs = x + dx;
+        xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
+        // Eq. (7) at the upstream site
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int c = 1; c < 9; ++c) {
+            const double w = c < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+            const double ps = psi[2 + dy + EY[c]][2 + dx + EX[c]];
+            sx += w * ps * EX[c];
+            sy += w * ps * EY[c];
+        }
+        const double pc = psi[2 + dy][2 + dx];
+        const double Fx = -ic.G * pc * sx, Fy = -ic.G * pc * sy;
         const long long i = (long long)ys * k.nx + xs;
         const double r = rho0[i];
-        const double ux = ux0 ? ux0[i] : 0.0, uy = uy0 ? uy0[i] : 0.0;
+        // Eq. (6): the equilibrium velocity is u0 - F / (2 rho0), so that the
+        // moments at t = 0 return u0
+        const double ux = (ux0 ? ux0[i] : 0.0) - Fx / (2.0 * r);
+        const double uy = (uy0 ? uy0[i] : 0.0) - Fy / (2.0 * r);
         const double eu = EX[a] * ux + EY[a] * uy;
         const double feq = W[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
         C::store_init(fout + (long long)y * k.row_stride, k, b, (unsigned)x * (unsigned)sizeof(typename C::T),
@@ -442,12 +479,13 @@ hipError_t launch_diag(int store, bool walls, const void* fin, const StepConst& 
 }
 
 hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux0,
-                       const float* uy0, void* fout, const StepConst& k, int* flag, hipStream_t s)
+                       const float* uy0, void* fout, const StepConst& k, const InitConst& ic, int* flag,
+                       hipStream_t s)
 {
     dim3 grid((k.nx + 255) / 256, k.ny), block(256);
 #define LBMP_INIT(S_, W_)                                                                          \
     hipLaunchKernelGGL((d2q9_init<S_, W_>), grid, block, 0, s, rho0, ux0, uy0,                     \
-                       static_cast<typename Codec<S_>::T*>(fout), k, flag)
+                       static_cast<typename Codec<S_>::T*>(fout), k, ic, flag)
     switch (store) {
     case kStoreF32: if (walls) LBMP_INIT(kStoreF32, true); else LBMP_INIT(kStoreF32, false); break;
     case kStoreF16: if (walls) LBMP_INIT(kStoreF16, true); else LBMP_INIT(kStoreF16, false); break;

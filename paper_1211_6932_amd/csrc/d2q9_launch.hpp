@@ -38,7 +38,8 @@ hipError_t launch_diag(int store, bool walls, const void* fin, const StepConst& 
 
 // Equilibrium initial state into `fout`; flag[0] = kFlagBadInput on invalid input.
 hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux0,
-                       const float* uy0, void* fout, const StepConst& k, int* flag, hipStream_t s);
+                       const float* uy0, void* fout, const StepConst& k, const InitConst& ic, int* flag,
+                       hipStream_t s);
 
 // Streaming copy of n16 16-byte elements (attainable-bandwidth reference).
 hipError_t launch_copy_probe(const void* src, void* dst, long long n16, hipStream_t s);

@@ -98,8 +98,8 @@ hipError_t refresh_bf16(lbml_net* n)
     return e;
 }
 
-// Forward pass; the output layer writes y (FP32 [B][128]).
-hipError_t forward(lbml_net* n, const float* x, int B, float* y)
+// Forward pass; the output layer writes y = network(x) + base (FP32 [B][128]).
+hipError_t forward(lbml_net* n, const float* x, const float* base, int B, float* y)
 {
     hipError_t e = lbml::launch_pack_input(x, n->f(n->L.norm), n->f(n->L.norm) + lbml::kIn, n->h16(n->L.x16), B,
                                            n->stream);
@@ -111,7 +111,8 @@ hipError_t forward(lbml_net* n, const float* x, int B, float* y)
         const bool last = i == kLayers - 1;
         float* z = last ? y : n->f(n->L.z[i]);
         __bf16* hout = last ? nullptr : n->h16(n->L.h[i]);
-        e = lbml::launch_bias_act(n->f(n->L.c), n->f(n->L.theta) + b_off(i), z, hout, B, N, n->stream);
+        e = lbml::launch_bias_act(n->f(n->L.c), n->f(n->L.theta) + b_off(i), last ? base : nullptr, z, hout, B, N,
+                                  n->stream);
         hin = hout;
     }
     return e;
@@ -221,21 +222,22 @@ lb_status lbml_get_params(lbml_net* n, float* theta)
     return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_get_params");
 }
 
-lb_status lbml_forward(lbml_net* n, const float* x, int32_t B, float* y)
+lb_status lbml_forward(lbml_net* n, const float* x, const float* base, int32_t B, float* y)
 {
     lb_status st = check_net(n, B, false);
     if (st != LB_OK) return st;
     if (!x || !y) return abi_fail(LB_EINVAL, "NULL argument");
-    hipError_t e = forward(n, x, B, y);
+    hipError_t e = forward(n, x, base, B, y);
     return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_forward");
 }
 
-lb_status lbml_loss_grad(lbml_net* n, const float* x, const float* target, int32_t B, float* loss, float* grad)
+lb_status lbml_loss_grad(lbml_net* n, const float* x, const float* base, const float* target, int32_t B, float* loss,
+                         float* grad)
 {
     lb_status st = check_net(n, B, true);
     if (st != LB_OK) return st;
     if (!x || !target) return abi_fail(LB_EINVAL, "NULL argument");
-    hipError_t e = forward(n, x, B, n->f(n->L.z[kLayers - 1]));
+    hipError_t e = forward(n, x, base, B, n->f(n->L.z[kLayers - 1]));
     if (e == hipSuccess) e = backward(n, target, B, loss ? loss : n->f(n->L.loss));
     if (e == hipSuccess && grad)
         e = hipMemcpyAsync(grad, n->f(n->L.grad), LBML_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, n->stream);
@@ -260,9 +262,10 @@ lb_status lbml_adam(lbml_net* n, float lr)
     return LB_OK;
 }
 
-lb_status lbml_train_step(lbml_net* n, const float* x, const float* target, int32_t B, float lr, float* loss)
+lb_status lbml_train_step(lbml_net* n, const float* x, const float* base, const float* target, int32_t B, float lr,
+                          float* loss)
 {
-    lb_status st = lbml_loss_grad(n, x, target, B, loss, nullptr);
+    lb_status st = lbml_loss_grad(n, x, base, target, B, loss, nullptr);
     return st == LB_OK ? lbml_adam(n, lr) : st;
 }
 
@@ -272,14 +275,25 @@ lb_status lbml_destroy(lbml_net* n)
     return LB_OK;
 }
 
-lb_status lbml_profile_extract(const float* rho, int32_t nx, int32_t ny, double cx, double cy, double R,
-                               float* logrho, void* stream)
+size_t lbml_profile_scratch_bytes(int32_t ny)
 {
-    if (!rho || !logrho) return abi_fail(LB_EINVAL, "NULL argument");
-    if (nx < 2 || ny < 2 || (long long)nx * ny > (1LL << 31)) return abi_fail(LB_EINVAL, "bad lattice size");
+    if (ny < 2 || ny > (1 << 20)) return 0;
+    return (size_t)3 * ny * lbml::kOut * sizeof(double);
+}
+
+lb_status lbml_profile_extract(const float* rho, int32_t nx, int32_t ny, double cx, double cy, double R,
+                               void* scratch, size_t scratch_bytes, float* logrho, void* stream)
+{
+    if (!rho || !logrho || !scratch) return abi_fail(LB_EINVAL, "NULL argument");
+    if (nx < 2 || ny < 2 || nx > (1 << 20) || ny > (1 << 20) || (long long)nx * ny > (1LL << 31))
+        return abi_fail(LB_EINVAL, "bad lattice size");
     if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(R) || R < 0.0 || R > 1e6)
         return abi_fail(LB_EINVAL, "centre and radius must be finite, 0 <= R <= 1e6");
-    hipError_t e = lbml::launch_profile_extract(rho, nx, ny, cx, cy, R, logrho, static_cast<hipStream_t>(stream));
+    if (reinterpret_cast<uintptr_t>(scratch) % 8) return abi_fail(LB_EINVAL, "scratch must be 8-byte aligned");
+    if (scratch_bytes < lbml_profile_scratch_bytes(ny))
+        return abi_fail(LB_ENOMEM, "scratch smaller than lbml_profile_scratch_bytes(ny)");
+    hipError_t e = lbml::launch_profile_extract(rho, nx, ny, cx, cy, R, static_cast<double*>(scratch), logrho,
+                                                static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_extract");
 }
 
@@ -293,6 +307,21 @@ lb_status lbml_profile_to_rho0(const float* logrho, double R, double cx, double 
         return abi_fail(LB_EINVAL, "centre and radius must be finite, 0 <= R <= 1e6");
     hipError_t e = lbml::launch_profile_to_rho0(logrho, R, cx, cy, nx, ny, rho0, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_to_rho0");
+}
+
+lb_status lbml_profile_to_rho0_mass(const float* logrho, double R, double cx, double cy, int32_t nx, int32_t ny,
+                                    double mass, double* shift, float* rho0, void* stream)
+{
+    if (!rho0 || !logrho || !shift) return abi_fail(LB_EINVAL, "NULL argument");
+    if (nx < 1 || ny < 1 || ny > 65535 || (long long)nx * ny > (1LL << 31))
+        return abi_fail(LB_EINVAL, "bad lattice size");
+    if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(R) || R < 0.0 || R > 1e6)
+        return abi_fail(LB_EINVAL, "centre and radius must be finite, 0 <= R <= 1e6");
+    if (!std::isfinite(mass) || !(mass > 0.0)) return abi_fail(LB_EINVAL, "mass must be positive and finite");
+    if (reinterpret_cast<uintptr_t>(shift) % 8) return abi_fail(LB_EINVAL, "shift must be 8-byte aligned");
+    hipError_t e = lbml::launch_profile_to_rho0_mass(logrho, R, cx, cy, nx, ny, mass, shift, rho0,
+                                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_to_rho0_mass");
 }
 
 lb_status lbml_gemm_bf16(const void* A, int64_t sam, int64_t sak, const void* B, int64_t sbk, int64_t sbn, float* C,

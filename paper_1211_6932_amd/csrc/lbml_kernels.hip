@@ -68,13 +68,15 @@ __global__ void fill_zero(unsigned int* __restrict__ p, size_t n)
     if (i < n) p[i] = 0u;
 }
 
-// Z = C + b; H = bf16(GELU(Z))  (hidden layers), or Y = C + b (output layer, H == nullptr).
-__global__ void bias_act(const float* __restrict__ C, const float* __restrict__ bias, float* __restrict__ Z,
-                         __bf16* __restrict__ H, int B, int N)
+// Z = C + b; H = bf16(GELU(Z)) (hidden layers), or Y = C + b + base (output
+// layer: H == nullptr; base [B][N] may be nullptr).
+__global__ void bias_act(const float* __restrict__ C, const float* __restrict__ bias,
+                         const float* __restrict__ base, float* __restrict__ Z, __bf16* __restrict__ H, int B, int N)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B * N) return;
-    const float z = C[i] + bias[i % N];
+    float z = C[i] + bias[i % N];
+    if (base) z += base[i];
     Z[i] = z;
     if (H) H[i] = static_cast<__bf16>(gelu(z));
 }
@@ -148,55 +150,166 @@ __global__ void to_bf16(const float* __restrict__ src, __bf16* __restrict__ dst,
 }
 
 // ---------------------------------------------------------------- profiles
-// Sample radii r_k = R + (k - 63.5) * 0.5, k = 0..127 (a 64-cell window
-// centred on the interface).
+// Sample radii r_k = R + (k - 63.5) / 2, k = 0..127 (a 64-cell window centred
+// on the interface).  A profile L (log densities at r_k) defines the field
+// log rho0(d) = (1 - t) L_j + t L_{j+1} with s = (d - r_0) / 0.5 clamped to
+// [0, 127], j = min(floor(s), 126), t = s - j, d the minimum-image distance.
 
-// logrho[k] = log(mean over 256 angles of the bilinearly interpolated density
-// at distance r_k from (cx, cy)), periodic lattice.  One thread per sample.
-__global__ void profile_extract(const float* __restrict__ rho, int nx, int ny, double cx, double cy, double R,
-                                float* __restrict__ logrho)
+__device__ __forceinline__ double min_image(double d, int n)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= kOut) return;
-    const double r = R + (k - 63.5) * 0.5;
-    double acc = 0.0;
-    for (int j = 0; j < kAngles; ++j) {
-        const double th = 2.0 * 3.14159265358979323846 * j / kAngles;
-        const double x = cx + r * cos(th), y = cy + r * sin(th);
-        const double xf = floor(x), yf = floor(y);
-        const double fx = x - xf, fy = y - yf;
-        // periodic wrap of the lower corner, then of its right / upper neighbour
-        long long xi = (long long)xf % nx, yi = (long long)yf % ny;
-        const int x0 = (int)(xi < 0 ? xi + nx : xi), y0 = (int)(yi < 0 ? yi + ny : yi);
-        const int x1 = x0 + 1 < nx ? x0 + 1 : 0, y1 = y0 + 1 < ny ? y0 + 1 : 0;
-        const double v = (1 - fx) * (1 - fy) * rho[(long long)y0 * nx + x0] + fx * (1 - fy) * rho[(long long)y0 * nx + x1] +
-                         (1 - fx) * fy * rho[(long long)y1 * nx + x0] + fx * fy * rho[(long long)y1 * nx + x1];
-        acc += v;
-    }
-    logrho[k] = (float)log(acc / kAngles);
+    d = fabs(d);
+    return fmin(d, n - d);
 }
 
-// rho0(x, y) = exp(linear interpolation of logrho at the minimum-image distance
-// from (cx, cy)), held constant outside the sampled window.
-__global__ void profile_to_rho0(const float* __restrict__ logrho, double R, double cx, double cy, int nx, int ny,
-                                float* __restrict__ rho0)
+// Hat coordinates (j, t) of distance d.
+__device__ __forceinline__ void hat_of(double d, double r0, int& j, double& t)
+{
+    double s = (d - r0) * 2.0;
+    s = fmin(fmax(s, 0.0), (double)(kOut - 1));
+    j = min((int)s, kOut - 2);
+    t = s - j;
+}
+
+// Least-squares fit, stage 1: row y's contributions to the normal equations
+// (H^T H) L = H^T log rho.  Thread k accumulates, in x order, the diagonal
+// (k, k), the upper off-diagonal (k, k+1) and the right-hand side of sample k
+// over the sites of the row.  part: [3][ny][128] doubles.
+__global__ __launch_bounds__(kOut) void profile_rows(const float* __restrict__ rho, int nx, int ny, double cx,
+                                                     double cy, double r0, double* __restrict__ part)
+{
+    const int k = threadIdx.x;
+    const int y = blockIdx.x;
+    const double dy = min_image(y - cy, ny);
+    const float* row = rho + (long long)y * nx;
+    double a = 0.0, e = 0.0, b = 0.0;
+    for (int x = 0; x < nx; ++x) {
+        const double dx = min_image(x - cx, nx);
+        int j;
+        double t;
+        hat_of(sqrt(dx * dx + dy * dy), r0, j, t);
+        if (j == k) {
+            const double v = log((double)row[x]);
+            a += (1.0 - t) * (1.0 - t);
+            e += (1.0 - t) * t;
+            b += (1.0 - t) * v;
+        } else if (j + 1 == k) {
+            const double v = log((double)row[x]);
+            a += t * t;
+            b += t * v;
+        }
+    }
+    const long long plane = (long long)ny * kOut;
+    part[(long long)y * kOut + k] = a;
+    part[plane + (long long)y * kOut + k] = e;
+    part[2 * plane + (long long)y * kOut + k] = b;
+}
+
+// Stage 2 (one workgroup): sum the rows in order, add lam * (graph Laplacian
+// of the sample path), solve the symmetric positive-definite tridiagonal
+// system (Thomas algorithm, FP64) and write L as FP32.
+__global__ __launch_bounds__(kOut) void profile_solve(const double* __restrict__ part, int ny,
+                                                      float* __restrict__ logrho)
+{
+    __shared__ double A[kOut], E[kOut], Bv[kOut], Cp[kOut], Dp[kOut];
+    const int k = threadIdx.x;
+    const long long plane = (long long)ny * kOut;
+    double a = 0.0, e = 0.0, b = 0.0;
+    for (int y = 0; y < ny; ++y) {
+        a += part[(long long)y * kOut + k];
+        e += part[plane + (long long)y * kOut + k];
+        b += part[2 * plane + (long long)y * kOut + k];
+    }
+    if (k > 0) a += kSmooth;
+    if (k < kOut - 1) {
+        a += kSmooth;
+        e -= kSmooth;
+    }
+    A[k] = a;
+    E[k] = e;  // coupling of samples k and k + 1 (unused for k = 127)
+    Bv[k] = b;
+    __syncthreads();
+    if (k == 0) {
+        Cp[0] = E[0] / A[0];
+        Dp[0] = Bv[0] / A[0];
+        for (int i = 1; i < kOut; ++i) {
+            const double m = A[i] - E[i - 1] * Cp[i - 1];
+            Cp[i] = i < kOut - 1 ? E[i] / m : 0.0;
+            Dp[i] = (Bv[i] - E[i - 1] * Dp[i - 1]) / m;
+        }
+        for (int i = kOut - 2; i >= 0; --i) Dp[i] -= Cp[i] * Dp[i + 1];
+    }
+    __syncthreads();
+    logrho[k] = (float)Dp[k];
+}
+
+// rho0(x, y) = exp((1 - t) L_j + t L_{j+1}) at the minimum-image distance of
+// (x, y) from (cx, cy); the sample radii are moved outwards by shift[0] when
+// shift is not NULL.
+__global__ void profile_to_rho0(const float* __restrict__ logrho, double r0, const double* __restrict__ shift,
+                                double cx, double cy, int nx, int ny, float* __restrict__ rho0)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= nx) return;
-    double dx = fabs(x - cx), dy = fabs(y - cy);
-    dx = fmin(dx, nx - dx);
-    dy = fmin(dy, ny - dy);
-    const double s = (sqrt(dx * dx + dy * dy) - R) * 2.0 + 63.5;  // fractional sample index
-    double v;
-    if (s <= 0.0) v = logrho[0];
-    else if (s >= kOut - 1) v = logrho[kOut - 1];
-    else {
-        const int i = (int)s;
-        const double f = s - i;
-        v = (1.0 - f) * logrho[i] + f * logrho[i + 1];
+    const double dx = min_image(x - cx, nx), dy = min_image(y - cy, ny);
+    int j;
+    double t;
+    hat_of(sqrt(dx * dx + dy * dy), r0 + (shift ? shift[0] : 0.0), j, t);
+    rho0[(long long)y * nx + x] = (float)exp((1.0 - t) * logrho[j] + t * logrho[j + 1]);
+}
+
+constexpr int kMassThreads = 1024;
+constexpr int kMassIters = 60;
+constexpr double kMaxShift = 8.0;
+
+// Bisection for the outward shift delta in [-8, 8] at which the profile's field
+// has total mass `mass` (the mass grows with delta for a profile that falls
+// outwards).  One workgroup; FP64 site sums reduced in a fixed tree order.
+// out[0] = delta, out[1] = the field's mass at delta.
+__global__ __launch_bounds__(kMassThreads) void profile_mass_shift(const float* __restrict__ logrho, double r0,
+                                                                   double cx, double cy, int nx, int ny,
+                                                                   double mass, double* __restrict__ out)
+{
+    __shared__ float L[kOut];
+    __shared__ double part[kMassThreads];
+    __shared__ double lohi[2];
+    const int tid = threadIdx.x;
+    if (tid < kOut) L[tid] = logrho[tid];
+    if (tid == 0) {
+        lohi[0] = -kMaxShift;
+        lohi[1] = kMaxShift;
     }
-    rho0[(long long)y * nx + x] = (float)exp(v);
+    __syncthreads();
+    const long long n = (long long)nx * ny;
+    double m = 0.0;
+    for (int it = 0; it <= kMassIters; ++it) {
+        const double delta = 0.5 * (lohi[0] + lohi[1]);
+        double acc = 0.0;
+        for (long long i = tid; i < n; i += kMassThreads) {
+            const int x = (int)(i % nx), y = (int)(i / nx);
+            const double dx = min_image(x - cx, nx), dy = min_image(y - cy, ny);
+            int j;
+            double t;
+            hat_of(sqrt(dx * dx + dy * dy), r0 + delta, j, t);
+            acc += exp((1.0 - t) * (double)L[j] + t * (double)L[j + 1]);
+        }
+        part[tid] = acc;
+        __syncthreads();
+        for (int s = kMassThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) part[tid] += part[tid + s];
+            __syncthreads();
+        }
+        m = part[0];
+        if (tid == 0 && it < kMassIters) {
+            if (m < mass) lohi[0] = delta;
+            else lohi[1] = delta;
+        }
+        __syncthreads();
+        if (it == kMassIters && tid == 0) {
+            out[0] = delta;
+            out[1] = m;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -229,9 +342,10 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_bias_act(const float* C, const float* b, float* Z, __bf16* H, int B, int N, hipStream_t s)
+hipError_t launch_bias_act(const float* C, const float* b, const float* base, float* Z, __bf16* H, int B, int N,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(bias_act, dim3(grid1((long long)B * N, 256)), dim3(256), 0, s, C, b, Z, H, B, N);
+    hipLaunchKernelGGL(bias_act, dim3(grid1((long long)B * N, 256)), dim3(256), 0, s, C, b, base, Z, H, B, N);
     return hipGetLastError();
 }
 
@@ -272,17 +386,35 @@ hipError_t launch_to_bf16(const float* src, __bf16* dst, int rows, int cols, int
     return hipGetLastError();
 }
 
-hipError_t launch_profile_extract(const float* rho, int nx, int ny, double cx, double cy, double R, float* logrho,
-                                  hipStream_t s)
+hipError_t launch_profile_extract(const float* rho, int nx, int ny, double cx, double cy, double R, double* part,
+                                  float* logrho, hipStream_t s)
 {
-    hipLaunchKernelGGL(profile_extract, dim3(1), dim3(kOut), 0, s, rho, nx, ny, cx, cy, R, logrho);
+    const double r0 = R - 0.25 * (kOut - 1);
+    hipLaunchKernelGGL(profile_rows, dim3(ny), dim3(kOut), 0, s, rho, nx, ny, cx, cy, r0, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(profile_solve, dim3(1), dim3(kOut), 0, s, part, ny, logrho);
     return hipGetLastError();
 }
 
 hipError_t launch_profile_to_rho0(const float* logrho, double R, double cx, double cy, int nx, int ny, float* rho0,
                                   hipStream_t s)
 {
-    hipLaunchKernelGGL(profile_to_rho0, dim3(grid1(nx, 256), ny), dim3(256), 0, s, logrho, R, cx, cy, nx, ny, rho0);
+    const double r0 = R - 0.25 * (kOut - 1);
+    hipLaunchKernelGGL(profile_to_rho0, dim3(grid1(nx, 256), ny), dim3(256), 0, s, logrho, r0,
+                       static_cast<const double*>(nullptr), cx, cy, nx, ny, rho0);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_to_rho0_mass(const float* logrho, double R, double cx, double cy, int nx, int ny,
+                                       double mass, double* shift, float* rho0, hipStream_t s)
+{
+    const double r0 = R - 0.25 * (kOut - 1);
+    hipLaunchKernelGGL(profile_mass_shift, dim3(1), dim3(kMassThreads), 0, s, logrho, r0, cx, cy, nx, ny, mass, shift);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(profile_to_rho0, dim3(grid1(nx, 256), ny), dim3(256), 0, s, logrho, r0,
+                       static_cast<const double*>(shift), cx, cy, nx, ny, rho0);
     return hipGetLastError();
 }
 

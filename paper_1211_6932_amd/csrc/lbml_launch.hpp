@@ -8,13 +8,14 @@ constexpr int kIn = 4;       // inputs: a, T/T_c, R, nu_g/nu_l (standardised)
 constexpr int kInPad = 32;   // first-layer depth padded to one matrix-core step
 constexpr int kHidden = 256;
 constexpr int kOut = 128;    // log-density samples across the interface
-constexpr int kAngles = 256; // azimuthal samples per radius
+constexpr double kSmooth = 1e-4;  // weight of the profile fit's smoothness term
 
 hipError_t gemm(const __bf16* A, long long sam, long long sak, const __bf16* B, long long sbk, long long sbn,
                 float* C, int ldc, int M, int N, int K, hipStream_t s);
 hipError_t launch_pack_input(const float* x, const float* mu, const float* inv_sd, __bf16* x16, int B,
                              hipStream_t s);
-hipError_t launch_bias_act(const float* C, const float* b, float* Z, __bf16* H, int B, int N, hipStream_t s);
+hipError_t launch_bias_act(const float* C, const float* b, const float* base, float* Z, __bf16* H, int B, int N,
+                           hipStream_t s);
 hipError_t launch_mse_grad(const float* Y, const float* T, __bf16* dY, float* loss, int B, int N, hipStream_t s);
 hipError_t launch_gelu_back(const float* dH, const float* Z, __bf16* dZ, int n, hipStream_t s);
 hipError_t launch_bias_grad(const __bf16* dZ, float* db, int B, int N, hipStream_t s);
@@ -23,9 +24,11 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int n, floa
                        float c1, float c2, hipStream_t s);
 hipError_t launch_to_bf16(const float* src, __bf16* dst, int rows, int cols, int ldd, hipStream_t s);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
-hipError_t launch_profile_extract(const float* rho, int nx, int ny, double cx, double cy, double R, float* logrho,
-                                  hipStream_t s);
+hipError_t launch_profile_extract(const float* rho, int nx, int ny, double cx, double cy, double R, double* part,
+                                  float* logrho, hipStream_t s);
 hipError_t launch_profile_to_rho0(const float* logrho, double R, double cx, double cy, int nx, int ny, float* rho0,
                                   hipStream_t s);
+hipError_t launch_profile_to_rho0_mass(const float* logrho, double R, double cx, double cy, int nx, int ny,
+                                       double mass, double* shift, float* rho0, hipStream_t s);
 
 }  // namespace lbml

@@ -316,7 +316,7 @@ lb_status init_ctx(lb_ctx** out, const lb_params* p, void* workspace, size_t wor
     hipError_t e = hipMemsetAsync(c->flag, 0, kAlign, c->stream);
     if (e == hipSuccess)
         e = lbmp::launch_init(p->store, p->bc == LB_BC_WALLS_Y, rho0, ux0, uy0, c->f[0], c->k,
-                              c->flag, c->stream);
+                              lbmp::InitConst{p->b / 4.0, p->R * p->T, p->a, p->G}, c->flag, c->stream);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "init launch");

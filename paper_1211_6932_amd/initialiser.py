@@ -1,0 +1,285 @@
+"""Learned droplet initialiser: training profiles produced by the lattice itself,
+training and inference of the profile network, and the comparison of
+learned starts against the tanh start of Eq. (31).
+
+Every device computation runs in liblbmp.so (lattice steps, diagnostics,
+profile fit and field, network forward / backward / Adam).  This module
+sequences those calls and keeps the host-side bookkeeping: feature statistics,
+the tanh base profile (the same Eq. (31) recipe the lattice starts from),
+convergence detection on the recorded diagnostics.
+
+Features: (a, T/T_c, R0, nu_g/nu_l).  Outputs: L_k = log rho(r_k),
+r_k = R0 + (k - 63.5) / 2, predicted as tanh base + network correction.
+
+Convergence of one run (checked every `every` steps), against the values a
+tanh-started run of the same droplet reaches at the end of the window:
+  * spurious-current convergence: the first check after which the maximum
+    velocity stays within 5 % of the reference's;
+  * strict convergence: the same, and the Laplace pressure jump within 1 %.
+A run that is outside those bounds at the last check does not converge in the
+window (None).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import lbmp
+
+U_TOL = 0.05
+DP_TOL = 0.01
+N_OUT = lbmp.LBML_OUT
+
+
+def radii(R):
+    return R + (np.arange(N_OUT, dtype=np.float64) - 63.5) * 0.5
+
+
+def features(ws):
+    return np.array([w.info["features"] for w in ws], dtype=np.float64)
+
+
+def tanh_base(ws, W=5.0):
+    """log of the Eq. (31) tanh start at the sample radii (the fallback profile)."""
+    out = np.empty((len(ws), N_OUT))
+    for i, w in enumerate(ws):
+        rl, rg, R = w.info["rho_l"], w.info["rho_g"], w.info["R0"]
+        d = radii(R) - R
+        out[i] = np.log(0.5 * (rl + rg) - 0.5 * (rl - rg) * np.tanh(2.0 * d / W))
+    return out
+
+
+def regions(w):
+    """Inner disc d < R0/2 and outer region d >= R0 + 15 around the droplet centre."""
+    c = (w.info["cx"], w.info["cy"])
+    R = w.info["R0"]
+    return (c[0], c[1], 0.0, 0.5 * R), (c[0], c[1], R + 15.0, math.inf)
+
+
+def record(batch, ws, steps, every, log=None, tag=""):
+    """Advance `steps` in chunks of `every`, recording max|u|, dp, rho_in, rho_out of
+    every lattice after each chunk (column 0 = the initial state)."""
+    rin, rout = zip(*[regions(w) for w in ws])
+    nc = steps // every + 1
+    rec = {k: np.zeros((len(ws), nc)) for k in ("U", "DP", "RHO_IN", "RHO_OUT")}
+    t0 = time.time()
+    for c in range(nc):
+        if c:
+            batch.step(every)
+        ds = batch.diagnostics_all(rin, rout)
+        rec["U"][:, c] = [d["max_u"] for d in ds]
+        rec["DP"][:, c] = [d["dp"] for d in ds]
+        rec["RHO_IN"][:, c] = [d["rho_in"] for d in ds]
+        rec["RHO_OUT"][:, c] = [d["rho_out"] for d in ds]
+        if log and (c % max(1, nc // 10) == 0 or c == nc - 1):
+            log(f"{tag} step {c * every}/{steps}  {time.time() - t0:.1f} s")
+    rec["unstable"] = np.array([bool(d["unstable"]) for d in ds])
+    return rec
+
+
+def n_conv(U, DP, u_ref, dp_ref, every, strict=False):
+    """Per run: first step after which |U - u_ref| <= 5 % u_ref (and, if strict,
+    |DP - dp_ref| <= 1 % |dp_ref|) holds at every later check; None if the last
+    check fails."""
+    ok = np.abs(U - u_ref[:, None]) <= U_TOL * u_ref[:, None]
+    if strict:
+        ok &= np.abs(DP - dp_ref[:, None]) <= DP_TOL * np.abs(dp_ref[:, None])
+    out = []
+    for row in ok:
+        bad = np.nonzero(~row)[0]
+        if len(bad) == 0:
+            out.append(0)
+        elif bad[-1] == len(row) - 1:
+            out.append(None)
+        else:
+            out.append(int((bad[-1] + 1) * every))
+    return out
+
+
+def relaxed_profiles(batch, ws, members):
+    """Least-squares profile of the current density field of batch lattices `members`
+    (descriptions `ws`), [n][128] device tensor.  The fits run on the batch's stream,
+    ordered after the moments they read."""
+    import torch
+    out = torch.empty((len(ws), N_OUT), dtype=torch.float32, device=batch.device)
+    scratch = torch.empty(max(lbmp.lbml_profile_scratch_bytes(w.params["ny"]) for w in ws), dtype=torch.uint8,
+                          device=batch.device)
+    s = batch.stream.cuda_stream
+    for i, (m, w) in enumerate(zip(members, ws)):
+        rho = batch.moments(int(m))[0]
+        lbmp.profile_extract(rho, w.info["cx"], w.info["cy"], w.info["R0"], out=out[i], scratch=scratch, stream=s)
+        rho.record_stream(batch.stream)
+    batch.stream.synchronize()
+    return out
+
+
+def generate(ws, steps, every=1000, log=None):
+    """Run every tanh-started lattice for `steps` and fit its relaxed profile.
+    Returns (features [n][4], base [n][128], target [n][128], kept mask); lattices
+    that went unstable are dropped."""
+    import torch
+    batch = lbmp.Batch([w.params for w in ws], [torch.from_numpy(w.rho0.astype(np.float32)) for w in ws])
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        n = min(every, steps - done)
+        batch.step(n)
+        done += n
+        batch.stream.synchronize()
+        if log:
+            log(f"training runs: step {done}/{steps}  {time.time() - t0:.1f} s")
+    rin, rout = zip(*[regions(w) for w in ws])
+    kept = np.array([not d["unstable"] for d in batch.diagnostics_all(rin, rout)])
+    members = np.nonzero(kept)[0]
+    keep = [ws[i] for i in members]
+    prof = relaxed_profiles(batch, keep, members).cpu().numpy().astype(np.float64)
+    batch.close()
+    finite = np.all(np.isfinite(prof), axis=1)
+    kept[members[~finite]] = False
+    keep = [w for w, f in zip(keep, finite) if f]
+    return features(keep), tanh_base(keep), prof[finite], kept
+
+
+def init_params(seed=1211):
+    """He-normal weights (std sqrt(2 / fan_in)), zero biases, in the parameter layout
+    of include/lbml.h."""
+    rng = np.random.default_rng(seed)
+    sizes = [lbmp.LBML_IN, lbmp.LBML_HIDDEN, lbmp.LBML_HIDDEN, lbmp.LBML_HIDDEN, N_OUT]
+    parts = []
+    for i in range(4):
+        parts.append(rng.standard_normal(sizes[i + 1] * sizes[i]) * math.sqrt(2.0 / sizes[i]))
+        parts.append(np.zeros(sizes[i + 1]))
+    theta = np.concatenate(parts).astype(np.float32)
+    assert theta.size == lbmp.LBML_PARAMS
+    return theta
+
+
+def train(X, base, T, steps=3000, lr=1e-3, lr_min=1e-5, minibatch=512, seed=1211, log=None):
+    """Adam on the mean squared error of (network + base) against T with a cosine
+    learning-rate decay from lr to lr_min; minibatches drawn without replacement
+    within each pass over the data.  Returns (net, losses)."""
+    import torch
+    n = X.shape[0]
+    mb = min(minibatch, n // 32 * 32)
+    if mb < 32:
+        raise ValueError("need at least 32 training profiles")
+    mu, sd = X.mean(0), X.std(0)
+    sd = np.where(sd > 0, sd, 1.0)
+    net = lbmp.Net(init_params(seed), mu, sd, max_batch=max(mb, 32))
+    dev = net.device
+    x = torch.from_numpy(X.astype(np.float32)).to(dev)
+    b = torch.from_numpy(base.astype(np.float32)).to(dev)
+    t = torch.from_numpy(T.astype(np.float32)).to(dev)
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    order, pos = torch.randperm(n, generator=gen), 0
+    losses = []
+    t0 = time.time()
+    for k in range(steps):
+        if pos + mb > n:
+            order, pos = torch.randperm(n, generator=gen), 0
+        idx = order[pos:pos + mb].to(dev)
+        pos += mb
+        xb, bb, tb = x.index_select(0, idx), b.index_select(0, idx), t.index_select(0, idx)
+        net.stream.wait_stream(torch.cuda.current_stream(dev))
+        rate = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * k / max(1, steps - 1)))
+        report = k % 100 == 0 or k == steps - 1
+        loss = net.train_step(xb, tb, rate, base=bb, sync=report)
+        torch.cuda.current_stream(dev).wait_stream(net.stream)
+        if report:
+            losses.append((k, loss))
+            if log and (k % 1000 == 0 or k == steps - 1):
+                log(f"train step {k}/{steps} loss {loss:.3e} lr {rate:.2e}  {time.time() - t0:.1f} s")
+    net.stream.synchronize()
+    return net, losses
+
+
+def predict(net, ws):
+    """Predicted profiles [n][128] (device) for droplets described by workloads."""
+    import torch
+    n = len(ws)
+    pad = (n + 15) // 16 * 16
+    X = np.zeros((pad, lbmp.LBML_IN))
+    base = np.zeros((pad, N_OUT))
+    X[:n], base[:n] = features(ws), tanh_base(ws)
+    X[n:] = X[0]
+    out = torch.empty((pad, N_OUT), dtype=torch.float32, device=net.device)
+    for s in range(0, pad, net.max_batch // 16 * 16):
+        e = min(pad, s + net.max_batch // 16 * 16)
+        out[s:e] = net.forward(torch.from_numpy(X[s:e].astype(np.float32)),
+                               torch.from_numpy(base[s:e].astype(np.float32)))
+    return out[:n]
+
+
+def learned_rho0(net, ws):
+    """Initial density fields from the network's profiles (device tensors), each moved
+    radially so that it carries the mass of the tanh start of the same droplet (both
+    starts then relax towards the same equilibrium).  Returns (fields, shifts)."""
+    import torch
+    prof = predict(net, ws)
+    fields, shifts = [], []
+    for i, w in enumerate(ws):
+        mass = float(w.rho0.astype(np.float32).sum(dtype=np.float64))
+        f, sh = lbmp.profile_to_rho0_mass(prof[i], w.info["R0"], w.info["cx"], w.info["cy"], w.params["nx"],
+                                          w.params["ny"], mass)
+        fields.append(f)
+        shifts.append(sh)
+    torch.cuda.synchronize()
+    return fields, [float(s[0]) for s in torch.stack(shifts).cpu()]
+
+
+def evaluate(net, ws, steps=30000, every=50, log=None):
+    """Tanh and learned starts of the same droplets, advanced together in one batch.
+    Returns per-droplet n_conv of both arms, the final-state errors of the learned
+    arm against the tanh arm and the inference wall time."""
+    import torch
+    n = len(ws)
+    t0 = time.time()
+    rho_l, shifts = learned_rho0(net, ws)
+    t_infer = time.time() - t0
+    rho_t = [torch.from_numpy(w.rho0.astype(np.float32)) for w in ws]
+    # fallback to the tanh start where a prediction is not a usable density
+    fallback = [i for i, f in enumerate(rho_l) if not bool(torch.isfinite(f).all() and (f > 0).all())]
+    for i in fallback:
+        rho_l[i] = rho_t[i]
+    batch = lbmp.Batch([w.params for w in ws] * 2, rho_t + rho_l)
+    rec = record(batch, list(ws) * 2, steps, every, log=log, tag="evaluation")
+    batch.close()
+    tanh = {k: v[:n] for k, v in rec.items()}
+    lrn = {k: v[n:] for k, v in rec.items()}
+    u_ref, dp_ref = tanh["U"][:, -1], tanh["DP"][:, -1]
+    res = dict(unstable=(tanh["unstable"] | lrn["unstable"]).tolist(),
+               dp_err=(lrn["DP"][:, -1] / dp_ref - 1.0).tolist(),
+               rho_in_err=(lrn["RHO_IN"][:, -1] / tanh["RHO_IN"][:, -1] - 1.0).tolist(),
+               rho_out_err=(lrn["RHO_OUT"][:, -1] / tanh["RHO_OUT"][:, -1] - 1.0).tolist(),
+               infer_seconds=t_infer, steps=steps, every=every, fallback=fallback, shifts=shifts)
+    for crit, strict in (("u", False), ("strict", True)):
+        res[f"n_tanh_{crit}"] = n_conv(tanh["U"], tanh["DP"], u_ref, dp_ref, every, strict)
+        res[f"n_learned_{crit}"] = n_conv(lrn["U"], lrn["DP"], u_ref, dp_ref, every, strict)
+    res["summary"] = {crit: summarise(res, crit) for crit in ("u", "strict")}
+    return res, rec
+
+
+def summarise(res, crit="u"):
+    """Median steps to convergence of both arms and the median per-droplet ratio
+    (tanh / learned), over droplets whose tanh run converges inside the window; a
+    learned run that does not converge counts as the full window.  Final-state
+    errors of the learned arm against the tanh arm over the same droplets."""
+    steps, every = res["steps"], res["every"]
+    nt, nl, bad = res[f"n_tanh_{crit}"], res[f"n_learned_{crit}"], res["unstable"]
+    idx = [i for i in range(len(nt)) if not bad[i] and nt[i] is not None and nt[i] < steps - every]
+    if not idx:
+        return dict(converged=0, total=len(nt))
+    a = np.array([nt[i] for i in idx], dtype=np.float64)
+    b = np.array([steps if nl[i] is None else max(nl[i], every) for i in idx], dtype=np.float64)
+
+    def med(key):
+        return float(np.median(np.abs([res[key][i] for i in idx])))
+
+    return dict(converged=len(idx), total=len(nt), unstable=int(np.sum(bad)),
+                median_steps_tanh=float(np.median(a)), median_steps_learned=float(np.median(b)),
+                ratio_of_medians=float(np.median(a) / np.median(b)), median_ratio=float(np.median(a / b)),
+                learned_not_converged=int(sum(1 for i in idx if nl[i] is None)),
+                median_abs_dp_err=med("dp_err"), max_abs_dp_err=float(np.max(np.abs([res["dp_err"][i] for i in idx]))),
+                median_abs_rho_in_err=med("rho_in_err"), median_abs_rho_out_err=med("rho_out_err"))

@@ -65,7 +65,7 @@ EXPORTS = [
     "lb_batch_destroy", "lb_batch_diagnostics_all",
     "lbml_workspace_bytes", "lbml_init", "lbml_set_params", "lbml_get_params", "lbml_forward",
     "lbml_loss_grad", "lbml_adam", "lbml_train_step", "lbml_destroy", "lbml_profile_extract",
-    "lbml_profile_to_rho0", "lbml_gemm_bf16",
+    "lbml_profile_to_rho0", "lbml_gemm_bf16", "lbml_profile_scratch_bytes", "lbml_profile_to_rho0_mass",
 ]
 LBML_IN, LBML_HIDDEN, LBML_OUT, LBML_PARAMS = 4, 256, 128, 165760
 
@@ -145,13 +145,15 @@ def load():
         "lbml_init": ([ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, dp, dp, vp], ctypes.c_int),
         "lbml_set_params": ([vp, vp], ctypes.c_int),
         "lbml_get_params": ([vp, vp], ctypes.c_int),
-        "lbml_forward": ([vp, vp, i32, vp], ctypes.c_int),
-        "lbml_loss_grad": ([vp, vp, vp, i32, vp, vp], ctypes.c_int),
+        "lbml_forward": ([vp, vp, vp, i32, vp], ctypes.c_int),
+        "lbml_loss_grad": ([vp, vp, vp, vp, i32, vp, vp], ctypes.c_int),
         "lbml_adam": ([vp, f32], ctypes.c_int),
-        "lbml_train_step": ([vp, vp, vp, i32, f32, vp], ctypes.c_int),
+        "lbml_train_step": ([vp, vp, vp, vp, i32, f32, vp], ctypes.c_int),
         "lbml_destroy": ([vp], ctypes.c_int),
-        "lbml_profile_extract": ([vp, i32, i32, f64, f64, f64, vp, vp], ctypes.c_int),
+        "lbml_profile_scratch_bytes": ([i32], ctypes.c_size_t),
+        "lbml_profile_extract": ([vp, i32, i32, f64, f64, f64, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
         "lbml_profile_to_rho0": ([vp, f64, f64, f64, i32, i32, vp, vp], ctypes.c_int),
+        "lbml_profile_to_rho0_mass": ([vp, f64, f64, f64, i32, i32, f64, vp, vp, vp], ctypes.c_int),
         "lbml_gemm_bf16": ([vp, i64, i64, vp, i64, i64, vp, i32, i32, i32, i32, vp], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
@@ -358,36 +360,47 @@ def lbml_get_params(net, theta_ptr):
     return _check(load().lbml_get_params(net, _vp(theta_ptr)), "lbml_get_params")
 
 
-def lbml_forward(net, x_ptr, B, y_ptr):
-    return _check(load().lbml_forward(net, _vp(x_ptr), int(B), _vp(y_ptr)), "lbml_forward")
+def lbml_forward(net, x_ptr, base_ptr, B, y_ptr):
+    return _check(load().lbml_forward(net, _vp(x_ptr), _vp(base_ptr), int(B), _vp(y_ptr)), "lbml_forward")
 
 
-def lbml_loss_grad(net, x_ptr, target_ptr, B, loss_ptr, grad_ptr):
-    return _check(load().lbml_loss_grad(net, _vp(x_ptr), _vp(target_ptr), int(B), _vp(loss_ptr), _vp(grad_ptr)),
-                  "lbml_loss_grad")
+def lbml_loss_grad(net, x_ptr, base_ptr, target_ptr, B, loss_ptr, grad_ptr):
+    return _check(load().lbml_loss_grad(net, _vp(x_ptr), _vp(base_ptr), _vp(target_ptr), int(B), _vp(loss_ptr),
+                                        _vp(grad_ptr)), "lbml_loss_grad")
 
 
 def lbml_adam(net, lr):
     return _check(load().lbml_adam(net, float(lr)), "lbml_adam")
 
 
-def lbml_train_step(net, x_ptr, target_ptr, B, lr, loss_ptr):
-    return _check(load().lbml_train_step(net, _vp(x_ptr), _vp(target_ptr), int(B), float(lr), _vp(loss_ptr)),
-                  "lbml_train_step")
+def lbml_train_step(net, x_ptr, base_ptr, target_ptr, B, lr, loss_ptr):
+    return _check(load().lbml_train_step(net, _vp(x_ptr), _vp(base_ptr), _vp(target_ptr), int(B), float(lr),
+                                         _vp(loss_ptr)), "lbml_train_step")
 
 
 def lbml_destroy(net):
     return load().lbml_destroy(net)
 
 
-def lbml_profile_extract(rho_ptr, nx, ny, cx, cy, R, logrho_ptr, stream):
+def lbml_profile_scratch_bytes(ny):
+    return load().lbml_profile_scratch_bytes(int(ny))
+
+
+def lbml_profile_extract(rho_ptr, nx, ny, cx, cy, R, scratch_ptr, scratch_bytes, logrho_ptr, stream):
     return _check(load().lbml_profile_extract(_vp(rho_ptr), int(nx), int(ny), float(cx), float(cy), float(R),
-                                              _vp(logrho_ptr), _vp(stream)), "lbml_profile_extract")
+                                              _vp(scratch_ptr), int(scratch_bytes), _vp(logrho_ptr), _vp(stream)),
+                  "lbml_profile_extract")
 
 
 def lbml_profile_to_rho0(logrho_ptr, R, cx, cy, nx, ny, rho0_ptr, stream):
     return _check(load().lbml_profile_to_rho0(_vp(logrho_ptr), float(R), float(cx), float(cy), int(nx), int(ny),
                                               _vp(rho0_ptr), _vp(stream)), "lbml_profile_to_rho0")
+
+
+def lbml_profile_to_rho0_mass(logrho_ptr, R, cx, cy, nx, ny, mass, shift_ptr, rho0_ptr, stream):
+    return _check(load().lbml_profile_to_rho0_mass(_vp(logrho_ptr), float(R), float(cx), float(cy), int(nx), int(ny),
+                                                   float(mass), _vp(shift_ptr), _vp(rho0_ptr), _vp(stream)),
+                  "lbml_profile_to_rho0_mass")
 
 
 def lbml_gemm_bf16(A_ptr, sam, sak, B_ptr, sbk, sbn, C_ptr, ldc, M, N, K, stream):
@@ -629,23 +642,28 @@ class Net:
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         return t
 
-    def forward(self, x):
+    def forward(self, x, base=None):
+        """network(x) + base, [B][128] (base: [B][128] or None)."""
         x = self._dev(x, LBML_IN)
+        base = None if base is None else self._dev(base, LBML_OUT)
         y = self.torch.empty((x.shape[0], LBML_OUT), dtype=self.torch.float32, device=self.device)
-        lbml_forward(self.net, x.data_ptr(), x.shape[0], y.data_ptr())
+        lbml_forward(self.net, x.data_ptr(), 0 if base is None else base.data_ptr(), x.shape[0], y.data_ptr())
         self.stream.synchronize()
         return y
 
-    def loss_grad(self, x, target):
+    def loss_grad(self, x, target, base=None):
         x, target = self._dev(x, LBML_IN), self._dev(target, LBML_OUT)
+        base = None if base is None else self._dev(base, LBML_OUT)
         g = self.torch.empty(LBML_PARAMS, dtype=self.torch.float32, device=self.device)
-        lbml_loss_grad(self.net, x.data_ptr(), target.data_ptr(), x.shape[0], self.loss_buf.data_ptr(), g.data_ptr())
+        lbml_loss_grad(self.net, x.data_ptr(), 0 if base is None else base.data_ptr(), target.data_ptr(), x.shape[0],
+                       self.loss_buf.data_ptr(), g.data_ptr())
         self.stream.synchronize()
         return float(self.loss_buf.item()), g
 
-    def train_step(self, x, target, lr, sync=True):
-        """x, target: device tensors already in place (no copies when they are)."""
-        lbml_train_step(self.net, x.data_ptr(), target.data_ptr(), x.shape[0], lr, self.loss_buf.data_ptr())
+    def train_step(self, x, target, lr, base=None, sync=True):
+        """x, target, base: device tensors already in place (no copies when they are)."""
+        lbml_train_step(self.net, x.data_ptr(), 0 if base is None else base.data_ptr(), target.data_ptr(),
+                        x.shape[0], lr, self.loss_buf.data_ptr())
         if sync:
             self.stream.synchronize()
             return float(self.loss_buf.item())
@@ -661,3 +679,37 @@ class Net:
         theta = self.torch.as_tensor(theta).to(device=self.device, dtype=self.torch.float32).contiguous()
         lbml_set_params(self.net, theta.data_ptr())
         self.stream.synchronize()
+
+
+def profile_extract(rho, cx, cy, R, out=None, scratch=None, stream=0):
+    """Least-squares profile [128] of a device density field [ny][nx] (torch tensor)."""
+    import torch
+    ny, nx = rho.shape
+    if out is None:
+        out = torch.empty(LBML_OUT, dtype=torch.float32, device=rho.device)
+    need = lbml_profile_scratch_bytes(ny)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=rho.device)
+    lbml_profile_extract(rho.data_ptr(), nx, ny, cx, cy, R, scratch.data_ptr(), need, out.data_ptr(), stream)
+    return out
+
+
+def profile_to_rho0(logrho, R, cx, cy, nx, ny, out=None, stream=0):
+    """Device density field [ny][nx] of a profile (device tensor [128])."""
+    import torch
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float32, device=logrho.device)
+    lbml_profile_to_rho0(logrho.data_ptr(), R, cx, cy, nx, ny, out.data_ptr(), stream)
+    return out
+
+
+def profile_to_rho0_mass(logrho, R, cx, cy, nx, ny, mass, out=None, shift=None, stream=0):
+    """Device density field [ny][nx] of a profile moved radially to carry `mass`;
+    returns (field, shift tensor [2] = (delta, achieved mass))."""
+    import torch
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float32, device=logrho.device)
+    if shift is None:
+        shift = torch.empty(2, dtype=torch.float64, device=logrho.device)
+    lbml_profile_to_rho0_mass(logrho.data_ptr(), R, cx, cy, nx, ny, mass, shift.data_ptr(), out.data_ptr(), stream)
+    return out, shift

@@ -143,13 +143,21 @@ def test_learned_initialiser_host_checks():
     assert L.lbml_init(ctypes.byref(net), 64, vp(256), ws, vp(256), mu, bad_sd, None) == B.LB_EINVAL
     assert L.lbml_init(ctypes.byref(net), 64, vp(256), ws, None, mu, sd, None) == B.LB_EINVAL
     assert B.lb_last_error() != ""
-    assert L.lbml_forward(None, vp(256), 16, vp(256)) == B.LB_EINVAL
-    assert L.lbml_loss_grad(None, vp(256), vp(256), 32, None, None) == B.LB_EINVAL
+    assert L.lbml_forward(None, vp(256), None, 16, vp(256)) == B.LB_EINVAL
+    assert L.lbml_loss_grad(None, vp(256), None, vp(256), 32, None, None) == B.LB_EINVAL
     assert L.lbml_adam(None, 1e-3) == B.LB_EINVAL
     assert L.lbml_destroy(None) == B.LB_OK
     assert L.lbml_gemm_bf16(vp(256), 32, 1, vp(256), 16, 1, vp(256), 16, 16, 16, 48, None) == B.LB_EINVAL
     assert L.lbml_gemm_bf16(vp(256), 32, 1, vp(256), 16, 1, vp(256), 8, 16, 16, 32, None) == B.LB_EINVAL
-    assert L.lbml_profile_extract(vp(256), 1, 64, 0.0, 0.0, 10.0, vp(256), None) == B.LB_EINVAL
-    assert L.lbml_profile_extract(vp(256), 64, 64, float("nan"), 0.0, 10.0, vp(256), None) == B.LB_EINVAL
+    sb = B.lbml_profile_scratch_bytes(64)
+    assert sb == 3 * 64 * 128 * 8 and B.lbml_profile_scratch_bytes(1) == 0
+    assert L.lbml_profile_extract(vp(256), 1, 64, 0.0, 0.0, 10.0, vp(256), sb, vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_extract(vp(256), 64, 64, float("nan"), 0.0, 10.0, vp(256), sb, vp(256),
+                                  None) == B.LB_EINVAL
+    assert L.lbml_profile_extract(vp(256), 64, 64, 0.0, 0.0, 10.0, vp(256), sb - 8, vp(256), None) == B.LB_ENOMEM
+    assert L.lbml_profile_extract(vp(256), 64, 64, 0.0, 0.0, 10.0, None, sb, vp(256), None) == B.LB_EINVAL
     assert L.lbml_profile_to_rho0(vp(256), -1.0, 0.0, 0.0, 64, 64, vp(256), None) == B.LB_EINVAL
     assert L.lbml_profile_to_rho0(None, 10.0, 0.0, 0.0, 64, 64, vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_to_rho0_mass(vp(256), 10.0, 0.0, 0.0, 64, 64, 100.0, None, vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_to_rho0_mass(vp(256), 10.0, 0.0, 0.0, 64, 64, -1.0, vp(256), vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_to_rho0_mass(vp(256), 10.0, 0.0, 0.0, 64, 64, 100.0, vp(260), vp(256), None) == B.LB_EINVAL

@@ -1,0 +1,54 @@
+"""What the learned initialiser gains over the tanh start (small scale, seconds).
+
+256 tanh-started droplets on 128 x 128 lattices relax for 12,000 steps; the
+least-squares profiles of their densities train the network on the device; 32
+held-out droplets then start from the tanh profile and from the network's
+profile (placed radially so it carries the tanh start's mass) and run 12,000
+steps together.  Checked against the tanh runs' final state:
+  * spurious-current convergence (max|u| within 5 % for good): the learned
+    starts need at least 1.5 x fewer steps (median per-droplet ratio);
+  * with the pressure jump also within 1 %: at least 1.1 x fewer;
+  * the learned runs end on the same state: median |Delta dp| <= 1e-3,
+    coexistence densities within 1e-4;
+  * no prediction falls back to the tanh start.
+At the full size (4096 training runs, 256 droplets on 256 x 256, 30,000
+steps) the same protocol is run by `bench.py --workload learned`.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1211_6932_amd.lbmp")
+I = pytest.importorskip("paper_1211_6932_amd.initialiser")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    B.load()
+    yield
+
+
+def test_learned_start_converges_faster_than_tanh():
+    print("[gpu-case] learned initialiser 128x128 small protocol", flush=True)
+    train = W.learned_train_instances(n=256, side_lo=128, side_hi=128)
+    X, base, T, kept = I.generate(train, 12000, every=4000, log=print)
+    assert kept.sum() >= 240 and np.all(np.isfinite(T))
+    net, losses = I.train(X, base, T, steps=2000, log=print)
+    assert losses[-1][1] < 0.01 * losses[0][1]
+    held_out = W.learned_eval_instances(n=32, side=128)
+    res, _ = I.evaluate(net, held_out, steps=12000, every=50)
+    net.close()
+    u, strict = res["summary"]["u"], res["summary"]["strict"]
+    print("spurious-current convergence:", u)
+    print("strict convergence:", strict)
+    assert res["fallback"] == []
+    assert u["converged"] >= 24 and u["median_ratio"] >= 1.5
+    assert strict["converged"] >= 16 and strict["median_ratio"] >= 1.1
+    assert u["median_abs_dp_err"] <= 1e-3
+    assert u["median_abs_rho_in_err"] <= 1e-4 and u["median_abs_rho_out_err"] <= 1e-4

@@ -31,6 +31,27 @@ def momentum(f):
 # ------------------------------------------------------------------ invariants
 
 @pytest.mark.parametrize("bc", [0, 1])
+def test_initial_moments_return_rho0_and_u0(bc):
+    """Eq. (6): rho v = sum e f + F/2.  The initial state is built so that the
+    velocity of the moments at t = 0 is the requested u0 (not u0 + F / (2 rho0))."""
+    w = W.stationary_droplet(n=40, R0=11.0)
+    p = dict(w.params, bc=bc)
+    rng = np.random.default_rng(7)
+    ux0 = 0.01 * rng.standard_normal(w.rho0.shape)
+    uy0 = 0.01 * rng.standard_normal(w.rho0.shape)
+    s = state(p, w.rho0, ux0, uy0)
+    rho, ux, uy, Fx, Fy, _ = s.moments()
+    assert np.abs(rho - w.rho0).max() < 1e-15
+    assert np.abs(ux - ux0).max() < 1e-14 and np.abs(uy - uy0).max() < 1e-14
+    # the force is far from zero across the interface, so the correction is not vacuous
+    assert np.abs(Fx / (2 * rho)).max() > 1e-3
+    # the distributions themselves are the equilibria at u_eq = u0 - F / (2 rho0)
+    jx, jy = (s.f * EX[:, None, None]).sum(0), (s.f * EY[:, None, None]).sum(0)
+    assert np.abs(jx - (w.rho0 * ux0 - Fx / 2)).max() < 1e-14
+    assert np.abs(jy - (w.rho0 * uy0 - Fy / 2)).max() < 1e-14
+
+
+@pytest.mark.parametrize("bc", [0, 1])
 @pytest.mark.parametrize("rho", [0.4, 0.01])
 def test_uniform_state_stays_at_equilibrium(bc, rho):
     p = W.base_params(24, 16, bc=bc)

@@ -66,3 +66,18 @@ def test_adam_matches_library():
         opt.step()
         theta, m, v = M.adam_step(theta, m, v, g, t, 1e-3)
     assert np.abs(theta - p.detach().numpy()).max() < 1e-12
+
+
+def test_base_profile_shifts_outputs_not_gradients():
+    """A base added to the outputs is the same as a target shifted by it."""
+    rng = np.random.default_rng(5)
+    theta = M.init_params(seed=6)
+    X = rng.standard_normal((8, 4))
+    T = rng.standard_normal((8, 128))
+    base = rng.standard_normal((8, 128))
+    y0, _ = M.forward(theta, X)
+    y1, _ = M.forward(theta, X, base=base)
+    assert np.array_equal(y1, y0 + base)
+    l1, g1 = M.loss_and_grad(theta, X, T, base=base)
+    l2, g2 = M.loss_and_grad(theta, X, T - base)
+    assert abs(l1 - l2) < 1e-12 * l2 and np.abs(g1 - g2).max() < 1e-12 * np.abs(g2).max()

@@ -1,9 +1,8 @@
-"""Pins of the radial-profile oracle (oracle/profile.py): fields whose angular mean
-is known in closed form, a library bilinear interpolator, exact sample sites."""
+"""Pins of the radial-profile oracle (oracle/profile.py): exact sample sites, profiles
+inside the least-squares model's span, a brute-force normal-equation solve."""
 import math
 
 import numpy as np
-from scipy import ndimage
 
 from oracle import profile as P
 
@@ -15,40 +14,6 @@ def test_radii_window():
     assert np.allclose(np.diff(r), 0.5)
 
 
-def test_bilinear_matches_library_interpolator():
-    rng = np.random.default_rng(0)
-    rho = rng.uniform(0.1, 1.0, (23, 31))
-    pts = rng.uniform(-40, 70, (200, 2))
-    ref = ndimage.map_coordinates(rho, [pts[:, 1], pts[:, 0]], order=1, mode="grid-wrap")
-    got = np.array([P.bilinear_periodic(rho, x, y) for x, y in pts])
-    assert np.abs(got - ref).max() < 1e-13
-
-
-def test_extract_of_constant_and_bilinear_fields_is_exact():
-    nx, ny = 200, 160
-    x = np.arange(nx, dtype=np.float64)[None, :]
-    y = np.arange(ny, dtype=np.float64)[:, None]
-    assert np.abs(P.extract(np.full((ny, nx), 0.37), 97.0, 80.0, 40.0) - math.log(0.37)).max() < 1e-14
-    # rho = 1 + 2e-3 x + 1e-5 x y: bilinear interpolation reproduces it, and the mean over
-    # equally spaced angles of (cx + r cos)(cy + r sin) is cx cy (no wrap: r <= 72 < distances to edges)
-    rho = 1.0 + 2e-3 * x + 1e-5 * x * y
-    cx, cy = 99.0, 79.5
-    prof = P.extract(rho, cx, cy, 40.0)
-    assert np.abs(prof - math.log(1.0 + 2e-3 * cx + 1e-5 * cx * cy)).max() < 1e-13
-
-
-def test_extract_of_radial_field_recovers_the_radial_function():
-    nx = ny = 256
-    cx = cy = 127.5
-    x = np.arange(nx, dtype=np.float64)[None, :]
-    y = np.arange(ny, dtype=np.float64)[:, None]
-    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
-    f = lambda s: 0.3 + 0.2 * np.tanh((50.0 - s) / 4.0)  # noqa: E731
-    prof = P.extract(f(r), cx, cy, 50.0)
-    # bilinear interpolation of a smooth radial function: error O(h^2 f'')
-    assert np.abs(np.exp(prof) - f(P.radii(50.0))).max() < 2e-3
-
-
 def test_to_rho0_exact_at_sample_sites_and_held_outside():
     R, cx, cy, n = 40.75, 100.0, 90.0, 256
     logrho = np.linspace(-0.5, -6.0, 128) + 0.1 * np.sin(np.arange(128))
@@ -58,15 +23,81 @@ def test_to_rho0_exact_at_sample_sites_and_held_outside():
         assert abs(field[int(cy), int(cx) + d] - math.exp(logrho[k])) < 1e-14
         assert abs(field[int(cy) - d, int(cx)] - math.exp(logrho[k])) < 1e-14
     assert field[int(cy), int(cx)] == math.exp(logrho[0])
-    # minimum image: the far corner is at distance < n/sqrt(2) and beyond the window
+    # minimum image: the far corner is beyond the window
     assert field[int(cy) + 128, int(cx) + 128] == math.exp(logrho[-1])
+    # R = 40.5: r_k = 8.75 + k/2, so distance 9 + j lies halfway between samples 2j and 2j+1
+    half = P.to_rho0(logrho, 40.5, cx, cy, n, n)
+    for j in (0, 5, 30):
+        assert abs(half[int(cy), int(cx) + 9 + j] - math.exp(0.5 * (logrho[2 * j] + logrho[2 * j + 1]))) < 1e-14
 
 
-def test_round_trip_in_the_window():
-    R, cx, cy, n = 60.0, 127.0, 128.0, 256
-    logrho = np.log(0.3 + 0.2 * np.tanh((R - P.radii(R)) / 3.0))
-    back = P.extract(P.to_rho0(logrho, R, cx, cy, n, n), cx, cy, R)
-    # both interpolations are exact for linear data; the tanh curvature costs about
-    # h^2 max|rho''| / 4 = 0.2 * 0.77 / 9 / 4 = 4e-3 in rho, 1.4e-2 in log rho at rho = 0.3
-    assert np.abs(back[2:-2] - logrho[2:-2]).max() < 2e-2
-    assert np.abs(back[:20] - logrho[:20]).max() < 1e-6  # flat bulk (r <= R - 22): exact up to the tanh tail
+def test_extract_constant_and_linear_profiles_exactly():
+    n, cx, cy, R = 200, 99.5, 100.25, 60.0
+    assert np.abs(P.extract(np.full((n, n), 0.37), cx, cy, R) - math.log(0.37)).max() < 1e-12
+    # a linear profile is in the model's span; the smoothness term only pulls the two end
+    # samples, by about lam * slope / (weight of their data)
+    L = -0.7 - 0.04 * np.arange(128)
+    back = P.extract(P.to_rho0(L, R, cx, cy, n, n), cx, cy, R)
+    assert np.abs(back - L)[1:-1].max() < 1e-9 and np.abs(back - L).max() < 1e-8
+
+
+def test_extract_recovers_a_curved_profile_in_its_span():
+    n, cx, cy, R = 256, 127.5, 127.5, 50.0
+    r = P.radii(R)
+    L = np.log(0.26 + 0.24 * np.tanh((R - r) / 3.0))
+    back = P.extract(P.to_rho0(L, R, cx, cy, n, n), cx, cy, R)
+    # only the smoothness term perturbs it: lam |second difference| / (sites per hat)
+    assert np.abs(back - L).max() < 1e-5
+
+
+def test_extract_matches_brute_force_normal_equations():
+    rng = np.random.default_rng(3)
+    n, cx, cy, R = 48, 20.3, 25.9, 12.0
+    rho = np.exp(rng.normal(-1.0, 0.3, (n, n)))
+    d = P.min_image_distance(n, n, cx, cy).ravel()
+    H = np.zeros((d.size, 128))
+    r = P.radii(R)
+    for i, di in enumerate(d):  # hat functions written out, end hats extended
+        if di <= r[0]:
+            H[i, 0] = 1.0
+        elif di >= r[-1]:
+            H[i, -1] = 1.0
+        else:
+            j = int((di - r[0]) // 0.5)
+            t = (di - r[j]) / 0.5
+            H[i, j] += 1.0 - t
+            H[i, j + 1] += t
+    D = np.zeros((127, 128))
+    D[np.arange(127), np.arange(127)] = -1.0
+    D[np.arange(127), np.arange(1, 128)] = 1.0
+    A = H.T @ H + P.LAM * D.T @ D
+    ref = np.linalg.solve(A, H.T @ np.log(rho).ravel())
+    assert np.abs(P.extract(rho, cx, cy, R) - ref).max() < 1e-9
+
+
+def test_empty_radii_take_the_nearest_fitted_value():
+    # R = 10: r_k < 0 for k < 43.5, where no site lies; the smoothness term carries
+    # the innermost fitted value inwards
+    n, cx, cy, R = 64, 31.5, 31.5, 10.0
+    rho = 0.3 + 0.1 * np.tanh((R - P.min_image_distance(n, n, cx, cy)) / 2.0)
+    L = P.extract(rho, cx, cy, R)
+    assert np.all(np.isfinite(L))
+    inner = int(np.ceil(63.5 - 2 * R))
+    assert np.abs(L[:inner] - L[inner]).max() < 1e-3
+
+
+def test_mass_matched_field_carries_the_mass_and_shifts_the_profile():
+    n, cx, cy, R = 128, 63.5, 63.5, 30.0
+    r = P.radii(R)
+    L = np.log(0.26 + 0.24 * np.tanh((R - r) / 2.5))
+    base_field = P.to_rho0(L, R, cx, cy, n, n)
+    # the unshifted field's own mass gives delta = 0 (to the bisection's resolution)
+    f0, d0 = P.to_rho0_mass(L, R, cx, cy, n, n, base_field.sum())
+    assert abs(d0) < 1e-12 and np.abs(f0 - base_field).max() < 1e-12
+    # a larger mass moves the interface outwards by the area it needs: 2 pi R delta drho ~ dM
+    dm = 0.5 * 2 * np.pi * R * (0.5 - 0.02)
+    f1, d1 = P.to_rho0_mass(L, R, cx, cy, n, n, base_field.sum() + dm)
+    assert abs(f1.sum() - (base_field.sum() + dm)) < 1e-9 * f1.sum()
+    assert 0.45 < d1 < 0.55
+    # the shifted field is the profile sampled at d - delta
+    assert np.allclose(f1, P.to_rho0(L, R + d1, cx, cy, n, n))

@@ -168,6 +168,25 @@ def splash(scale=1, Re=200, nx=None, ny=None, U=0.05, t_over_tc=0.45, a=0.25, ra
                     info=dict(R=R, film=film, U=U, Re=Re, rho_l=rl, rho_g=rg, t_over_tc=t_over_tc))
 
 
+def wall_film_droplet(nx=200, ny=150, U=0.02, t_over_tc=0.45, a=0.25) -> Workload:
+    """Wall-bounded case without topology change: a liquid film of mean height 20 with
+    a one-period sinusoidal surface (amplitude 3) on the lower wall, and a droplet of
+    radius 25 centred at (nx/2, 95) moving towards it at (0, -U), well clear of the
+    film, both walls and its periodic images.  Splash parameters (walls in y)."""
+    p = splash(nx=nx, ny=ny).params
+    p = dict(p, a=float(a), T=float(t_over_tc * critical_temperature(a)))
+    rl, rg = coexistence(t_over_tc)
+    x, y = _grid(nx, ny)
+    film = tanh_profile(y - (20.0 + 3.0 * np.sin(2.0 * np.pi * x / nx)), rl, rg)
+    drop = droplet_field(nx, ny, 25.0, rl, rg, cx=nx / 2.0, cy=95.0, periodic_y=False)
+    rho0 = np.maximum(film, drop)
+    phi = np.clip((drop - rg) / (rl - rg), 0.0, 1.0)
+    ux0 = np.zeros_like(rho0)
+    uy0 = -U * phi
+    return Workload(f"wall_film_droplet_{nx}x{ny}", p, rho0, ux0, uy0,
+                    info=dict(rho_l=rl, rho_g=rg, t_over_tc=t_over_tc, U=U))
+
+
 def splash_crop(Re=200) -> Workload:
     """512 x 256 cut-down of the splash case (same R = 100, film 20, centre (256, 125))."""
     return splash(scale=1, Re=Re, nx=512, ny=256)
@@ -190,4 +209,45 @@ def batch_instances(n=512, seed=1211, side_lo=64, side_hi=512):
         rho0 = ellipse_field(side, side, R0, 1.2, rl, rg) if ellipse else droplet_field(side, side, R0, rl, rg)
         out.append(Workload(f"inst{k}_{'ell' if ellipse else 'drop'}_{side}", p, rho0,
                             info=dict(R0=R0, rho_l=rl, rho_g=rg, t_over_tc=tb, ellipse=ellipse)))
+    return out
+
+
+def _droplet_case(side, a, tb, R0, ratio, nu_l=0.1):
+    p = base_params(side, side, a=a, t_over_tc=tb, nu_l=nu_l, nu_g=ratio * nu_l)
+    rl, rg = coexistence(tb)
+    c = (side - 1) / 2.0
+    rho0 = droplet_field(side, side, R0, rl, rg)
+    return Workload(f"drop_{side}_a{a:g}_t{tb:.3f}_R{R0:.1f}_v{ratio:.2f}", p, rho0,
+                    info=dict(R0=R0, rho_l=rl, rho_g=rg, t_over_tc=tb, ratio=ratio, cx=c, cy=c,
+                              features=(a, tb, R0, ratio)))
+
+
+def learned_train_instances(n=4096, seed=1212, side_lo=128, side_hi=512):
+    """Training runs of the droplet initialiser: circular stationary droplets of the
+    batched-sweep kind (square periodic side ~ U{side_lo..side_hi}, a ~ {0.25, 0.5, 1.0},
+    T/T_c ~ U[0.5, 0.85], R0 ~ U[0.1, 0.3] side) with nu_g / nu_l ~ U[1, 15], nu_l = 0.1.
+    side_lo = 128 keeps the sampled window (R0 +- 32) clear of the periodic images."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        side = int(rng.integers(side_lo, side_hi + 1))
+        a = float(rng.choice([0.25, 0.5, 1.0]))
+        tb = float(rng.uniform(0.5, 0.85))
+        R0 = float(rng.uniform(0.1, 0.3) * side)
+        ratio = float(rng.uniform(1.0, 15.0))
+        out.append(_droplet_case(side, a, tb, R0, ratio))
+    return out
+
+
+def learned_eval_instances(n=256, seed=1213, side=256):
+    """Held-out droplets for the initialiser: side x side periodic, R0 ~ U[0.1, 0.3] side,
+    the other inputs drawn as for the training runs."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        a = float(rng.choice([0.25, 0.5, 1.0]))
+        tb = float(rng.uniform(0.5, 0.85))
+        R0 = float(rng.uniform(0.1, 0.3) * side)
+        ratio = float(rng.uniform(1.0, 15.0))
+        out.append(_droplet_case(side, a, tb, R0, ratio))
     return out
