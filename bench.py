@@ -39,7 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-BYTES_PER_SITE = {"f32": 72, "f16": 36, "bf16": 36, "f16local": 44, "bf16local": 44}
+BYTES_PER_SITE = {"f32": 72, "f16": 36, "bf16": 36, "f16local": 44, "bf16local": 44, "f16dest": 40}
 PEAK_HBM_GBPS = 8000.0
 
 

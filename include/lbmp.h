@@ -61,7 +61,11 @@ typedef enum {
     LB_STORE_BF16_OFFSET = 2,  /* BF16 of f_a - w_a rho_ref (36 B/site/step)                  */
     LB_STORE_F16_LOCAL = 3,    /* FP16 of f_a - w_a rho(x) with the site's own density
                                   rho(x) stored in FP32 beside them (44 B/site/step)         */
-    LB_STORE_BF16_LOCAL = 4    /* BF16 of f_a - w_a rho(x), rho(x) in FP32 (44 B/site/step)   */
+    LB_STORE_BF16_LOCAL = 4,   /* BF16 of f_a - w_a rho(x), rho(x) in FP32 (44 B/site/step)   */
+    LB_STORE_F16_DEST = 5      /* FP16 of f*_a(x) / rhohat(x + e_a) - w_a, scaled by the density
+                                  of the site that pulls the value (x itself for a population
+                                  reflected at a wall); rhohat = bf16 of each site's density,
+                                  stored beside it (40 B/site/step)                          */
 } lb_store;
 /* w_a are the D2Q9 lattice weights 4/9 (rest), 1/9 (axis), 1/36 (diagonal).
  * Collision and force are computed in FP32 for every storage type. */
@@ -117,7 +121,8 @@ size_t lb_workspace_bytes(const lb_params* p);
 
 /* Bytes of one stored state, the size of the buffers lb_get_state /
  * lb_set_state copy: 9 * nx * ny elements of the storage type, plus nx * ny FP32
- * densities for the local-density encodings.  Pure host function. */
+ * densities for the local-density encodings or nx * ny bf16 scales for
+ * LB_STORE_F16_DEST.  Pure host function. */
 size_t lb_state_bytes(const lb_params* p);
 
 /* Create a context and set the state at t = 0 to f_a = [M^-1 m_eq(rho0, u_eq)]_a,
@@ -188,7 +193,7 @@ typedef struct lb_batch lb_batch;
 
 /* Workspace bytes for n lattices with parameter blocks p[0..n-1] (0 if invalid:
  * n < 1, a bad block, differing store/bc, or a store other than LB_STORE_F32 /
- * LB_STORE_F16_LOCAL).  Pure host function. */
+ * LB_STORE_F16_LOCAL / LB_STORE_F16_DEST).  Pure host function. */
 size_t lb_batch_workspace_bytes(const lb_params* p, int32_t n);
 
 /* Create the batch on a caller-owned device workspace (256-byte aligned, at

@@ -38,7 +38,7 @@ constexpr int kBatchWaves = LBMP_BATCH_WAVES;  // wavefronts per workgroup (= pe
 constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kDiagFields = 10;       // doubles per wave partial in the diagnostics pass
 
-enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2, kStoreF16Local = 3, kStoreBF16Local = 4 };
+enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2, kStoreF16Local = 3, kStoreBF16Local = 4, kStoreF16Dest = 5 };
 enum : int { kModeStep = 0, kModeMoments = 1, kModeDiag = 2 };
 enum : int { kFlagUnstable = 1, kFlagBadInput = 2 };
 
@@ -136,6 +136,7 @@ template <int S> struct Codec;
 template <> struct Codec<kStoreF32> {
     using T = float;
     static constexpr int kRowSlots = 9;  // T-sized row slots per lattice row
+    static constexpr bool kDestScaled = false;
     static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
         return ld(row + a * k.pitch, col);
     }
@@ -143,7 +144,8 @@ template <> struct Codec<kStoreF32> {
         st(row + a * k.pitch, col, v);
     }
     static __device__ __forceinline__ void store_density(T*, const StepConst&, unsigned, float) {}
-    static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v, double) {
+    static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v, double,
+                                                      double) {
         at(row + a * k.pitch, col) = static_cast<float>(v);
     }
 };
@@ -153,6 +155,7 @@ template <> struct Codec<kStoreF32> {
 template <class H> struct CodecGlobal {
     using T = H;
     static constexpr int kRowSlots = 9;
+    static constexpr bool kDestScaled = false;
     static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
         return static_cast<float>(ld(row + a * k.pitch, col)) + k.off[a];
     }
@@ -160,7 +163,8 @@ template <class H> struct CodecGlobal {
         st(row + a * k.pitch, col, static_cast<T>(v - k.off[a]));  // round to nearest even
     }
     static __device__ __forceinline__ void store_density(T*, const StepConst&, unsigned, float) {}
-    static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v, double) {
+    static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v, double,
+                                                      double) {
         at(row + a * k.pitch, col) = static_cast<T>(static_cast<float>(v - (double)k.off[a]));
     }
 };
@@ -174,6 +178,7 @@ template <class H> struct CodecGlobal {
 template <class H> struct CodecLocal {
     using T = H;
     static constexpr int kRowSlots = 11;
+    static constexpr bool kDestScaled = false;
     static __device__ __forceinline__ const float* dens(const T* row, const StepConst& k) {
         return reinterpret_cast<const float*>(row + 9 * k.pitch);
     }
@@ -189,7 +194,7 @@ template <class H> struct CodecLocal {
         st(reinterpret_cast<float*>(row + 9 * k.pitch), 2u * col, rho);
     }
     static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v,
-                                                      double rho) {
+                                                      double rho, double) {
         const double w = a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
         const float r = static_cast<float>(rho);
         at(row + a * k.pitch, col) = static_cast<T>(static_cast<float>(v / (double)r - w));
@@ -197,10 +202,54 @@ template <class H> struct CodecLocal {
     }
 };
 
+// 16-bit relative offsets scaled by the density of the site that will pull the
+// value: slot a of site s holds g_a = f*_a(s) / rhohat(d) - w_a, d = s + e_a
+// (d = s for a population that reflects at a wall), and each site stores
+// rhohat = bf16(rho) of its own density once.  The puller d then decodes all
+// nine populations with its own rhohat: f_a = rhohat(d) (w_a + g_a), one
+// density load per site instead of nine.  The encoder takes rhohat of the
+// eight neighbours from the density window it keeps for the force stencil;
+// every lane computing a site's density gets the same bits, so encoder and
+// decoder use the same scale.  The scale only needs to be consistent, not
+// precise: its bf16 rounding is absorbed in g.
+struct CodecDest {
+    using T = _Float16;
+    static constexpr int kRowSlots = 10;
+    static constexpr bool kDestScaled = true;
+    static __device__ __forceinline__ const __bf16* dens(const T* row, const StepConst& k) {
+        return reinterpret_cast<const __bf16*>(row + 9 * k.pitch);
+    }
+    static __device__ __forceinline__ float round_scale(float rho) {
+        return static_cast<float>(static_cast<__bf16>(rho));
+    }
+    static __device__ __forceinline__ float scale(const T* row, const StepConst& k, unsigned col) {
+        return static_cast<float>(ld(dens(row, k), col));
+    }
+    // g_a only: pull_row forms rhohat g_a + rhohat w_a with the puller's own scale
+    static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
+        return static_cast<float>(ld(row + a * k.pitch, col));
+    }
+    static __device__ __forceinline__ void store(T* row, const StepConst& k, int a, unsigned col, float v,
+                                                 float inv_scale_dest) {
+        st(row + a * k.pitch, col, static_cast<T>(fmaf(v, inv_scale_dest, -lattice_weight(a))));
+    }
+    static __device__ __forceinline__ void store_density(T* row, const StepConst& k, unsigned col, float rho) {
+        st(reinterpret_cast<__bf16*>(row + 9 * k.pitch), col, static_cast<__bf16>(rho));
+    }
+    static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v,
+                                                      double rho, double rho_dest) {
+        const double w = a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        const double sd = (double)round_scale((float)rho_dest);
+        at(row + a * k.pitch, col) = static_cast<T>(static_cast<float>(v / sd - w));
+        if (a == 0) at(reinterpret_cast<__bf16*>(row + 9 * k.pitch), col) = static_cast<__bf16>((float)rho);
+    }
+};
+
 template <> struct Codec<kStoreF16> : CodecGlobal<_Float16> {};
 template <> struct Codec<kStoreBF16> : CodecGlobal<__bf16> {};
 template <> struct Codec<kStoreF16Local> : CodecLocal<_Float16> {};
 template <> struct Codec<kStoreBF16Local> : CodecLocal<__bf16> {};
+template <> struct Codec<kStoreF16Dest> : CodecDest {};
 
 // ---------------------------------------------------------------- streaming (Eq. 5)
 // Velocity ordering: 0 rest; 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1);
@@ -245,6 +294,15 @@ __device__ __forceinline__ void pull_row(const typename Codec<S>::T* __restrict_
     f[4] = C::load(rb, k, top ? 2 : 4, xc);
     f[7] = C::load(rb, k, top ? 5 : 7, x7);
     f[8] = C::load(rb, k, top ? 6 : 8, x8);
+    if constexpr (C::kDestScaled) {
+        const float sc = C::scale(r0, k, xc);
+        const float sw0 = sc * (4.0f / 9.0f), sw1 = sc * (1.0f / 9.0f), sw2 = sc * (1.0f / 36.0f);
+        f[0] = fmaf(f[0], sc, sw0);
+#pragma unroll
+        for (int a = 1; a < 5; ++a) f[a] = fmaf(f[a], sc, sw1);
+#pragma unroll
+        for (int a = 5; a < 9; ++a) f[a] = fmaf(f[a], sc, sw2);
+    }
 }
 
 __device__ __forceinline__ float density(const float f[9])

@@ -58,11 +58,15 @@ __device__ __forceinline__ void strip_tile(
 
     // psi of the row above the strip (y0 - 1), or its mirror at a wall
     float pm = 0.0f;
+    // destination-scaled storage: 1/rhohat of rows y-1, y, y+1 at columns x-1, x, x+1
+    float im = 0.0f, imL = 0.0f, imR = 0.0f, ic = 0.0f, icL = 0.0f, icR = 0.0f;
     int yh = y0 - 1;
     if (!WALLS && yh < 0) yh += k.ny;
     if (yh >= 0) {
         pull_row<S, WALLS>(fin, k, yh, xm, xc, xp, fn);
-        pm = pseudopotential(density(fn), k, bad);
+        const float rm = density(fn);
+        pm = pseudopotential(rm, k, bad);
+        if constexpr (C::kDestScaled) im = recip(C::round_scale(rm));
     }
     pull_row<S, WALLS>(fin, k, y0, xm, xc, xp, f);
     // row y0 + 1 is requested before row y0 is consumed (two rows in flight)
@@ -73,6 +77,14 @@ __device__ __forceinline__ void strip_tile(
     if (WALLS && y0 == 0) pm = pc;
     float pmL = lane_from_left(pm), pmR = lane_from_right(pm);
     float pcL = lane_from_left(pc), pcR = lane_from_right(pc);
+    if constexpr (C::kDestScaled) {
+        ic = recip(C::round_scale(rc));
+        if (WALLS && y0 == 0) im = ic;
+        imL = lane_from_left(im);
+        imR = lane_from_right(im);
+        icL = lane_from_left(ic);
+        icR = lane_from_right(ic);
+    }
 
     double acc[kDiagFields];
     if (MODE == kModeDiag) {
@@ -97,6 +109,12 @@ __device__ __forceinline__ void strip_tile(
             pp = pc;  // mirror beyond the top wall
         }
         const float ppL = lane_from_left(pp), ppR = lane_from_right(pp);
+        float in = 0.0f, inL = 0.0f, inR = 0.0f;
+        if constexpr (C::kDestScaled) {
+            in = has_n ? recip(C::round_scale(rn)) : ic;
+            inL = lane_from_left(in);
+            inR = lane_from_right(in);
+        }
 
         float Fx, Fy, Fs2;
         force_stencil(pmL, pm, pmR, pcL, pc, pcR, ppL, pp, ppR, k, Fx, Fy, Fs2);
@@ -110,8 +128,27 @@ __device__ __forceinline__ void strip_tile(
             collide(f, rc, vx, vy, Fx, Fy, Fs2, k);
             if (live) {
                 typename C::T* row = fout + (long long)y * k.row_stride;
+                if constexpr (C::kDestScaled) {
+                    // 1/rhohat of the site that pulls population a next step: the
+                    // neighbour at x + e_a, or this site for a population that
+                    // reflects at a wall
+                    const bool bot = WALLS && y == 0, top = WALLS && y == k.ny - 1;
+                    float id[9];
+                    id[0] = ic;
+                    id[1] = icR;
+                    id[3] = icL;
+                    id[2] = top ? ic : in;
+                    id[5] = top ? ic : inR;
+                    id[6] = top ? ic : inL;
+                    id[4] = bot ? ic : im;
+                    id[7] = bot ? ic : imL;
+                    id[8] = bot ? ic : imR;
 #pragma unroll
-                for (int a = 0; a < 9; ++a) C::store(row, k, a, xc, f[a], inv_rho);
+                    for (int a = 0; a < 9; ++a) C::store(row, k, a, xc, f[a], id[a]);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) C::store(row, k, a, xc, f[a], inv_rho);
+                }
                 C::store_density(row, k, xc, rc);
             }
         } else if (MODE == kModeMoments) {
@@ -148,6 +185,10 @@ __device__ __forceinline__ void strip_tile(
         pmL = pcL; pm = pc; pmR = pcR;
         pcL = ppL; pc = pp; pcR = ppR;
         rc = rn;
+        if constexpr (C::kDestScaled) {
+            imL = icL; im = ic; imR = icR;
+            icL = inL; ic = in; icR = inR;
+        }
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             f[a] = fn[a];
@@ -343,7 +384,7 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
         const double eu = EX[a] * ux + EY[a] * uy;
         const double feq = W[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
         C::store_init(fout + (long long)y * k.row_stride, k, b, (unsigned)x * (unsigned)sizeof(typename C::T),
-                      feq, (double)rho0[(long long)y * k.nx + x]);
+                      feq, (double)rho0[(long long)y * k.nx + x], r);
     }
 }
 
@@ -396,6 +437,9 @@ static hipError_t dispatch(int store, bool walls, const void* fin, void* fout, c
     case kStoreBF16Local:
         return walls ? launch_mode<kStoreBF16Local, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
                      : launch_mode<kStoreBF16Local, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+    case kStoreF16Dest:
+        return walls ? launch_mode<kStoreF16Dest, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_mode<kStoreF16Dest, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
     default:
         return hipErrorInvalidValue;
     }
@@ -414,6 +458,7 @@ int step_blocks_per_cu(int store, bool walls)
     case kStoreBF16: if (walls) LBMP_OCC(kStoreBF16, true); else LBMP_OCC(kStoreBF16, false); break;
     case kStoreF16Local: if (walls) LBMP_OCC(kStoreF16Local, true); else LBMP_OCC(kStoreF16Local, false); break;
     case kStoreBF16Local: if (walls) LBMP_OCC(kStoreBF16Local, true); else LBMP_OCC(kStoreBF16Local, false); break;
+    case kStoreF16Dest: if (walls) LBMP_OCC(kStoreF16Dest, true); else LBMP_OCC(kStoreF16Dest, false); break;
     default: break;
     }
 #undef LBMP_OCC
@@ -438,6 +483,7 @@ hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n,
     switch (store) {
     case kStoreF32: if (walls) LBMP_BATCH(kStoreF32, true); else LBMP_BATCH(kStoreF32, false); break;
     case kStoreF16Local: if (walls) LBMP_BATCH(kStoreF16Local, true); else LBMP_BATCH(kStoreF16Local, false); break;
+    case kStoreF16Dest: if (walls) LBMP_BATCH(kStoreF16Dest, true); else LBMP_BATCH(kStoreF16Dest, false); break;
     default: return hipErrorInvalidValue;
     }
 #undef LBMP_BATCH
@@ -455,6 +501,7 @@ hipError_t launch_batch_flat(int store, bool walls, const BatchInstance* inst, c
     switch (store) {
     case kStoreF32: if (walls) LBMP_FLAT(kStoreF32, true); else LBMP_FLAT(kStoreF32, false); break;
     case kStoreF16Local: if (walls) LBMP_FLAT(kStoreF16Local, true); else LBMP_FLAT(kStoreF16Local, false); break;
+    case kStoreF16Dest: if (walls) LBMP_FLAT(kStoreF16Dest, true); else LBMP_FLAT(kStoreF16Dest, false); break;
     default: return hipErrorInvalidValue;
     }
 #undef LBMP_FLAT
@@ -492,6 +539,7 @@ hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux
     case kStoreBF16: if (walls) LBMP_INIT(kStoreBF16, true); else LBMP_INIT(kStoreBF16, false); break;
     case kStoreF16Local: if (walls) LBMP_INIT(kStoreF16Local, true); else LBMP_INIT(kStoreF16Local, false); break;
     case kStoreBF16Local: if (walls) LBMP_INIT(kStoreBF16Local, true); else LBMP_INIT(kStoreBF16Local, false); break;
+    case kStoreF16Dest: if (walls) LBMP_INIT(kStoreF16Dest, true); else LBMP_INIT(kStoreF16Dest, false); break;
     default: return hipErrorInvalidValue;
     }
 #undef LBMP_INIT

@@ -48,8 +48,20 @@ size_t elem_bytes(int store) { return store == LB_STORE_F32 ? 4 : 2; }
 bool local_density(int store) { return store == LB_STORE_F16_LOCAL || store == LB_STORE_BF16_LOCAL; }
 
 // storage-type row slots per lattice row: nine population rows, plus an FP32
-// density row (two 16-bit slots) for the local-density encodings
-int row_slots(int store) { return local_density(store) ? 11 : 9; }
+// density row (two 16-bit slots) for the local-density encodings, or a bf16
+// density-scale row (one slot) for the destination-scaled encoding
+int row_slots(int store)
+{
+    if (local_density(store)) return 11;
+    return store == LB_STORE_F16_DEST ? 10 : 9;
+}
+
+// bytes per site of the exported density plane (0: none)
+size_t density_plane_bytes(int store)
+{
+    if (local_density(store)) return sizeof(float);
+    return store == LB_STORE_F16_DEST ? 2 : 0;
+}
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
@@ -94,7 +106,7 @@ lb_status validate(const lb_params* p)
     if ((long long)pitch_of(p->nx) * (p->store == LB_STORE_F32 ? 4 : 2) >= (1LL << 32))
         return fail(LB_EINVAL, "a padded row must stay below 4 GiB");
     if (p->bc != LB_BC_PERIODIC && p->bc != LB_BC_WALLS_Y) return fail(LB_EINVAL, "unknown bc");
-    if (p->store < LB_STORE_F32 || p->store > LB_STORE_BF16_LOCAL) return fail(LB_EINVAL, "unknown store");
+    if (p->store < LB_STORE_F32 || p->store > LB_STORE_F16_DEST) return fail(LB_EINVAL, "unknown store");
     if (!finite_all({p->a, p->b, p->R, p->T, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta, p->s_j,
                      p->s_q, p->nu_l, p->nu_g, p->rho_switch, p->rho_ref}))
         return fail(LB_EINVAL, "non-finite parameter");
@@ -153,16 +165,23 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
 // strips, down to 2 rows.
 int auto_strip_rows(const lb_params& p)
 {
+    // preferred height (measured on the 8192 x 4096 splash): 3 rows for FP32 and
+    // the source-density encodings; the issue-bound 16-bit encodings gain from
+    // fewer recomputed halo rows: 4 rows for the global offsets, 8 for the
+    // destination-scaled one
+    int preferred = kMinStripRows;
+    if (p.store == LB_STORE_F16_DEST) preferred = 8;
+    else if (p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET) preferred = 4;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-        return kMinStripRows;
+        return preferred;
     const int nb = std::max(1, lbmp::step_blocks_per_cu(p.store, p.bc == LB_BC_WALLS_Y));
     const long long resident = (long long)nb * lbmp::kWavesPerBlock * ncu;
     const long long tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
     const long long strips_wanted = (resident + tiles_x - 1) / tiles_x;
     const long long h = std::max<long long>(2, p.ny / strips_wanted);
-    return (int)std::min<long long>(h, kMinStripRows);
+    return (int)std::min<long long>(h, preferred);
 }
 
 }  // namespace
@@ -275,8 +294,7 @@ size_t lb_workspace_bytes(const lb_params* p)
 size_t lb_state_bytes(const lb_params* p)
 {
     if (validate(p) != LB_OK) return 0;
-    return (size_t)9 * p->nx * p->ny * elem_bytes(p->store) +
-           (local_density(p->store) ? (size_t)p->nx * p->ny * sizeof(float) : 0);
+    return (size_t)9 * p->nx * p->ny * elem_bytes(p->store) + (size_t)p->nx * p->ny * density_plane_bytes(p->store);
 }
 
 }  // extern "C"
@@ -456,7 +474,8 @@ lb_status lb_check(lb_ctx* c)
 int64_t lb_time(const lb_ctx* c) { return c ? c->t : -1; }
 
 // The exported state is [9][ny][nx] (then [ny][nx] FP32 densities for the
-// local-density encodings); the stored one is [ny][row_slots][pitch].
+// local-density encodings, or [ny][nx] bf16 scales for the destination-scaled
+// one); the stored one is [ny][row_slots][pitch].
 static hipError_t copy_state(lb_ctx* c, void* dst, const void* src, bool out)
 {
     const size_t eb = elem_bytes(c->p.store);
@@ -471,11 +490,12 @@ static hipError_t copy_state(lb_ctx* c, void* dst, const void* src, bool out)
         e = out ? hipMemcpy2DAsync(x, nx * eb, b, row, nx * eb, ny, hipMemcpyDeviceToDevice, c->stream)
                 : hipMemcpy2DAsync(b, row, x, nx * eb, nx * eb, ny, hipMemcpyDeviceToDevice, c->stream);
     }
-    if (e == hipSuccess && local_density(c->p.store)) {
+    const size_t db = density_plane_bytes(c->p.store);
+    if (e == hipSuccess && db) {
         char* b = buf + 9 * pitch * eb;
         char* x = ext + 9 * ny * nx * eb;
-        e = out ? hipMemcpy2DAsync(x, nx * 4, b, row, nx * 4, ny, hipMemcpyDeviceToDevice, c->stream)
-                : hipMemcpy2DAsync(b, row, x, nx * 4, nx * 4, ny, hipMemcpyDeviceToDevice, c->stream);
+        e = out ? hipMemcpy2DAsync(x, nx * db, b, row, nx * db, ny, hipMemcpyDeviceToDevice, c->stream)
+                : hipMemcpy2DAsync(b, row, x, nx * db, nx * db, ny, hipMemcpyDeviceToDevice, c->stream);
     }
     return e;
 }
@@ -651,8 +671,8 @@ lb_status validate_batch(const lb_params* p, int32_t n)
         if (p[i].store != p[0].store || p[i].bc != p[0].bc)
             return fail(LB_EINVAL, "all lattices of a batch share store and bc");
     }
-    if (p[0].store != LB_STORE_F32 && p[0].store != LB_STORE_F16_LOCAL)
-        return fail(LB_EINVAL, "batched storage must be LB_STORE_F32 or LB_STORE_F16_LOCAL");
+    if (p[0].store != LB_STORE_F32 && p[0].store != LB_STORE_F16_LOCAL && p[0].store != LB_STORE_F16_DEST)
+        return fail(LB_EINVAL, "batched storage must be LB_STORE_F32, LB_STORE_F16_LOCAL or LB_STORE_F16_DEST");
     return LB_OK;
 }
 

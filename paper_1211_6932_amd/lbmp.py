@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(_HERE, "liblbmp.so")
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
 LB_BC_PERIODIC, LB_BC_WALLS_Y = 0, 1
 LB_STORE_F32, LB_STORE_F16_OFFSET, LB_STORE_BF16_OFFSET = 0, 1, 2
-LB_STORE_F16_LOCAL, LB_STORE_BF16_LOCAL = 3, 4
+LB_STORE_F16_LOCAL, LB_STORE_BF16_LOCAL, LB_STORE_F16_DEST = 3, 4, 5
 STORE_NAMES = {"f32": LB_STORE_F32, "f16": LB_STORE_F16_OFFSET, "bf16": LB_STORE_BF16_OFFSET,
-               "f16local": LB_STORE_F16_LOCAL, "bf16local": LB_STORE_BF16_LOCAL}
+               "f16local": LB_STORE_F16_LOCAL, "bf16local": LB_STORE_BF16_LOCAL, "f16dest": LB_STORE_F16_DEST}
 STATUS_NAMES = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EHIP", -4: "LB_EUNSTABLE",
                 -5: "LB_ESTATE"}
 

@@ -61,7 +61,7 @@ def test_validate_accepts_paper_parameters():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 2), ("ny", 0), ("nx", (1 << 20) + 1), ("bc", 2), ("store", 5), ("store", -1), ("b", 0.0), ("T", -1.0),
+    ("nx", 2), ("ny", 0), ("nx", (1 << 20) + 1), ("bc", 2), ("store", 6), ("store", -1), ("b", 0.0), ("T", -1.0),
     ("G", 0.0), ("G", 1.0), ("sigma", -0.1), ("s_e", 0.0), ("s_e", 2.0), ("s_q", 2.5),
     ("s_rho", -1.0), ("s_j", 2.0), ("nu_l", 0.0), ("nu_g", -0.1), ("a", float("nan")),
     ("R", 0.0), ("T", float("inf")),

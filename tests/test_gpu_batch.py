@@ -50,7 +50,7 @@ def single_state(w, store, steps):
 
 
 @pytest.mark.parametrize("mode", [B.LB_BATCH_STEPWISE, B.LB_BATCH_PERSISTENT])
-@pytest.mark.parametrize("store,bc", [("f32", 0), ("f32", 1), ("f16local", 0)])
+@pytest.mark.parametrize("store,bc", [("f32", 0), ("f32", 1), ("f16local", 0), ("f16dest", 0), ("f16dest", 1)])
 def test_batch_is_bitwise_equal_to_single_runs(store, bc, mode):
     ws = mixed_lattices(bc)
     print(f"[gpu-case] batch bitwise store={store} bc={bc} mode={mode} n={len(ws)}", flush=True)

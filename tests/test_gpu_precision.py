@@ -2,17 +2,22 @@
 
 Encodings (collision and force stay FP32):
   f16 / bf16            h_a = RNE16(f*_a - w_a rho_ref), one reference density;
-  f16local / bf16local  g_a = RNE16(f*_a / rho - w_a) with the site's rho in FP32.
+  f16local / bf16local  g_a = RNE16(f*_a / rho - w_a) with the site's rho in FP32;
+  f16dest               g_a = RNE16(f*_a / rhohat(x + e_a) - w_a), scaled by the bf16
+                        density of the site that pulls the value (the site itself for a
+                        population that reflects at a wall).
 
 Bounds:
   * one step from the same (decoded) state: each stored value is the oracle's
     post-collision value rounded once to 16 bits, so
       |decoded - oracle| <= 0.5 ulp16(encoded value) * scale + 2e-6 max|f|
-    (scale = 1 for the global offsets, rho for the relative local ones; the
-    second term is the FP32 arithmetic, as in the FP32 one-step test);
+    (scale = 1 for the global offsets, rho for the relative local ones, the
+    puller's rhohat for f16dest; the second term is the FP32 arithmetic, as in
+    the FP32 one-step test);
   * at rest with rho = rho_ref (global) or any uniform rho (local) the stored
     offsets vanish up to FP32 rounding of the weights (|offset| <= 1e-6, against
-    O(1e-2) offsets in a flow);
+    O(1e-2) offsets in a flow); for f16dest they equal w_a (rho / rhohat - 1),
+    the bf16 rounding of the scale, and decode to w_a rho;
   * f16local: Laplace pressure jump of an equilibrated droplet within 1 % of the
     FP64 oracle (the accuracy target for reduced-precision storage)."""
 import numpy as np
@@ -30,6 +35,9 @@ B = pytest.importorskip("paper_1211_6932_amd.lbmp")
 WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 GLOBAL = ("f16", "bf16")
 LOCAL = ("f16local", "bf16local")
+DEST = ("f16dest",)
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -55,7 +63,7 @@ def make_sim(w, store, strip_rows=0):
 
 
 def raw_state(s, store):
-    """(encoded [9][ny][nx] as float64, densities [ny][nx] or None)."""
+    """(encoded [9][ny][nx] as float64, densities or scales [ny][nx], or None)."""
     buf = s.get_state()
     n = 9 * s.ny * s.nx
     h16 = buf[: 2 * n].view(torch.float16 if store.startswith("f16") else torch.bfloat16)
@@ -63,12 +71,29 @@ def raw_state(s, store):
     rho = None
     if store in LOCAL:
         rho = buf[2 * n:].view(torch.float32).cpu().numpy().astype(np.float64).reshape(s.ny, s.nx)
+    elif store in DEST:
+        rho = buf[2 * n:].view(torch.bfloat16).float().cpu().numpy().astype(np.float64).reshape(s.ny, s.nx)
     return enc, rho
 
 
-def decode(enc, rho, store, rho_ref):
+def dest_scales(scale, walls):
+    """[9][ny][nx]: the scale of the site that pulls slot a of each site."""
+    ny = scale.shape[0]
+    out = np.empty((9,) + scale.shape)
+    y = np.arange(ny)[:, None]
+    for a in range(9):
+        out[a] = np.roll(scale, shift=(-EY[a], -EX[a]), axis=(0, 1))
+        if walls:
+            beyond = (y + EY[a] < 0) | (y + EY[a] >= ny)
+            out[a] = np.where(beyond, scale, out[a])
+    return out
+
+
+def decode(enc, rho, store, rho_ref, walls=False):
     if store in LOCAL:
         return rho[None] * (WEIGHTS[:, None, None] + enc)
+    if store in DEST:
+        return dest_scales(rho, walls) * (WEIGHTS[:, None, None] + enc)
     return enc + (WEIGHTS * rho_ref)[:, None, None]
 
 
@@ -81,7 +106,7 @@ def ulp16(x, store):
     return 2.0 ** (e - 10)
 
 
-@pytest.mark.parametrize("store", GLOBAL + LOCAL)
+@pytest.mark.parametrize("store", GLOBAL + LOCAL + DEST)
 @pytest.mark.parametrize("case", ["droplet_periodic", "splash_walls"])
 def test_one_step_is_the_oracle_rounded_once(store, case):
     if case == "droplet_periodic":
@@ -97,13 +122,18 @@ def test_one_step_is_the_oracle_rounded_once(store, case):
     s.step(1)
     e6, r6 = raw_state(s, store)
     p = O.Params(**w.params)
-    f5 = O.stream(p, decode(e5, r5, store, rho_ref))
+    walls = w.params["bc"] == 1
+    f5 = O.stream(p, decode(e5, r5, store, rho_ref, walls))
     ny, nx = w.params["ny"], w.params["nx"]
     ref = O.collide_at(p, f5, np.arange(nx * ny)).T.reshape(9, ny, nx)
-    got = decode(e6, r6, store, rho_ref)
+    got = decode(e6, r6, store, rho_ref, walls)
     if store in LOCAL:
         enc_ref = ref / r6[None] - WEIGHTS[:, None, None]
         bound = 0.5 * ulp16(enc_ref, store) * r6[None]
+    elif store in DEST:
+        sd = dest_scales(r6, walls)
+        enc_ref = ref / sd - WEIGHTS[:, None, None]
+        bound = 0.5 * ulp16(enc_ref, store) * sd
     else:
         bound = 0.5 * ulp16(ref - (WEIGHTS * rho_ref)[:, None, None], store)
     bound = bound + 2e-6 * np.abs(ref).max()
@@ -111,7 +141,7 @@ def test_one_step_is_the_oracle_rounded_once(store, case):
     assert excess.max() <= 0.0, (store, case, float(excess.max()))
 
 
-@pytest.mark.parametrize("store", GLOBAL + LOCAL)
+@pytest.mark.parametrize("store", GLOBAL + LOCAL + DEST)
 def test_offsets_vanish_at_rest(store):
     rho = 0.3
     p = W.base_params(70, 20)
@@ -119,12 +149,19 @@ def test_offsets_vanish_at_rest(store):
     s = make_sim(wl, store)
     s.step(3)
     enc, dens = raw_state(s, store)
+    if store in DEST:
+        scale = float(torch.tensor(rho, dtype=torch.float32).to(torch.bfloat16).float())
+        assert np.abs(dens - scale).max() == 0.0
+        assert np.abs(enc - WEIGHTS[:, None, None] * (rho / scale - 1.0)).max() <= 2e-6
+        assert np.abs(decode(enc, dens, store, 0.0) - WEIGHTS[:, None, None] * rho).max() <= 5e-7
+        return
     assert np.abs(enc).max() <= 1e-6
     if dens is not None:
         assert np.abs(dens - rho).max() <= 1e-7
 
 
-def test_f16local_laplace_jump_within_one_percent():
+@pytest.mark.parametrize("store", ["f16local", "f16dest"])
+def test_16bit_laplace_jump_within_one_percent(store):
     """Droplet 96 x 96, R0 = 20, a = 0.5, T = 0.6 T_c.  The FP64 oracle's pressure jump
     has converged to 1e-3 by step 5000.  With FP16 relative-offset storage the jump
     keeps fluctuating by about 1 % from step to step (storage rounding feeds weak
@@ -133,7 +170,8 @@ def test_f16local_laplace_jump_within_one_percent():
     w = W.stationary_droplet(n=96, R0=20)
     o = O.State(O.Params(**w.params), f32(w.rho0).astype(np.float64)).step(5000)
     lo = post.laplace(o.moments()[0], w.params, 20.0)
-    s = make_sim(w, "f16local")
+    print(f"[gpu-case] Laplace 96x96 store={store}", flush=True)
+    s = make_sim(w, store)
     s.step(8000)
     samples = []
     for k in range(41):
@@ -144,7 +182,7 @@ def test_f16local_laplace_jump_within_one_percent():
     s.check()
     dp = np.array([d["dp"] for d in samples])
     rel = dp.mean() / lo["dp"] - 1.0
-    print(f"f16local Laplace dp mean {dp.mean():.6e} (min {dp.min():.4e} max {dp.max():.4e}) "
+    print(f"{store} Laplace dp mean {dp.mean():.6e} (min {dp.min():.4e} max {dp.max():.4e}) "
           f"vs oracle {lo['dp']:.6e}: {rel:+.3e}")
     assert abs(rel) <= 0.01
     assert np.abs(dp / lo["dp"] - 1.0).max() <= 0.03
