@@ -13,6 +13,7 @@ force, MRT collision with the improved forcing, store).  The metric is MLUPS
     python bench.py [--steps K] [--warmup W] [--store f32|f16|bf16|f16local|bf16local] [--no-cpu-baseline]
     python bench.py --workload batch [--instances 512] [--steps 10000]
     python bench.py --workload learned [--train-runs 4096] [--eval-droplets 256] [--relax-steps 30000]
+    python bench.py --workload lamb      (droplet oscillation against Lamb, Sec. IV.A)
 
 The batch workload advances 512 independent droplet lattices (seed 1211: sides 64-512,
 a in {0.25, 0.5, 1}, T/Tc in [0.5, 0.85], half of them elliptic) in one persistent launch
@@ -209,9 +210,48 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_lamb(args):
+    import torch
+
+    import workloads as W
+    from paper_1211_6932_amd import lbmp
+    from paper_1211_6932_amd import validation as V
+
+    torch.cuda.set_device(0)
+    lbmp.load()
+    R0 = W.oscillating_droplet().info["R0"]
+    t0 = time.perf_counter()
+    st = V.surface_tension(W.laplace_droplets(radii=(20.0, 25.0, R0, 30.0, 35.0)), log=log)
+    theta = [p["theta"] for p in st["points"] if p["R0"] == R0][0]
+    runs = {}
+    for nu in (0.05, 0.1):
+        w = W.oscillating_droplet(nu_l=nu)
+        o = V.oscillation(w, log=log)
+        ta = V.lamb_period(theta, o["rho_l"], R0)
+        runs[str(nu)] = {"period_damped": round(o["period"], 1), "period_undamped": round(o["period0"], 1),
+                         "lamb": round(ta, 1), "rel_error": round(o["period0"] / ta - 1.0, 5),
+                         "decay_steps": round(o["decay"], 0), "viscous_decay_steps": round(R0 ** 2 / (4 * nu), 0),
+                         "rho_l": round(o["rho_l"], 5)}
+    wall = time.perf_counter() - t0
+    err = max(abs(r["rel_error"]) for r in runs.values())
+    out = {
+        "metric": "droplet oscillation period vs Lamb's Eq. (32), max relative error over nu_l = 0.05, 0.1",
+        "value": round(err, 5), "unit": "fraction", "n_gpus": 1, "steps": 10400, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "200x200 ellipse 30x27, T=0.5Tc, a=0.5, nu_g=0.3 (Sec. IV.A, Fig. 2)",
+                   "parallelism": "single GPU"},
+        "surface_tension": {"theta_at_R0": theta, "laplace_slope": st["theta"], "laplace_intercept": st["c"],
+                            "r2": st["r2"]},
+        "runs": runs, "paper": {"numerical": 2600.0, "analytical": 2593.8}, "wall_seconds": round(wall, 2),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="splash", choices=["splash", "batch", "learned"])
+    ap.add_argument("--workload", default="splash", choices=["splash", "batch", "learned", "lamb"])
     ap.add_argument("--train-runs", type=int, default=4096)
     ap.add_argument("--eval-droplets", type=int, default=256)
     ap.add_argument("--relax-steps", type=int, default=30000)
@@ -236,6 +276,8 @@ def main():
         return bench_batch(args)
     if args.workload == "learned":
         return bench_learned(args)
+    if args.workload == "lamb":
+        return bench_lamb(args)
 
     import numpy as np
     import torch

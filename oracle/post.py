@@ -11,7 +11,12 @@ Readings (the paper does not define these precisely):
     p_out = mean over d >= R0 + 3W (W = 5, the tanh width of Eq. (31));
   * R_eff = sqrt((sum rho - rho_out N) / (pi (rho_in - rho_out)));
   * interface thickness = distance between the 10 % and 90 % crossings of
-    (rho - rho_g)/(rho_l - rho_g), linearly interpolated.
+    (rho - rho_g)/(rho_l - rho_g), linearly interpolated;
+  * droplet oscillation (Sec. IV.A, Fig. 2): the interface on the major axis is
+    where the density on the horizontal line through the centre (linear in y
+    between the two rows around it) first falls below a level, going outwards,
+    linearly interpolated in x; the period is twice the mean spacing of the
+    successive crossings of the signal's mean.
 """
 from __future__ import annotations
 
@@ -90,3 +95,36 @@ def linear_fit(x, y):
     yhat = s * x + c
     r2 = 1.0 - ((y - yhat) ** 2).sum() / ((y - y.mean()) ** 2).sum()
     return float(s), float(c), float(r2)
+
+
+def major_axis_radius(rho, cx, cy, level):
+    """Distance from (cx, cy) along +x to the first crossing of `level` (see module notes)."""
+    ny, nx = rho.shape
+    j = int(np.floor(cy))
+    fy = cy - j
+    line = (1.0 - fy) * rho[j % ny] + fy * rho[(j + 1) % ny]
+    i0 = int(np.floor(cx))
+    xs = np.arange(i0, i0 + nx + 1, dtype=np.float64)
+    vals = line[(np.arange(i0, i0 + nx + 1)) % nx]
+    # the centre itself, then the lattice columns to its right
+    v_c = vals[0] + (cx - i0) * (vals[1] - vals[0])
+    xs = np.concatenate([[cx], xs[1:]])
+    vals = np.concatenate([[v_c], vals[1:]])
+    below = np.nonzero(vals < level)[0]
+    if below.size == 0:
+        raise ValueError("no crossing on the major axis")
+    k = int(below[0])
+    x = xs[k - 1] + (vals[k - 1] - level) / (vals[k - 1] - vals[k]) * (xs[k] - xs[k - 1])
+    return float(x - cx)
+
+
+def oscillation_period(t, r):
+    """Twice the mean spacing of successive crossings (either direction) of r - mean(r)."""
+    t = np.asarray(t, dtype=np.float64)
+    v = np.asarray(r, dtype=np.float64) - float(np.mean(r))
+    s = np.sign(v)
+    idx = np.nonzero(s[:-1] * s[1:] < 0)[0]
+    if idx.size < 3:
+        raise ValueError("too few crossings")
+    tc = t[idx] - v[idx] * (t[idx + 1] - t[idx]) / (v[idx + 1] - v[idx])
+    return float(2.0 * np.mean(np.diff(tc)))

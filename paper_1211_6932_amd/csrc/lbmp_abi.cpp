@@ -716,9 +716,11 @@ lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* wor
     b->wg_first = reinterpret_cast<int*>(ws + hoff);
     b->wg_capacity = batch_wg_capacity(p, n);
     b->mode = LB_BATCH_STEPWISE;
-    if (hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess) {
+    hipError_t ee = hipEventCreate(&b->ev[0]);
+    if (ee == hipSuccess) ee = hipEventCreate(&b->ev[1]);
+    if (ee != hipSuccess) {
         lb_batch_destroy(b);
-        return fail(LB_EHIP, "hipEventCreate");
+        return hip_fail(ee, "hipEventCreate");
     }
     size_t off = batch_header_bytes(p, n);
     b->inst.assign(n, nullptr);

@@ -251,3 +251,29 @@ def learned_eval_instances(n=256, seed=1213, side=256):
         ratio = float(rng.uniform(1.0, 15.0))
         out.append(_droplet_case(side, a, tb, R0, ratio))
     return out
+
+
+def oscillating_droplet(n=200, r_max=30.0, r_min=27.0, t_over_tc=0.5, a=0.5, nu_l=0.1, nu_g=0.3) -> Workload:
+    """Droplet oscillation (Sec. IV.A, Fig. 2): n x n periodic, an ellipse with semi-axes
+    r_max (x) and r_min (y) at the centre, tanh profile (Eq. 31) between the Maxwell
+    densities; equilibrium radius R0 = sqrt(r_max r_min)."""
+    p = base_params(n, n, a=a, t_over_tc=t_over_tc, nu_l=nu_l, nu_g=nu_g)
+    rl, rg = coexistence(t_over_tc)
+    R0 = math.sqrt(r_max * r_min)
+    rho0 = ellipse_field(n, n, R0, r_max / r_min, rl, rg)
+    c = (n - 1) / 2.0
+    return Workload(f"oscillating_droplet_{n}_{r_max:g}x{r_min:g}_nu{nu_l:g}", p, rho0,
+                    info=dict(R0=R0, r_max=r_max, r_min=r_min, rho_l=rl, rho_g=rg, t_over_tc=t_over_tc,
+                              cx=c, cy=c))
+
+
+def laplace_droplets(radii=(20.0, 25.0, 30.0, 35.0), n=200, t_over_tc=0.5, a=0.5, nu_l=0.1, nu_g=0.3):
+    """Stationary droplets of several radii for a Laplace-law fit of the surface tension
+    (Sec. IV.B/C evaluate it with Laplace's law)."""
+    out = []
+    for R in radii:
+        w = stationary_droplet(n=n, R0=R, a=a, t_over_tc=t_over_tc, nu_l=nu_l, nu_g=nu_g)
+        c = (n - 1) / 2.0
+        w.info.update(cx=c, cy=c)
+        out.append(w)
+    return out
