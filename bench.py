@@ -14,6 +14,7 @@ force, MRT collision with the improved forcing, store).  The metric is MLUPS
     python bench.py --workload batch [--instances 512] [--steps 10000]
     python bench.py --workload learned [--train-runs 4096] [--eval-droplets 256] [--relax-steps 30000]
     python bench.py --workload lamb      (droplet oscillation against Lamb, Sec. IV.A)
+    python bench.py --workload sweeps    (coexistence curves, stability edges, Table I, Fig. 4)
 
 The batch workload advances 512 independent droplet lattices (seed 1211: sides 64-512,
 a in {0.25, 0.5, 1}, T/Tc in [0.5, 0.85], half of them elliptic) in one persistent launch
@@ -210,6 +211,67 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweeps(args):
+    import json as _json
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1211_6932_amd import lbmp
+    from paper_1211_6932_amd import sweeps as S
+
+    torch.cuda.set_device(0)
+    lbmp.load()
+    golden = _json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))
+    t0 = time.perf_counter()
+    improved_T = [0.49, 0.5, 0.55, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9, 0.95]
+    edge_T = [round(0.76 + 0.0025 * i, 4) for i in range(29)]
+    groups = {"improved_0.8": W.coexistence_droplets(improved_T, tau_nu=0.8),
+              "original_0.6": W.coexistence_droplets(edge_T, sigma=0.0, tau_nu=0.6),
+              "original_0.8": W.coexistence_droplets(edge_T, sigma=0.0, tau_nu=0.8),
+              "table1": [w for a in (1.0, 0.5, 0.25) for w in W.coexistence_droplets([0.5, 0.55], tau_nu=0.8, a=a)]}
+    ws = [w for g in groups.values() for w in g]
+    res, k, out_groups = S.droplet_sweep(ws, log=log), 0, {}
+    for name, g in groups.items():
+        out_groups[name] = res[k:k + len(g)]
+        k += len(g)
+    t_sweep = time.perf_counter() - t0
+    curve = [{"T_over_Tc": r["t_over_tc"], "rho_l": r["rho_l"], "rho_g": r["rho_g"],
+              "maxwell": W.coexistence(r["t_over_tc"])} for r in out_groups["improved_0.8"]]
+    edges = {}
+    for tau in ("0.6", "0.8"):
+        rows = out_groups[f"original_{tau}"]
+        t_low = S.lowest_stable(rows)
+        edges[tau] = {"lowest_T_over_Tc": t_low,
+                      "ratio": [r["ratio"] for r in rows if r["t_over_tc"] == t_low][0]}
+    table1 = [{"a": r["a"], "T_over_Tc": r["t_over_tc"], "max_u": r["max_u"]} for r in out_groups["table1"]]
+    nus = [float(v) for v in np.geomspace(0.0015, 0.15, 12)]
+    ratios = (1, 20, 50)
+    t1 = time.perf_counter()
+    failed = S.survival([W.paper_splash(nu, r) for r in ratios for nu in nus], 4000)
+    t_visc = time.perf_counter() - t1
+    visc = {str(r): S.lowest_stable_viscosity(nus, failed[i * len(nus):(i + 1) * len(nus)])
+            for i, r in enumerate(ratios)}
+    t2 = {row[0]: row for row in golden["table2"]["rows"]}
+    by_t = {c["T_over_Tc"]: c for c in curve}
+    worst_l = max(abs(by_t[t]["rho_l"] / t2[t][1] - 1) for t in t2)
+    out = {
+        "metric": "coexistence densities vs Table II (max relative error, liquid, tau_nu = 0.8)",
+        "value": round(worst_l, 5), "unit": "fraction", "n_gpus": 1, "steps": 40000, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(ws)} droplets 200x200 R=50 (Sec. IV.A/B) + 36 splash runs 600x250 "
+                               "(Sec. IV.C), one batched launch each", "parallelism": "single GPU"},
+        "improved_curve_tau0.8": curve, "original_edge": edges,
+        "paper_original_edge": {"T_over_Tc": 0.8, "ratio_tau0.6": 30.0, "ratio_tau0.8": 56.5},
+        "table1": table1, "lowest_nu_l": visc, "paper_lowest_nu_l": {"1": 0.075, "20": 0.009, "50": 0.0039},
+        "wall_seconds": {"droplet_sweep": round(t_sweep, 2), "viscosity_search": round(t_visc, 2)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_lamb(args):
     import torch
 
@@ -251,7 +313,7 @@ def bench_lamb(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="splash", choices=["splash", "batch", "learned", "lamb"])
+    ap.add_argument("--workload", default="splash", choices=["splash", "batch", "learned", "lamb", "sweeps"])
     ap.add_argument("--train-runs", type=int, default=4096)
     ap.add_argument("--eval-droplets", type=int, default=256)
     ap.add_argument("--relax-steps", type=int, default=30000)
@@ -278,6 +340,8 @@ def main():
         return bench_learned(args)
     if args.workload == "lamb":
         return bench_lamb(args)
+    if args.workload == "sweeps":
+        return bench_sweeps(args)
 
     import numpy as np
     import torch

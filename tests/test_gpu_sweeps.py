@@ -1,0 +1,145 @@
+"""The paper's stationary-droplet sweeps on the batched GPU path (Sec. IV.A, Fig. 1;
+Sec. IV.B, Tables I and II), against the printed values in tests/golden/.
+
+Setup (Sec. IV.A): 200 x 200 periodic, a droplet of radius 50 at the centre, tanh
+start (Eq. 31), a = 0.5 unless stated, one viscosity (tau_nu) in both phases,
+s_e = s_zeta = s_q = 1.1, 40,000 steps, densities averaged over the last 10,000.
+
+Bounds:
+  * improved scheme (sigma = 0.11): stable from T/T_c = 0.49 up; Table II numerical
+    densities (tau_nu = 0.8) within 0.2 % (liquid) and 3 % (vapour); liquid branch
+    within 0.5 % of the Maxwell construction over the sweep, vapour within 15 %;
+  * original scheme (sigma = 0): the lowest surviving T/T_c lies within 0.03 of the
+    printed 0.8 for both tau_nu; at that edge the density ratio is within 15 % of the
+    printed 30.0 (tau_nu = 0.6) and at least 85 % of 56.5 (tau_nu = 0.8); its vapour
+    branch misses the Maxwell value by more than 20 % at T/T_c = 0.82 (the paper:
+    "significantly deviate");
+  * Table I spurious velocities within 15 % of the printed values, and a = 1 -> 0.25
+    lowers them by a factor 10 to 25 (the paper: 15 ~ 20).
+The same sigma = 0 step is also checked site by site against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import lbref as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1211_6932_amd.lbmp")
+S = pytest.importorskip("paper_1211_6932_amd.sweeps")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    B.load()
+    yield
+
+
+@pytest.fixture(scope="module")
+def sweep():
+    improved_T = [0.49, 0.5, 0.55, 0.6, 0.7, 0.8, 0.9]
+    edge_T = [round(0.76 + 0.0025 * i, 4) for i in range(29)]
+    groups = {
+        "improved_0.6": W.coexistence_droplets(improved_T, tau_nu=0.6),
+        "improved_0.8": W.coexistence_droplets(improved_T, tau_nu=0.8),
+        "original_0.6": W.coexistence_droplets(edge_T, sigma=0.0, tau_nu=0.6),
+        "original_0.8": W.coexistence_droplets(edge_T, sigma=0.0, tau_nu=0.8),
+        "table1": [w for a in (1.0, 0.5, 0.25) for w in W.coexistence_droplets([0.5, 0.55], tau_nu=0.8, a=a)],
+    }
+    ws = [w for g in groups.values() for w in g]
+    print(f"[gpu-case] droplet sweep of {len(ws)} lattices, 200x200, 40000 steps", flush=True)
+    res = S.droplet_sweep(ws)
+    out, k = {}, 0
+    for name, g in groups.items():
+        out[name] = res[k:k + len(g)]
+        k += len(g)
+    return out
+
+
+def test_improved_scheme_coexistence(sweep, golden):
+    for tau in ("0.6", "0.8"):
+        rows = sweep[f"improved_{tau}"]
+        assert all(r["stable"] for r in rows), tau
+        for r in rows:
+            ml, mg = W.coexistence(r["t_over_tc"])
+            assert abs(r["rho_l"] / ml - 1) <= 5e-3, (tau, r)
+            assert abs(r["rho_g"] / mg - 1) <= 0.15, (tau, r)
+    by_t = {r["t_over_tc"]: r for r in sweep["improved_0.8"]}
+    for row in golden["table2"]["rows"]:
+        t, num_l, num_g = row[0], row[1], row[2]
+        r = by_t[t]
+        print(f"T/Tc {t}: rho_l {r['rho_l']:.5f} (Table II {num_l}), rho_g {r['rho_g']:.6f} (Table II {num_g})")
+        assert abs(r["rho_l"] / num_l - 1) <= 2e-3
+        assert abs(r["rho_g"] / num_g - 1) <= 0.03
+    low = by_t[golden["original_scheme_lowest_T"]["improved"]]
+    assert low["stable"] and low["ratio"] >= 700  # the paper: rho_l / rho_g ~ 900 at 0.49
+
+
+def test_original_scheme_stability_edge(sweep, golden):
+    printed = golden["original_scheme_lowest_T"]["original"]
+    edge = {}
+    for tau in ("0.6", "0.8"):
+        rows = sweep[f"original_{tau}"]
+        t_low = S.lowest_stable(rows)
+        r = [x for x in rows if x["t_over_tc"] == t_low][0]
+        edge[tau] = r
+        print(f"original scheme tau_nu={tau}: lowest surviving T/Tc {t_low}, density ratio {r['ratio']:.1f}")
+        assert abs(t_low - printed) <= 0.03
+    assert abs(edge["0.6"]["ratio"] / 30.0 - 1) <= 0.15
+    assert edge["0.8"]["ratio"] >= 0.85 * 56.5
+    # the vapour branch of the original scheme is far from the Maxwell construction
+    r = [x for x in sweep["original_0.8"] if x["t_over_tc"] == 0.82][0]
+    assert abs(r["rho_g"] / W.coexistence(0.82)[1] - 1) > 0.2
+
+
+def test_table1_spurious_velocities(sweep, golden):
+    cols = golden["table1"]["columns"]
+    got = {(r["a"], r["t_over_tc"]): r["max_u"] for r in sweep["table1"]}
+    for row in golden["table1"]["rows"]:
+        t = row[0]
+        for a in (1.0, 0.5, 0.25):
+            printed = row[cols.index(f"a{a}")]
+            print(f"T/Tc {t} a {a}: max|u| {got[(a, t)]:.4e} (Table I {printed})")
+            assert abs(got[(a, t)] / printed - 1) <= 0.15
+        assert 10.0 <= got[(1.0, t)] / got[(0.25, t)] <= 25.0
+
+
+def test_original_scheme_step_matches_oracle():
+    """sigma = 0 (original forcing) through the C ABI against the FP64 oracle, 1000 steps."""
+    print("[gpu-case] original scheme parity 96x96 1000 steps", flush=True)
+    w = W.coexistence_droplets([0.85], sigma=0.0, tau_nu=0.6, n=96, R0=24.0)[0]
+    r0 = w.rho0.astype(np.float32)
+    s = B.Sim(w.params, torch.from_numpy(r0))
+    s.step(1000)
+    s.check()
+    rho = s.moments()[0].cpu().numpy().astype(np.float64)
+    s.close()
+    o = O.State(O.Params(**w.params), r0.astype(np.float64)).step(1000)
+    d = np.abs(rho - o.moments()[0]).max() / w.info["rho_l"]
+    print(f"max|drho|/rho_l = {d:.2e}")
+    assert d <= 1e-5
+
+
+def test_lowest_liquid_viscosity_falls_with_the_viscosity_ratio():
+    """Sec. IV.C, Fig. 4 (printed: nu_l ~ 0.075 at nu_g/nu_l = 1, 0.009 at 20, 0.0039 at
+    50) on the paper's splash geometry (600 x 250, R = 50, U = 0.125, 4000 steps = five
+    impact times D/U).  This implementation survives lower viscosities than the figure
+    at every ratio (documented departure), so the checks are the trend and that the
+    printed values are reachable."""
+    nus = [float(v) for v in np.geomspace(0.0015, 0.15, 12)]
+    ratios = (1, 20, 50)
+    ws = [W.paper_splash(nu, r) for r in ratios for nu in nus]
+    print(f"[gpu-case] viscosity-ratio stability search, {len(ws)} splash runs 600x250", flush=True)
+    failed = S.survival(ws, 4000)
+    low = {}
+    for k, r in enumerate(ratios):
+        fl = failed[k * len(nus):(k + 1) * len(nus)]
+        low[r] = S.lowest_stable_viscosity(nus, fl)
+        print(f"nu_g/nu_l = {r}: lowest surviving nu_l {low[r]}, failures {fl}")
+    assert low[1] is not None and low[1] <= 0.075
+    assert low[20] is not None and low[20] <= 0.009
+    assert low[20] < low[1] and low[50] is not None and low[50] <= low[20]

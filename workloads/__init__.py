@@ -277,3 +277,34 @@ def laplace_droplets(radii=(20.0, 25.0, 30.0, 35.0), n=200, t_over_tc=0.5, a=0.5
         w.info.update(cx=c, cy=c)
         out.append(w)
     return out
+
+
+def coexistence_droplets(t_values, sigma=None, tau_nu=0.8, a=0.5, n=200, R0=50.0):
+    """Stationary droplets of the coexistence-curve test (Sec. IV.A, Fig. 1): n x n periodic,
+    radius R0 at the centre, tanh start (Eq. 31) between the Maxwell densities, one
+    viscosity nu = (tau_nu - 1/2)/3 in both phases, s_e = s_zeta = s_q = 1.1; sigma = 0 is
+    the original forcing scheme."""
+    out = []
+    nu = (tau_nu - 0.5) / 3.0
+    for tb in t_values:
+        kw = {} if sigma is None else {"sigma": float(sigma)}
+        w = stationary_droplet(n=n, R0=R0, a=a, t_over_tc=float(tb), nu_l=nu, nu_g=nu, **kw)
+        c = (n - 1) / 2.0
+        w.info.update(cx=c, cy=c, sigma=w.params["sigma"], tau_nu=tau_nu, a=a)
+        out.append(w)
+    return out
+
+
+def paper_splash(nu_l, ratio, U=0.125, nx=600, ny=250, R=50.0, gap=5.0, t_over_tc=0.5, a=0.25) -> Workload:
+    """The paper's splash geometry (Sec. IV.C): 600 x 250, film one tenth of the height on
+    the lower wall, droplet of radius 50 at (nx/2, film + R + gap) moving at (0, -U),
+    walls in y, periodic x, a = 0.25, T = 0.5 T_c, 1/tau_e = 1/tau_zeta = 0.8,
+    nu(rho) = nu_l above rho_c and ratio * nu_l below (the gap is not stated in the paper)."""
+    p = base_params(nx, ny, a=a, t_over_tc=t_over_tc, bc=1, s_e=0.8, s_zeta=0.8, s_q=1.1,
+                    nu_l=nu_l, nu_g=ratio * nu_l)
+    rl, rg = coexistence(t_over_tc)
+    film = ny / 10.0
+    rho0, ux0, uy0 = splash_field(nx, ny, R, film, U, rl, rg, gap)
+    return Workload(f"paper_splash_nu{nu_l:.4g}_ratio{ratio:g}", p, rho0, ux0, uy0,
+                    info=dict(R=R, film=film, U=U, rho_l=rl, rho_g=rg, t_over_tc=t_over_tc, nu_l=nu_l,
+                              ratio=ratio))
