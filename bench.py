@@ -15,6 +15,7 @@ force, MRT collision with the improved forcing, store).  The metric is MLUPS
     python bench.py --workload learned [--train-runs 4096] [--eval-droplets 256] [--relax-steps 30000]
     python bench.py --workload lamb      (droplet oscillation against Lamb, Sec. IV.A)
     python bench.py --workload sweeps    (coexistence curves, stability edges, Table I, Fig. 4)
+    python bench.py --workload spread    (splash spread radius and Weber number, Sec. IV.C)
 
 The batch workload advances 512 independent droplet lattices (seed 1211: sides 64-512,
 a in {0.25, 0.5, 1}, T/Tc in [0.5, 0.85], half of them elliptic) in one persistent launch
@@ -272,6 +273,43 @@ def bench_sweeps(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_spread(args):
+    import torch
+
+    import workloads as W
+    from paper_1211_6932_amd import lbmp
+    from paper_1211_6932_amd import validation as V
+
+    torch.cuda.set_device(0)
+    lbmp.load()
+    t0 = time.perf_counter()
+    runs = {}
+    for Re, ratio in ((40, 1.0), (100, 1.0), (1000, 15.0)):
+        w = W.paper_splash(0.125 * 100 / Re, ratio)
+        sp = V.splash_spread(w, t_end_star=2.0, log=log)
+        t, r = sp["t_star"], sp["r_over_D"]
+        runs[str(Re)] = {"nu_g_over_nu_l": ratio,
+                         "C_short": round(V.power_law_coefficient(t, r, 0.02, 0.2), 4),
+                         "C_0.5_1.5": round(V.power_law_coefficient(t, r, 0.5, 1.5), 4),
+                         "r_over_D": {f"{x:.2f}": round(float(r[abs(t - x).argmin()]), 4)
+                                      for x in (0.05, 0.1, 0.2, 0.4, 0.7, 1.0, 1.5, 1.9)}}
+    st = V.surface_tension(W.laplace_droplets(radii=(30.0, 40.0, 50.0), n=256, t_over_tc=0.5, a=0.25), log=log)
+    p50 = [p for p in st["points"] if p["R0"] == 50.0][0]
+    we = p50["rho_in"] * 0.125 ** 2 * 100.0 / p50["theta"]
+    wall = time.perf_counter() - t0
+    out = {
+        "metric": "splash spread coefficient C of r/D = C sqrt(Ut/D) at short times (Re = 100)",
+        "value": runs["100"]["C_short"], "unit": "dimensionless", "n_gpus": 1, "steps": None, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": None, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "600x250 splash, D = 100, U = 0.125, a = 0.25, T = 0.5Tc, walls in y (Sec. IV.C)",
+                   "parallelism": "single GPU"},
+        "runs": runs, "weber": {"theta": p50["theta"], "rho_l": p50["rho_in"], "We": round(we, 2)},
+        "paper": {"C": 1.3, "We": 103}, "wall_seconds": round(wall, 2), "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_lamb(args):
     import torch
 
@@ -313,7 +351,7 @@ def bench_lamb(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="splash", choices=["splash", "batch", "learned", "lamb", "sweeps"])
+    ap.add_argument("--workload", default="splash", choices=["splash", "batch", "learned", "lamb", "sweeps", "spread"])
     ap.add_argument("--train-runs", type=int, default=4096)
     ap.add_argument("--eval-droplets", type=int, default=256)
     ap.add_argument("--relax-steps", type=int, default=30000)
@@ -342,6 +380,8 @@ def main():
         return bench_lamb(args)
     if args.workload == "sweeps":
         return bench_sweeps(args)
+    if args.workload == "spread":
+        return bench_spread(args)
 
     import numpy as np
     import torch

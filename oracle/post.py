@@ -16,7 +16,11 @@ Readings (the paper does not define these precisely):
     where the density on the horizontal line through the centre (linear in y
     between the two rows around it) first falls below a level, going outwards,
     linearly interpolated in x; the period is twice the mean spacing of the
-    successive crossings of the signal's mean.
+    successive crossings of the signal's mean;
+  * droplet splashing (Sec. IV.C): the spread radius is the half-width of the
+    liquid around the impact point on the line half a lattice unit above the
+    undisturbed film surface (linear in y between rows, mid-density crossings
+    linearly interpolated in x, the mean of the two sides).
 """
 from __future__ import annotations
 
@@ -128,3 +132,28 @@ def oscillation_period(t, r):
         raise ValueError("too few crossings")
     tc = t[idx] - v[idx] * (t[idx + 1] - t[idx]) / (v[idx + 1] - v[idx])
     return float(2.0 * np.mean(np.diff(tc)))
+
+
+def spread_radius(rho, cx, y_line, level):
+    """Half-width of the liquid (rho > level) around column cx on the line y = y_line."""
+    ny, nx = rho.shape
+    j = int(np.floor(y_line))
+    fy = y_line - j
+    line = (1.0 - fy) * rho[j] + fy * rho[j + 1]
+    # walk outwards over the columns on each side, starting from the interpolated centre value
+    i0 = int(np.floor(cx))
+    v_c = line[i0 % nx] + (cx - i0) * (line[(i0 + 1) % nx] - line[i0 % nx])
+    if v_c < level:
+        return 0.0
+    half = []
+    for cols in (np.arange(i0 + 1, i0 + 1 + nx // 2), np.arange(int(np.ceil(cx)) - 1, int(np.ceil(cx)) - 1 - nx // 2, -1)):
+        pos = np.concatenate([[cx], cols.astype(np.float64)])
+        val = np.concatenate([[v_c], line[cols % nx]])
+        k = np.nonzero(val < level)[0]
+        if k.size == 0:
+            half.append(nx / 2.0)
+            continue
+        k = int(k[0])
+        x = pos[k - 1] + (val[k - 1] - level) / (val[k - 1] - val[k]) * (pos[k] - pos[k - 1])
+        half.append(abs(x - cx))
+    return 0.5 * (half[0] + half[1])

@@ -10,6 +10,10 @@
     two-dimensional result, Eq. (32); the damping rate with the viscous rate of the
     mode, 2 nu_l n (n - 1) / R0^2.
 
+  * droplet splashing (Sec. IV.C, Fig. 9): the spread radius r of the liquid joining
+    droplet and film, against the power law r / D = C sqrt(U t / D) (the paper:
+    C ~ 1.3 for a planar droplet, no clear dependence on Re).
+
 Lattice steps and reductions run in liblbmp.so; this module sequences them and
 does the host arithmetic on the reduced values and on one lattice row per sample
 (interface position by linear interpolation, level crossings for a first period
@@ -23,7 +27,10 @@ radius R0 (the straight-line fit over several radii has a small intercept, so it
 slope differs from dp R by a few per cent); the interface on the major axis is where the density
 along the line through the centre crosses (rho_l + rho_g)/2 of the Maxwell
 densities; rho_l in Eq. (32) is the oscillating droplet's inner density averaged
-over the run.
+over the run.  Splash: the spread radius is the half-width of the liquid around
+the impact point on the line half a lattice unit above the undisturbed film
+surface (mean of the left and right mid-density crossings), and t counts from the
+geometric contact time gap / U.
 """
 from __future__ import annotations
 
@@ -173,3 +180,65 @@ def oscillation(w, steps=10400, every=10, skip=400, log=None):
         log(f"{w.name}: damped period {fit['period']:.1f}, undamped {fit['period0']:.1f}, "
             f"decay {fit['decay']:.0f} steps (fit rms {fit['rms']:.1e})")
     return dict(t=ts, x=xs, rho_l=float(np.mean(rls)), crossing_period=float(guess), **fit)
+
+
+def spread_half_width(row, cx, rho_mid):
+    """Mean distance from cx to the mid-density crossings left and right of it on a
+    periodic row whose density at cx is above rho_mid; 0 if it is not."""
+    nx = row.shape[0]
+    xs = np.arange(nx, dtype=np.float64)
+    if float(np.interp(cx, xs, row)) < rho_mid:
+        return 0.0
+    ext = []
+    for step in (1, -1):
+        x_prev, v_prev = cx, float(np.interp(cx, xs, row))
+        x = math.floor(cx) + 1 if step == 1 else math.ceil(cx) - 1
+        while abs(x - cx) < nx / 2:
+            v = float(row[x % nx])
+            if v < rho_mid:
+                ext.append(abs(x_prev + (v_prev - rho_mid) / (v_prev - v) * (x - x_prev) - cx))
+                break
+            x_prev, v_prev = x, v
+            x += step
+        else:
+            ext.append(nx / 2.0)
+    return 0.5 * (ext[0] + ext[1])
+
+
+def splash_spread(w, t_end_star=2.0, every=10, log=None):
+    """Run a splash workload; sample the spread radius every `every` steps up to
+    t* = U t / D = t_end_star after contact.  Returns dict(t_star, r_over_D)."""
+    import torch
+
+    def f(a):
+        return torch.from_numpy(np.asarray(a, dtype=np.float32))
+
+    U, D, film = w.info["U"], 2.0 * w.info["R"], w.info["film"]
+    t_contact = (w.info.get("gap", 5.0)) / U
+    steps = int(math.ceil(t_contact + t_end_star * D / U))
+    s = lbmp.Sim(w.params, f(w.rho0), f(w.ux0), f(w.uy0))
+    mid = 0.5 * (w.info["rho_l"] + w.info["rho_g"])
+    cx = w.params["nx"] / 2.0
+    ts, rs = [], []
+    for k in range(steps // every + 1):
+        if k:
+            s.step(every)
+        rho = s.moments()[0].cpu().numpy().astype(np.float64)
+        t = k * every - t_contact
+        if t > 0:
+            ts.append(U * t / D)
+            rs.append(spread_half_width(centre_row(rho, film + 0.5), cx, mid) / D)
+    s.check()
+    s.close()
+    if log:
+        log(f"{w.name}: {len(ts)} samples to t* = {ts[-1]:.2f}, r/D at the end {rs[-1]:.3f}")
+    return dict(t_star=np.array(ts), r_over_D=np.array(rs))
+
+
+def power_law_coefficient(t_star, r_over_D, lo=0.1, hi=1.0):
+    """Least-squares C of r / D = C sqrt(t*) over lo <= t* <= hi."""
+    t = np.asarray(t_star)
+    r = np.asarray(r_over_D)
+    m = (t >= lo) & (t <= hi)
+    q = np.sqrt(t[m])
+    return float((q * r[m]).sum() / (q * q).sum())

@@ -78,3 +78,54 @@ def test_oscillation_trajectory_matches_oracle():
     s.close()
     print(f"max |dx| over 1300 steps: {worst:.2e}")
     assert worst <= 1e-3
+
+
+def test_splash_spread_radius_power_law():
+    """Sec. IV.C, Fig. 9: 600 x 250 splash, D = 100, U = 0.125, a = 0.25, T = 0.5 T_c.
+    The spread radius at short times after contact (0.02 <= t* <= 0.2) follows
+    r / D = C sqrt(t*) with C within 15 % of the paper's 1.3, for Re = 100 and 1000
+    alike (within 10 % of each other); the Weber number rho_l U^2 D / theta with theta
+    from Laplace's law (a droplet of radius 50) is within 10 % of the printed 103."""
+    Cs = {}
+    for Re, ratio in ((100, 1.0), (1000, 15.0)):
+        print(f"[gpu-case] splash Re={Re} 600x250", flush=True)
+        w = W.paper_splash(0.125 * 100 / Re, ratio)
+        sp = V.splash_spread(w, t_end_star=2.0, log=print)
+        Cs[Re] = V.power_law_coefficient(sp["t_star"], sp["r_over_D"], 0.02, 0.2)
+        late = V.power_law_coefficient(sp["t_star"], sp["r_over_D"], 0.5, 1.5)
+        print(f"Re {Re}: C(0.02..0.2) = {Cs[Re]:.3f}, C(0.5..1.5) = {late:.3f}")
+        assert abs(Cs[Re] / 1.3 - 1) <= 0.15
+    assert abs(Cs[100] / Cs[1000] - 1) <= 0.10
+    print("[gpu-case] Laplace droplets a=0.25 T=0.5Tc", flush=True)
+    lw = W.laplace_droplets(radii=(30.0, 40.0, 50.0), n=256, t_over_tc=0.5, a=0.25)
+    st = V.surface_tension(lw)
+    theta = [p["theta"] for p in st["points"] if p["R0"] == 50.0][0]
+    rho_l = [p["rho_in"] for p in st["points"] if p["R0"] == 50.0][0]
+    we = rho_l * 0.125 ** 2 * 100.0 / theta
+    print(f"theta {theta:.4e}, rho_l {rho_l:.4f}: We = {we:.1f} (printed about 103)")
+    assert abs(we / 103.0 - 1) <= 0.10
+
+
+def test_splash_spread_matches_oracle():
+    """The spread radius of the first 400 steps (t* <= 0.45) from the GPU run and from the
+    FP64 oracle, each with its own measure.  Merging interfaces amplify rounding
+    differences near the neck, so the bound is 0.05 lattice units."""
+    print("[gpu-case] splash spread parity 600x250 400 steps", flush=True)
+    w = W.paper_splash(0.125, 1.0)
+    f32 = lambda a: np.asarray(a, dtype=np.float32)  # noqa: E731
+    s = B.Sim(w.params, torch.from_numpy(f32(w.rho0)), torch.from_numpy(f32(w.ux0)), torch.from_numpy(f32(w.uy0)))
+    o = O.State(O.Params(**w.params), f32(w.rho0).astype(np.float64), f32(w.ux0).astype(np.float64),
+                f32(w.uy0).astype(np.float64))
+    mid = 0.5 * (w.info["rho_l"] + w.info["rho_g"])
+    cx, y = w.params["nx"] / 2.0, w.info["film"] + 0.5
+    worst = 0.0
+    for k in range(9):
+        if k:
+            s.step(50)
+            o.step(50)
+        g = V.spread_half_width(V.centre_row(s.moments()[0].cpu().numpy().astype(np.float64), y), cx, mid)
+        ref = post.spread_radius(o.moments()[0], cx, y, mid)
+        worst = max(worst, abs(g - ref))
+    s.close()
+    print(f"max |dr| over 400 steps: {worst:.2e}")
+    assert worst <= 0.05

@@ -54,3 +54,20 @@ def test_damped_cosine_fit_recovers_frequency_and_decay():
         assert abs(fit["period"] / period - 1) < 1e-3 and abs(fit["decay"] / decay - 1) < 1e-2
         g, w = 1 / decay, 2 * np.pi / period
         assert abs(fit["period0"] - 2 * np.pi / np.sqrt(w * w + g * g)) < 1e-3 * period
+
+
+def test_spread_half_width_matches_closed_form_and_oracle():
+    # a circle of radius 50 sunk 4 units into a flat film: on a line above the film
+    # surface the liquid is the chord of the circle at that height (the line half a unit
+    # above the film averages the film's own mid-density row, so it is checked against
+    # the oracle's separately written measure only)
+    w = W.paper_splash(0.1, 1.0, gap=-4.0)
+    mid = 0.5 * (w.info["rho_l"] + w.info["rho_g"])
+    film, R = w.info["film"], w.info["R"]
+    cx = w.params["nx"] / 2.0
+    for y in (film + 0.5, film + 3.0, film + 8.0):
+        got = V.spread_half_width(V.centre_row(w.rho0, y), cx, mid)
+        assert abs(got - post.spread_radius(w.rho0, cx, y, mid)) < 1e-9
+        if y > film + 1.0:
+            dy = (film + R - 4.0) - y  # circle centre above the line
+            assert abs(got - math.sqrt(R * R - dy * dy)) < 0.01

@@ -306,5 +306,5 @@ def paper_splash(nu_l, ratio, U=0.125, nx=600, ny=250, R=50.0, gap=5.0, t_over_t
     film = ny / 10.0
     rho0, ux0, uy0 = splash_field(nx, ny, R, film, U, rl, rg, gap)
     return Workload(f"paper_splash_nu{nu_l:.4g}_ratio{ratio:g}", p, rho0, ux0, uy0,
-                    info=dict(R=R, film=film, U=U, rho_l=rl, rho_g=rg, t_over_tc=t_over_tc, nu_l=nu_l,
+                    info=dict(R=R, film=film, U=U, gap=gap, rho_l=rl, rho_g=rg, t_over_tc=t_over_tc, nu_l=nu_l,
                               ratio=ratio))
