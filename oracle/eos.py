@@ -9,7 +9,10 @@ Implements, from the paper (Li, Luo & Li):
   * Eq. (22)      Maxwell equal-area construction for the coexistence densities;
   * Eq. (24)      pseudopotential psi(rho) derived from the EOS;
   * Eq. (21)      mechanical-stability coexistence for a given epsilon;
-  * Eq. (29)      epsilon = -2 (alpha + 24 G sigma) / beta of the improved forcing.
+  * Eq. (29)      epsilon = -2 (alpha + 24 G sigma) / beta of the improved forcing;
+  * Eq. (23)      the Sbragaglia-Shan pseudopotential and the bulk pressure it implies,
+                  p = rho c_s^2 + G psi^2 / 2 (the bulk term of Eqs. (19)-(21)), with
+                  its critical point, Maxwell construction and Eq. (21) coexistence.
 """
 from __future__ import annotations
 
@@ -167,6 +170,106 @@ def mechanical_stability(T, a, eps, b=4.0, R=1.0, G=-1.0):
     p0 = optimize.brentq(cond, lo, hi, xtol=1e-18, rtol=1e-13, maxiter=500)
     rg, rl = _roots_at_pressure(p0, a, b, R, T, rs_g, rs_l)
     return rl, rg
+
+
+# ------------------------------------------------------------------ Eq. (23) pseudopotential
+
+def log_psi_ss(rho, eps):
+    """log of the Eq. (23) psi: -1/rho for eps = 0, (log rho - log(eps + rho)) / eps otherwise."""
+    rho = np.asarray(rho, dtype=np.float64)
+    if eps == 0.0:
+        return -1.0 / rho
+    return (np.log(rho) - np.log(eps + rho)) / eps
+
+
+def psi_ss(rho, eps):
+    """Eq. (23): psi = exp(-1/rho) for eps = 0, (rho / (eps + rho))^(1/eps) otherwise."""
+    rho = np.asarray(rho, dtype=np.float64)
+    if eps == 0.0:
+        return np.exp(-1.0 / rho)
+    return (rho / (eps + rho)) ** (1.0 / eps)
+
+
+def dpsi_ss(rho, eps):
+    """d psi / d rho of Eq. (23): log psi = (log rho - log(eps + rho)) / eps, so
+    psi' / psi = 1 / (rho (rho + eps)) (eps = 0: 1 / rho^2)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    return psi_ss(rho, eps) / (rho * (rho + eps))
+
+
+def p_ss(rho, G, eps):
+    """Bulk pressure of the pseudopotential model with the Eq. (23) psi: rho/3 + G psi^2 / 2."""
+    rho = np.asarray(rho, dtype=np.float64)
+    return CS2 * rho + 0.5 * G * psi_ss(rho, eps) ** 2
+
+
+def dp_ss(rho, G, eps):
+    return CS2 + G * psi_ss(rho, eps) * dpsi_ss(rho, eps)
+
+
+def critical_ss(eps):
+    """Critical point of p_ss: dp/drho = 1/3 + G h(rho) with h = psi^2 / (rho (rho + eps));
+    d log h / d rho = (2 - 2 rho - eps) / (rho (rho + eps)) vanishes at rho_c = 1 - eps/2,
+    and G_c = -1 / (3 h(rho_c)).  Returns (rho_c, G_c); needs 0 <= eps < 2."""
+    if not 0.0 <= eps < 2.0:
+        raise ValueError("eps must lie in [0, 2)")
+    rc = 1.0 - 0.5 * eps
+    h = float(psi_ss(rc, eps)) ** 2 / (rc * (rc + eps))
+    return rc, -1.0 / (3.0 * h)
+
+
+def spinodals_ss(G, eps):
+    rc, Gc = critical_ss(eps)
+    if not G < Gc:
+        raise ValueError("G must lie below the critical coupling")
+    f = lambda r: float(dp_ss(r, G, eps))
+    rg = optimize.brentq(f, 1e-3, rc, xtol=1e-16, rtol=1e-15)
+    hi = 2.0 * rc
+    while f(hi) < 0.0:
+        hi *= 2.0
+    rl = optimize.brentq(f, rc, hi, xtol=1e-16, rtol=1e-15)
+    return rg, rl
+
+
+def _roots_ss(p0, G, eps, rs_g, rs_l):
+    g = lambda r: float(p_ss(r, G, eps)) - p0
+    rg = optimize.brentq(g, 1e-3, rs_g, xtol=1e-300, rtol=1e-15, maxiter=500)
+    hi = 2.0 * rs_l
+    while g(hi) < 0.0:
+        hi *= 2.0
+    rl = optimize.brentq(g, rs_l, hi, xtol=1e-16, rtol=1e-15, maxiter=500)
+    return rg, rl
+
+
+def _coexistence_ss(G, eps, weight):
+    """p0 with integral_{rho_g}^{rho_l} (p0 - p_ss) weight(rho) d rho = 0 at the roots of p_ss = p0."""
+    rs_g, rs_l = spinodals_ss(G, eps)
+    p_hi = float(p_ss(rs_g, G, eps))
+    p_lo = max(float(p_ss(rs_l, G, eps)), float(p_ss(1e-3, G, eps)))
+
+    def area(p0):
+        rg, rl = _roots_ss(p0, G, eps, rs_g, rs_l)
+        val, _ = integrate.quad(lambda r: (p0 - float(p_ss(r, G, eps))) * weight(r), rg, rl,
+                                points=[rs_g, rs_l], limit=400, epsabs=0.0, epsrel=1e-12)
+        return val
+
+    d = 1e-13 * abs(p_hi)
+    p0 = optimize.brentq(area, p_lo + d, p_hi - d, xtol=1e-18, rtol=1e-14, maxiter=500)
+    rg, rl = _roots_ss(p0, G, eps, rs_g, rs_l)
+    return rl, rg
+
+
+def maxwell_ss(G, eps):
+    """Eq. (22) for p_ss: (rho_l, rho_g) with integral (p0 - p_ss) / rho^2 = 0."""
+    return _coexistence_ss(G, eps, lambda r: 1.0 / r ** 2)
+
+
+def mechanical_stability_ss(G, eps_psi, eps):
+    """Eq. (21) coexistence (rho_l, rho_g) with the Eq. (23) psi of parameter eps_psi and
+    the weight psi' / psi^(1 + eps) of a stencil/forcing with parameter eps."""
+    # psi' / psi^(1 + eps) = psi^(-eps) / (rho (rho + eps_psi)), psi^(-eps) from log psi
+    return _coexistence_ss(G, eps_psi,
+                           lambda r: math.exp(-eps * float(log_psi_ss(r, eps_psi))) / (r * (r + eps_psi)))
 
 
 def lamb_period(theta, rho_l, R0, n=2):

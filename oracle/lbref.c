@@ -19,7 +19,9 @@
  *             Eq. (6)  rho = sum f,  rho v = sum e f + F/2
  *             Eq. (7)  interaction force, w(1) = 1/3, w(2) = 1/12
  *             Eq. (10) kinematic viscosity nu = (tau_nu - 1/2)/3
- *   Sec. III  Eq. (24) psi = sqrt(2 (p_EOS - rho c_s^2) / (G c^2))
+ *   Sec. III  Eq. (24) psi = sqrt(2 (p_EOS - rho c_s^2) / (G c^2))  (psi_form 0)
+ *             Eq. (23) Sbragaglia-Shan psi = exp(-1/rho) (eps = 0) or
+ *                      (rho / (eps + rho))^(1/eps)                     (psi_form 1)
  *             Eq. (25) improved forcing term Sbar
  *   Sec. IV   Eq. (30) Carnahan-Starling p_EOS
  *   Sec. IV.C density-dependent viscosity nu(rho) = nu_l if rho >= rho_c else nu_g
@@ -45,12 +47,15 @@
 enum { LBREF_OK = 0, LBREF_EINVAL = -1, LBREF_ENOMEM = -2, LBREF_EUNSTABLE = -4 };
 enum { LBREF_PERIODIC = 0, LBREF_WALLS_Y = 1 };
 enum { LBREF_FORM_MOMENT = 0, LBREF_FORM_VELOCITY = 1 };
+enum { LBREF_PSI_CS = 0, LBREF_PSI_SS = 1 };
 
 typedef struct {
     int32_t nx, ny, bc, pad_;
     double a, b, R, T, G, sigma;        /* Eq. (30), Eq. (7)/(24), Eq. (25) */
     double s_rho, s_e, s_zeta, s_j, s_q;/* Eq. (2), as rates 1/tau         */
     double nu_l, nu_g, rho_switch;      /* Sec. IV.C viscosity switch      */
+    int32_t psi_form, pad2_;            /* Eq. (24) (0) or Eq. (23) (1)    */
+    double psi_eps;                     /* epsilon of Eq. (23)             */
 } lbref_params;
 
 /* D2Q9 velocities (standard ordering: rest, 4 axis, 4 diagonal). */
@@ -138,10 +143,24 @@ double lbref_p_eos(const lbref_params *p, double rho)
     return rho * p->R * p->T * num / den - p->a * rho * rho;
 }
 
-/* Eq. (24) with c = 1, c_s^2 = 1/3: psi^2 = 2 (p_EOS - rho/3) / G. */
+/* psi^2 of the chosen pseudopotential.  Eq. (24) with c = 1, c_s^2 = 1/3:
+ * psi^2 = 2 (p_EOS - rho/3) / G.  Eq. (23): psi = exp(-1/rho) for eps = 0,
+ * (rho / (eps + rho))^(1/eps) otherwise. */
 double lbref_psi2(const lbref_params *p, double rho)
 {
+    if (p->psi_form == LBREF_PSI_SS) {
+        double psi = (p->psi_eps == 0.0) ? exp(-1.0 / rho) : pow(rho / (p->psi_eps + rho), 1.0 / p->psi_eps);
+        return psi * psi;
+    }
     return 2.0 * (lbref_p_eos(p, rho) - rho / 3.0) / p->G;
+}
+
+/* Bulk pressure of the model, rho c_s^2 + G c^2 psi^2 / 2 (the bulk terms of
+ * Eqs. (19)-(21)); for the Eq. (24) psi this is p_EOS itself. */
+double lbref_pressure(const lbref_params *p, double rho)
+{
+    if (p->psi_form == LBREF_PSI_SS) return rho / 3.0 + 0.5 * p->G * lbref_psi2(p, rho);
+    return lbref_p_eos(p, rho);
 }
 
 /* Eq. (3): moment equilibria. */
@@ -260,7 +279,14 @@ static int validate(const lbref_params *p)
 {
     if (!p || p->nx < 1 || p->ny < 1) return LBREF_EINVAL;
     if (p->bc != LBREF_PERIODIC && p->bc != LBREF_WALLS_Y) return LBREF_EINVAL;
-    if (!(p->G < 0.0) || !(p->b > 0.0) || !(p->T > 0.0)) return LBREF_EINVAL;
+    if (!(p->G < 0.0)) return LBREF_EINVAL;
+    if (p->psi_form == LBREF_PSI_CS) {
+        if (!(p->b > 0.0) || !(p->T > 0.0)) return LBREF_EINVAL;
+    } else if (p->psi_form == LBREF_PSI_SS) {
+        if (!(p->psi_eps >= 0.0) || !isfinite(p->psi_eps)) return LBREF_EINVAL;
+    } else {
+        return LBREF_EINVAL;
+    }
     return LBREF_OK;
 }
 
@@ -271,9 +297,29 @@ static inline size_t IDX(const lbref_params *p, int a, int y, int x)
 
 static inline int wrap(int i, int n) { return ((i % n) + n) % n; }
 
-/* Eq. (30) + Eq. (24): psi at every site of a density field.  Returns
- * LBREF_EUNSTABLE (psi set to 0 there) if some site has a non-finite density,
- * b rho / 4 >= 1 or psi^2 <= 0. */
+/* psi at one site (Eq. (30) + Eq. (24), or Eq. (23)).  Sets *bad (and returns
+ * 0) for a non-finite density, or, for Eq. (24), b rho / 4 >= 1 or psi^2 <= 0,
+ * or, for Eq. (23), rho <= 0. */
+static double psi_site(const lbref_params *p, double r, int *bad)
+{
+    int ok;
+    double s2 = 0.0;
+    if (p->psi_form == LBREF_PSI_SS) {
+        ok = isfinite(r) && r > 0.0;
+        if (ok) s2 = lbref_psi2(p, r);
+    } else {
+        s2 = lbref_psi2(p, r);
+        ok = isfinite(r) && (p->b * r / 4.0 < 1.0) && (s2 > 0.0);
+    }
+    if (!ok) {
+        *bad = 1;
+        return 0.0;
+    }
+    return sqrt(s2);
+}
+
+/* psi at every site of a density field; LBREF_EUNSTABLE (psi set to 0 there)
+ * if some site is invalid as in psi_site. */
 static int psi_of(const lbref_params *p, const double *rho, double *psi)
 {
     const int nx = p->nx, ny = p->ny;
@@ -282,15 +328,9 @@ static int psi_of(const lbref_params *p, const double *rho, double *psi)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t i = (size_t)y * nx + x;
-            double r = rho[i];
-            double eta = p->b * r / 4.0;
-            double s2 = lbref_psi2(p, r);
-            if (!isfinite(r) || !(eta < 1.0) || !(s2 > 0.0)) {
-                bad = 1;
-                psi[i] = 0.0;
-            } else {
-                psi[i] = sqrt(s2);
-            }
+            int b = 0;
+            psi[i] = psi_site(p, rho[i], &b);
+            bad |= b;
         }
     return bad ? LBREF_EUNSTABLE : LBREF_OK;
 }
@@ -480,9 +520,9 @@ int lbref_collide_at(const lbref_params *p, const double *f, int64_t n, const in
                 else if (yn >= ny) yn = ny - 1;
                 double r = 0.0;
                 for (int a = 0; a < Q; ++a) r += f[IDX(p, a, yn, xn)];
-                double s2 = lbref_psi2(p, r);
-                if (!isfinite(r) || !(p->b * r / 4.0 < 1.0) || !(s2 > 0.0)) { bad = 1; s2 = 0.0; }
-                psi_n[dy + 1][dx + 1] = sqrt(s2);
+                int b = 0;
+                psi_n[dy + 1][dx + 1] = psi_site(p, r, &b);
+                bad |= b;
                 if (dx == 0 && dy == 0) rho_c = r;
             }
         double sx = 0.0, sy = 0.0;

@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liblbref.so")
 OK, EINVAL, ENOMEM, EUNSTABLE = 0, -1, -2, -4
 PERIODIC, WALLS_Y = 0, 1
 FORM_MOMENT, FORM_VELOCITY = 0, 1
+PSI_CS, PSI_SS = 0, 1  # pseudopotential of Eq. (24) / of Eq. (23)
 
 
 class LbrefParams(ctypes.Structure):
@@ -35,6 +36,7 @@ class LbrefParams(ctypes.Structure):
         ("s_rho", ctypes.c_double), ("s_e", ctypes.c_double), ("s_zeta", ctypes.c_double),
         ("s_j", ctypes.c_double), ("s_q", ctypes.c_double),
         ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("rho_switch", ctypes.c_double),
+        ("psi_form", ctypes.c_int32), ("pad2_", ctypes.c_int32), ("psi_eps", ctypes.c_double),
     ]
 
 
@@ -66,6 +68,8 @@ def lib():
         L.lbref_p_eos.restype = ctypes.c_double
         L.lbref_psi2.argtypes = [P, ctypes.c_double]
         L.lbref_psi2.restype = ctypes.c_double
+        L.lbref_pressure.argtypes = [P, ctypes.c_double]
+        L.lbref_pressure.restype = ctypes.c_double
         L.lbref_collide_site.argtypes = [P, dp] + [ctypes.c_double] * 6 + [ctypes.c_int, dp]
         L.lbref_init.argtypes = [P, dp, dp, dp, dp]
         L.lbref_moments.argtypes = [P, dp, dp, dp, dp, dp, dp, dp]
@@ -105,11 +109,14 @@ class Params:
     nu_l: float = 0.1
     nu_g: float = 0.3
     rho_switch: float = 0.13045
+    psi_form: int = PSI_CS   # Eq. (24) from the EOS, or Eq. (23) with parameter psi_eps
+    psi_eps: float = 0.0
 
     def c(self) -> LbrefParams:
         return LbrefParams(self.nx, self.ny, self.bc, 0, self.a, self.b, self.R, self.T, self.G,
                            self.sigma, self.s_rho, self.s_e, self.s_zeta, self.s_j, self.s_q,
-                           self.nu_l, self.nu_g, self.rho_switch)
+                           self.nu_l, self.nu_g, self.rho_switch, int(self.psi_form), 0,
+                           float(self.psi_eps))
 
 
 class OracleError(RuntimeError):
@@ -138,6 +145,12 @@ def p_eos(p: Params, rho: float) -> float:
 def psi2(p: Params, rho: float) -> float:
     c = p.c()
     return lib().lbref_psi2(ctypes.byref(c), float(rho))
+
+
+def pressure(p: Params, rho: float) -> float:
+    """Bulk pressure rho/3 + G psi^2 / 2 (p_EOS of Eq. (30) for the Eq. (24) psi)."""
+    c = p.c()
+    return lib().lbref_pressure(ctypes.byref(c), float(rho))
 
 
 def collide_site(p: Params, f9, rho, vx, vy, Fx, Fy, psi2_, form=FORM_MOMENT):

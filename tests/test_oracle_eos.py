@@ -124,3 +124,75 @@ def test_lamb_period_formula(golden):
     rho_l, R0 = 0.455, math.sqrt(30 * 27)
     theta = 4 * math.pi ** 2 * rho_l * R0 ** 3 / (6 * T_a ** 2)
     assert eos.lamb_period(theta, rho_l, R0) == pytest.approx(T_a, rel=1e-12)
+
+
+# ------------------------------------------------------------------ Eq. (23) pseudopotential
+
+def test_eq23_critical_points_closed_forms():
+    """p = rho/3 + G psi^2 / 2 with the Eq. (23) psi.  By hand: eps = 0 gives
+    p' = 1/3 + G exp(-2/rho) / rho^2, stationary slope at rho = 1, G_c = -e^2/3;
+    eps = 1 gives p' = 1/3 + G rho / (1 + rho)^3, maximal rho/(1+rho)^3 = 4/27 at
+    rho = 1/2, G_c = -9/4."""
+    rc0, gc0 = eos.critical_ss(0.0)
+    rc1, gc1 = eos.critical_ss(1.0)
+    assert rc0 == 1.0 and gc0 == pytest.approx(-math.e ** 2 / 3.0, rel=1e-14)
+    assert rc1 == 0.5 and gc1 == pytest.approx(-9.0 / 4.0, rel=1e-14)
+    for eps, rc, gc in ((0.0, rc0, gc0), (1.0, rc1, gc1), (0.5, *eos.critical_ss(0.5))):
+        h = 1e-4
+        d1 = (eos.p_ss(rc + h, gc, eps) - eos.p_ss(rc - h, gc, eps)) / (2 * h)
+        d2 = (eos.p_ss(rc + h, gc, eps) - 2 * eos.p_ss(rc, gc, eps) + eos.p_ss(rc - h, gc, eps)) / h ** 2
+        assert abs(d1) < 1e-8 and abs(d2) < 1e-5
+
+
+def test_eq23_psi_limit_derivative_and_consistency_identity():
+    """Eq. (23): the eps -> 0 limit is exp(-1/rho), and psi' / psi^(1+eps) = 1 / rho^2
+    (the property the paper states), checked with finite differences of psi."""
+    rho = np.array([0.05, 0.3, 1.0, 2.5])
+    assert np.allclose(eos.psi_ss(rho, 1e-8), np.exp(-1.0 / rho), rtol=1e-6)
+    for eps in (0.0, 0.5, 1.0, 10.0 / 31.0):
+        h = 1e-6 * rho
+        fd = (eos.psi_ss(rho + h, eps) - eos.psi_ss(rho - h, eps)) / (2 * h)
+        assert np.allclose(eos.dpsi_ss(rho, eps), fd, rtol=1e-7)
+        assert np.allclose(fd / eos.psi_ss(rho, eps) ** (1.0 + eps), 1.0 / rho ** 2, rtol=1e-7)
+
+
+def test_eq23_maxwell_equal_pressure_and_chemical_potential():
+    """The equal-area rule for p = rho/3 + G psi^2 / 2 <=> equal pressure and equal
+    chemical potential, mu' = p'/rho.  Closed forms by hand:
+      eps = 0: mu = ln(rho)/3 + G (1/(2 rho) + 1/4) exp(-2/rho);
+      eps = 1: mu = ln(rho)/3 - G / (2 (1 + rho)^2)."""
+    mu = {0.0: lambda r, G: math.log(r) / 3 + G * (0.5 / r + 0.25) * math.exp(-2.0 / r),
+          1.0: lambda r, G: math.log(r) / 3 - G / (2.0 * (1.0 + r) ** 2)}
+    for eps in (0.0, 1.0):
+        _, gc = eos.critical_ss(eps)
+        for f in (1.1, 1.3):
+            G = f * gc
+            rl, rg = eos.maxwell_ss(G, eps)
+            assert rl > 1.5 * rg
+            assert eos.p_ss(rl, G, eps) == pytest.approx(eos.p_ss(rg, G, eps), rel=1e-10)
+            assert mu[eps](rl, G) == pytest.approx(mu[eps](rg, G), abs=1e-10)
+
+
+def test_eq23_mechanical_stability_is_maxwell_when_epsilons_match():
+    """Eq. (21) with the Eq. (23) psi of parameter eps reduces to Eq. (22) when the
+    stencil/forcing epsilon equals eps; with epsilon = 0 it does not (eps = 1)."""
+    for eps in (0.0, 0.5, 1.0):
+        G = 1.2 * eos.critical_ss(eps)[1]
+        ml, mg = eos.maxwell_ss(G, eps)
+        tl, tg = eos.mechanical_stability_ss(G, eps, eps)
+        assert tl == pytest.approx(ml, rel=1e-7) and tg == pytest.approx(mg, rel=1e-7)
+    G = 1.2 * eos.critical_ss(1.0)[1]
+    tl, tg = eos.mechanical_stability_ss(G, 1.0, 0.0)
+    ml, mg = eos.maxwell_ss(G, 1.0)
+    assert eos.p_ss(tl, G, 1.0) == pytest.approx(eos.p_ss(tg, G, 1.0), rel=1e-10)
+    assert abs(tg / mg - 1) > 0.2
+
+
+def test_eq23_c_oracle_matches_python():
+    """The C oracle's Eq. (23) psi^2 and bulk pressure against this module's."""
+    from oracle import lbref as O
+    for eps in (0.0, 1.0, 10.0 / 31.0):
+        p = O.Params(nx=4, ny=4, G=-2.7, psi_form=O.PSI_SS, psi_eps=eps)
+        for r in (0.07, 0.4, 1.9):
+            assert O.psi2(p, r) == pytest.approx(float(eos.psi_ss(r, eps)) ** 2, rel=1e-13)
+            assert O.pressure(p, r) == pytest.approx(float(eos.p_ss(r, -2.7, eps)), rel=1e-12)

@@ -259,3 +259,46 @@ def test_laplace_law():
     slope, icpt, r2 = post.linear_fit(xs, ys)
     assert slope > 0 and r2 >= 0.999
     assert abs(icpt) <= 0.1 * max(ys)
+
+
+# ------------------------------------------------------------------ Eq. (23) pseudopotential
+
+def ss_flat_interface(eps, G, sigma, steps=20000):
+    ml, mg = eos.maxwell_ss(G, eps)
+    w = W.ss_slab(G, eps, ml, mg, sigma=sigma)
+    s = state(w.params, w.rho0)
+    s.step(steps)
+    r = s.moments()[0][:, 0]
+    return r[w.params["ny"] // 2], r[0], (ml, mg)
+
+
+def test_eq23_psi_with_original_forcing_follows_maxwell():
+    """Sec. III.A: with the Eq. (23) psi at eps = 0 and the original forcing (sigma = 0,
+    nearest-neighbour epsilon = 0), the mechanical-stability coexistence is the Maxwell
+    construction of p = rho/3 + G psi^2 / 2.  Flat interface at G = 1.1 G_c."""
+    G = 1.1 * eos.critical_ss(0.0)[1]
+    rl, rg, (ml, mg) = ss_flat_interface(0.0, G, 0.0)
+    assert rl == pytest.approx(ml, rel=1e-5)
+    assert rg == pytest.approx(mg, rel=1e-5)
+
+
+@pytest.mark.parametrize("eps", [0.5, 1.0])
+def test_eq23_psi_improved_forcing_sets_epsilon(eps):
+    """Eq. (29) with alpha = 0, beta = 3: epsilon = -16 G sigma.  Choosing
+    sigma = -eps / (16 G) for the Eq. (23) psi of parameter eps makes the LB coexistence
+    follow the Maxwell construction of its pressure (G = 1.2 G_c)."""
+    G = 1.2 * eos.critical_ss(eps)[1]
+    rl, rg, (ml, mg) = ss_flat_interface(eps, G, -eps / (16.0 * G))
+    assert rl == pytest.approx(ml, rel=1e-3)
+    assert rg == pytest.approx(mg, rel=1e-2)
+
+
+def test_eq23_psi_with_original_forcing_follows_eq21_not_maxwell():
+    """The same psi (eps = 1) with sigma = 0 follows Eq. (21) at epsilon = 0 and misses
+    the Maxwell vapour density by about a quarter."""
+    G = 1.2 * eos.critical_ss(1.0)[1]
+    rl, rg, (ml, mg) = ss_flat_interface(1.0, G, 0.0)
+    tl, tg = eos.mechanical_stability_ss(G, 1.0, 0.0)
+    assert rl == pytest.approx(tl, rel=1e-3)
+    assert rg == pytest.approx(tg, rel=2e-3)
+    assert abs(rg / mg - 1) > 0.2

@@ -143,6 +143,32 @@ def base_params(nx, ny, a=0.5, t_over_tc=0.6, bc=0, sigma=None, s_e=1.1, s_zeta=
                 nu_l=float(nu_l), nu_g=float(nu_g), rho_switch=rho_switch(b))
 
 
+def ss_params(nx, ny, G, eps, sigma=0.0, bc=0, nu=0.1, s_e=1.1, s_zeta=1.1, s_q=1.1):
+    """Parameters of a run with the Sbragaglia-Shan pseudopotential of Eq. (23)
+    (psi_form 1, parameter eps, coupling G); the Carnahan-Starling constants are
+    unused and one viscosity holds in both phases."""
+    return dict(nx=int(nx), ny=int(ny), bc=int(bc), a=0.0, b=4.0, R=1.0, T=1.0, G=float(G),
+                sigma=float(sigma), s_rho=1.0, s_e=float(s_e), s_zeta=float(s_zeta), s_j=1.0,
+                s_q=float(s_q), nu_l=float(nu), nu_g=float(nu), rho_switch=0.0, psi_form=1,
+                psi_eps=float(eps))
+
+
+def ss_slab(G, eps, rho_l, rho_g, sigma=0.0, nx=4, ny=200, thickness=None) -> Workload:
+    """Flat liquid slab (periodic, uniform in x) with the Eq. (23) pseudopotential,
+    started from a tanh profile between the given densities."""
+    thickness = ny / 2.0 if thickness is None else thickness
+    p = ss_params(nx, ny, G, eps, sigma)
+    return Workload(f"ss_slab_{nx}x{ny}_eps{eps:g}_G{G:g}", p, slab_field(nx, ny, thickness, rho_l, rho_g),
+                    info=dict(rho_l=rho_l, rho_g=rho_g, G=G, eps=eps, sigma=sigma))
+
+
+def ss_droplet(n, R0, G, eps, rho_l, rho_g, sigma=0.0) -> Workload:
+    """Stationary droplet with the Eq. (23) pseudopotential on an n x n periodic grid."""
+    p = ss_params(n, n, G, eps, sigma)
+    return Workload(f"ss_droplet_{n}x{n}_R{R0:g}_eps{eps:g}", p, droplet_field(n, n, R0, rho_l, rho_g),
+                    info=dict(R0=R0, rho_l=rho_l, rho_g=rho_g, G=G, eps=eps, sigma=sigma))
+
+
 def stationary_droplet(n=128, R0=25.0, a=0.5, t_over_tc=0.6, nu_l=0.1, nu_g=0.3, **kw) -> Workload:
     """Stationary droplet on an n x n periodic grid, tanh-initialised (Sec. IV.A recipe)."""
     p = base_params(n, n, a=a, t_over_tc=t_over_tc, nu_l=nu_l, nu_g=nu_g, **kw)
