@@ -9,6 +9,7 @@
  *      (x periodic; y periodic or halfway bounce-back walls)    Sec. IV.C
  *   2. density summation                                        Eq. (6)
  *   3. Carnahan-Starling pressure and pseudopotential psi       Eqs. (30), (24)
+ *      (or the Sbragaglia-Shan psi of Eq. (23), see lb_psi_form)
  *   4. 8-neighbour interaction force, w(1)=1/3, w(2)=1/12       Eq. (7)
  *   5. half-force-corrected velocity                            Eq. (6)
  *   6. MRT collision in moment space with the improved forcing  Eqs. (2)-(4), (25)
@@ -43,7 +44,8 @@ typedef enum {
     LB_EINVAL = -1,     /* invalid argument or parameter; nothing was launched          */
     LB_ENOMEM = -2,     /* workspace too small                                           */
     LB_EHIP = -3,       /* a HIP runtime call failed; see lb_last_error()                */
-    LB_EUNSTABLE = -4,  /* a site had a non-finite density, b rho/4 >= 1 or psi^2 <= 0   */
+    LB_EUNSTABLE = -4,  /* a site had a non-finite density, b rho/4 >= 1 or psi^2 <= 0
+                           (Eq. (24)), or a non-positive density (Eq. (23))              */
     LB_ESTATE = -5      /* context poisoned by an earlier LB_EUNSTABLE / LB_EHIP          */
 } lb_status;
 
@@ -70,6 +72,17 @@ typedef enum {
 /* w_a are the D2Q9 lattice weights 4/9 (rest), 1/9 (axis), 1/36 (diagonal).
  * Collision and force are computed in FP32 for every storage type. */
 
+typedef enum {
+    LB_PSI_CS = 0,  /* Eq. (24): psi = sqrt(2 (p_EOS - rho/3) / G) with the Carnahan-Starling
+                       p_EOS of Eq. (30) (the paper's choice)                          */
+    LB_PSI_SS = 1   /* Eq. (23), Sbragaglia-Shan: psi = exp(-1/rho) for psi_eps = 0, else
+                       (rho / (psi_eps + rho))^(1/psi_eps); a, b, R, T are unused and the
+                       bulk pressure is rho/3 + G psi^2 / 2.  With sigma = -psi_eps/(16 G)
+                       the improved forcing gives epsilon = psi_eps in Eq. (29), so the
+                       coexistence densities follow the Maxwell construction (Eq. (22)) of
+                       that pressure.                                                   */
+} lb_psi_form;
+
 /* Run parameters.  Rates are the inverse relaxation times 1/tau of Eq. (2).
  * The shear rate is per site: s_nu = 1/(3 nu + 1/2) with nu = nu_l where
  * rho >= rho_switch and nu_g elsewhere (Sec. IV.C; Eq. (10) gives
@@ -81,13 +94,16 @@ typedef struct {
     int32_t bc;              /* lb_bc                                                    */
     int32_t store;           /* lb_store                                                 */
     double a, b, R, T;       /* Carnahan-Starling constants and absolute temperature,
-                                Eq. (30); b > 0, T > 0                                   */
+                                Eq. (30); b > 0, T > 0, R > 0, a >= 0 (LB_PSI_CS)        */
     double G;                /* interaction strength of Eq. (7), G < 0                   */
     double sigma;            /* improved-forcing coefficient of Eq. (25), >= 0           */
     double s_rho, s_e, s_zeta, s_j, s_q;   /* rates in (0, 2)                            */
     double nu_l, nu_g;       /* kinematic viscosities, > 0                               */
     double rho_switch;       /* density at which nu switches from nu_g to nu_l           */
     double rho_ref;          /* reference density of LB_STORE_*_OFFSET (ignored otherwise) */
+    int32_t psi_form;        /* lb_psi_form: pseudopotential of Eq. (24) or of Eq. (23)    */
+    int32_t reserved_;       /* set to 0                                                 */
+    double psi_eps;          /* epsilon of Eq. (23), >= 0 (LB_PSI_SS only)               */
 } lb_params;
 
 /* An annulus r_min <= d < r_max around (cx, cy); d uses the minimum image in

@@ -41,6 +41,7 @@ constexpr int kDiagFields = 10;       // doubles per wave partial in the diagnos
 enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2, kStoreF16Local = 3, kStoreBF16Local = 4, kStoreF16Dest = 5 };
 enum : int { kModeStep = 0, kModeMoments = 1, kModeDiag = 2 };
 enum : int { kFlagUnstable = 1, kFlagBadInput = 2 };
+enum : int { kPsiCS = 0, kPsiSS = 1 };  // psi of Eq. (24) from Eq. (30), or of Eq. (23)
 
 // Per-launch constants (FP32 copies of FP64 host-derived values).
 struct StepConst {
@@ -56,6 +57,8 @@ struct StepConst {
     float rho_switch;           // nu_l for rho >= rho_switch, nu_g below
     float s_e, s_z, s_q, s_nu_l, s_nu_g;
     float c_e, c_z;             // 12 sigma G^2 s_e, 12 sigma G^2 s_zeta (Eq. 25 through I - Lambda/2)
+    int psi_form;               // kPsiCS or kPsiSS
+    float psi_eps, inv_psi_eps; // epsilon of Eq. (23) and 1/epsilon (0 when epsilon = 0)
     float off[9];               // w_a rho_ref: offsets of the 16-bit storage (0 for FP32)
 };
 
@@ -68,15 +71,22 @@ struct BatchInstance {
 };
 
 // Diagnostics regions (annuli) and output.
-// FP64 parameters of the initial-state kernel (Eqs. (7), (24), (30)).
-struct InitConst {
+// FP64 parameters of the pseudopotential: Eq. (24) with Eq. (30), or Eq. (23).
+struct PsiConst {
     double b4, RT, a, G;
+    double eps;     // epsilon of Eq. (23)
+    int form;       // kPsiCS or kPsiSS
+};
+
+// FP64 parameters of the initial-state kernel (Eqs. (7), (23)/(24), (30)).
+struct InitConst {
+    PsiConst psi;
 };
 
 struct DiagConst {
     double in_cx, in_cy, in_r0, in_r1;
     double out_cx, out_cy, out_r0, out_r1;
-    double b4, RT, a;  // FP64 copies for the pressure of Eq. (30)
+    PsiConst psi;  // FP64 copies for the bulk pressure
     int periodic_y;
 };
 
@@ -321,6 +331,33 @@ __device__ __forceinline__ double p_eos_f64(double rho, double b4, double RT, do
     return rho * (RT * num / (om * om * om) - a * rho);
 }
 
+// Eq. (23) in FP64: exp(-1/rho) for epsilon = 0, (rho / (epsilon + rho))^(1/epsilon)
+// otherwise (rho > 0).
+__device__ __forceinline__ double psi_ss_f64(double rho, double eps)
+{
+    return eps == 0.0 ? exp(-1.0 / rho) : pow(rho / (eps + rho), 1.0 / eps);
+}
+
+// psi^2 in FP64 (0 where psi is undefined: rho <= 0, or psi^2 <= 0 for Eq. (24)).
+__device__ __forceinline__ double psi2_f64(double rho, const PsiConst& c)
+{
+    if (c.form == kPsiSS) {
+        if (!(rho > 0.0)) return 0.0;
+        const double s = psi_ss_f64(rho, c.eps);
+        return s * s;
+    }
+    const double s2 = 2.0 * (p_eos_f64(rho, c.b4, c.RT, c.a) - rho / 3.0) / c.G;
+    return s2 > 0.0 ? s2 : 0.0;
+}
+
+// Bulk pressure in FP64: rho c_s^2 + G psi^2 / 2, the bulk terms of the pressure
+// tensor of Eqs. (18)-(21); with the Eq. (24) psi this is p_EOS of Eq. (30).
+__device__ __forceinline__ double pressure_f64(double rho, const PsiConst& c)
+{
+    if (c.form == kPsiSS) return rho / 3.0 + 0.5 * c.G * psi2_f64(rho, c);
+    return p_eos_f64(rho, c.b4, c.RT, c.a);
+}
+
 #ifndef LBMP_APPROX_DIV
 #define LBMP_APPROX_DIV 0
 #endif
@@ -363,15 +400,25 @@ __device__ __forceinline__ float p_eos(float rho, const StepConst& k)
     return rho * fmaf(k.RT * num, inv, -k.a * rho);
 }
 
-// Eq. (24): psi = sqrt(2 (p_EOS - rho/3) / G).  Flags non-finite rho, b rho/4 >= 1
-// and psi^2 <= 0; psi is then taken as 0 so the step stays finite-cost.
-// The divisions and the square root here and for 1/rho are the correctly rounded
-// IEEE forms, not the 1-ulp hardware approximations: the force of Eq. (7) takes
-// differences of neighbouring psi values, so an ulp-level staircase error in psi
-// becomes force noise, which in FP32 roughly quadruples the drift from the
-// FP64 solution over 10^3 steps.
+// PSI = kPsiCS: Eq. (24), psi = sqrt(2 (p_EOS - rho/3) / G).  Flags non-finite
+// rho, b rho/4 >= 1 and psi^2 <= 0; psi is then taken as 0 so the step stays
+// finite-cost.  The reciprocals and the square root here and for 1/rho are the
+// hardware approximations refined by one Newton step (recip, root), not the raw
+// 1-ulp approximations: the force of Eq. (7) takes differences of neighbouring
+// psi values, so an ulp-level staircase error in psi becomes force noise, which
+// in FP32 roughly quadruples the drift from the FP64 solution over 10^3 steps.
+// PSI = kPsiSS: Eq. (23), exp(-1/rho) or (rho / (epsilon + rho))^(1/epsilon);
+// flags a non-finite or non-positive rho (psi is then 0).  The form is a template
+// parameter so that the Eq. (24) step carries no trace of the other.
+template <int PSI = kPsiCS>
 __device__ __forceinline__ float pseudopotential(float rho, const StepConst& k, bool& bad)
 {
+    if constexpr (PSI == kPsiSS) {
+        const bool ok = (rho > 0.0f) && (rho < __builtin_huge_valf());
+        bad |= !ok;
+        if (!ok) return 0.0f;
+        return k.psi_eps == 0.0f ? expf(-recip(rho)) : powf(rho * recip(k.psi_eps + rho), k.inv_psi_eps);
+    }
     const float psi2 = k.two_over_G * (p_eos(rho, k) - rho * (1.0f / 3.0f));
     const bool ok = (psi2 > 0.0f) && (k.b4 * rho < 1.0f);
     bad |= !ok;

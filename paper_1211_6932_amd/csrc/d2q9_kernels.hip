@@ -22,7 +22,7 @@ namespace lbmp {
 // One wavefront processes strip `tile` of the lattice described by `k`: pull,
 // density, psi, force and velocity for every row, then by MODE collide and
 // store (a time step), write rho/v (moments) or accumulate FP64 reductions.
-template <int S, bool WALLS, int MODE>
+template <int S, bool WALLS, int MODE, int PSI>
 __device__ __forceinline__ void strip_tile(
     const typename Codec<S>::T* __restrict__ fin, typename Codec<S>::T* __restrict__ fout,
     const StepConst& k, const int tile, const int lane, int* __restrict__ flag,
@@ -65,7 +65,7 @@ __device__ __forceinline__ void strip_tile(
     if (yh >= 0) {
         pull_row<S, WALLS>(fin, k, yh, xm, xc, xp, fn);
         const float rm = density(fn);
-        pm = pseudopotential(rm, k, bad);
+        pm = pseudopotential<PSI>(rm, k, bad);
         if constexpr (C::kDestScaled) im = recip(C::round_scale(rm));
     }
     pull_row<S, WALLS>(fin, k, y0, xm, xc, xp, f);
@@ -73,7 +73,7 @@ __device__ __forceinline__ void strip_tile(
     const bool has1 = !WALLS || y0 + 1 < k.ny;
     if (has1) pull_row<S, WALLS>(fin, k, (y0 + 1 < k.ny) ? y0 + 1 : y0 + 1 - k.ny, xm, xc, xp, fn);
     float rc = density(f);
-    float pc = pseudopotential(rc, k, bad);
+    float pc = pseudopotential<PSI>(rc, k, bad);
     if (WALLS && y0 == 0) pm = pc;
     float pmL = lane_from_left(pm), pmR = lane_from_right(pm);
     float pcL = lane_from_left(pc), pcR = lane_from_right(pc);
@@ -104,7 +104,7 @@ __device__ __forceinline__ void strip_tile(
         float pp, rn = 0.0f;
         if (has_n) {
             rn = density(fn);
-            pp = pseudopotential(rn, k, bad);
+            pp = pseudopotential<PSI>(rn, k, bad);
         } else {
             pp = pc;  // mirror beyond the top wall
         }
@@ -161,7 +161,7 @@ __device__ __forceinline__ void strip_tile(
         } else {
             if (live) {
                 const double r = rc;
-                const double p = p_eos_f64(r, dg.b4, dg.RT, dg.a);
+                const double p = pressure_f64(r, dg.psi);
                 acc[0] += r;
                 acc[1] += r * (double)vx;
                 acc[2] += r * (double)vy;
@@ -206,7 +206,7 @@ __device__ __forceinline__ void strip_tile(
     if (bad) flag[0] = kFlagUnstable;  // vector store from any flagging lane; all write the same value
 }
 
-template <int S, bool WALLS, int MODE>
+template <int S, bool WALLS, int MODE, int PSI>
 __global__ __launch_bounds__(kWave * kWavesPerBlock)
 __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
     const typename Codec<S>::T* __restrict__ fin, typename Codec<S>::T* __restrict__ fout,
@@ -219,7 +219,7 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = logical_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
     if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
-    strip_tile<S, WALLS, MODE>(fin, fout, k, tile, lane, flag, rho_out, ux_out, uy_out, dg, partial);
+    strip_tile<S, WALLS, MODE, PSI>(fin, fout, k, tile, lane, flag, rho_out, ux_out, uy_out, dg, partial);
 }
 
 // Persistent multi-instance step: one workgroup owns one lattice and advances
@@ -228,7 +228,7 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
 // stores of step t before the loads of step t+1 for all waves of the CU).
 // Workgroups never wait for each other.  Each records the wall clock at its
 // start and end (for per-instance completion times).
-template <int S, bool WALLS>
+template <int S, bool WALLS, int PSI>
 __global__ __launch_bounds__(kWave * kBatchWaves) void d2q9_batch(
     const BatchInstance* __restrict__ inst, int steps, int parity,
     unsigned long long* __restrict__ clock_out)
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kWave * kBatchWaves) void d2q9_batch(
     for (int s = 0; s < steps; ++s) {
         const int cur = (parity + s) & 1;
         for (int tile = wave; tile < ntiles; tile += kBatchWaves)
-            strip_tile<S, WALLS, kModeStep>(buf[cur], buf[cur ^ 1], k, tile, lane, I.flag, nullptr,
+            strip_tile<S, WALLS, kModeStep, PSI>(buf[cur], buf[cur ^ 1], k, tile, lane, I.flag, nullptr,
                                             nullptr, nullptr, dg, nullptr);
         __syncthreads();
     }
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kWave * kBatchWaves) void d2q9_batch(
 // wg_first[b] is the lattice of workgroup b's first tile, so each wavefront
 // finds its lattice by a short forward scan.  Launch shape as the single
 // lattice step (16 strips per workgroup, XCD-aware renumbering).
-template <int S, bool WALLS>
+template <int S, bool WALLS, int PSI>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_batch_flat(
     const BatchInstance* __restrict__ inst, const int* __restrict__ tile_start,
     const int* __restrict__ wg_first, int ntotal, int parity)
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_batch_flat(
     const BatchInstance& I = inst[i];
     const StepConst k = I.k;
     DiagConst dg{};
-    strip_tile<S, WALLS, kModeStep>(reinterpret_cast<const T*>(I.f[parity]), reinterpret_cast<T*>(I.f[parity ^ 1]),
+    strip_tile<S, WALLS, kModeStep, PSI>(reinterpret_cast<const T*>(I.f[parity]), reinterpret_cast<T*>(I.f[parity ^ 1]),
                                     k, g - tile_start[i], lane, I.flag, nullptr, nullptr, nullptr, dg, nullptr);
 }
 
@@ -328,11 +328,14 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
         const float r = rho0[i];
         const float ux = ux0 ? ux0[i] : 0.0f, uy = uy0 ? uy0[i] : 0.0f;
         bool bad = !(r > 0.0f) || !isfinite(ux) || !isfinite(uy) || !isfinite(r);
-        if (!bad) pseudopotential(r, k, bad);
+        if (!bad) {
+            if (ic.psi.form == kPsiSS) pseudopotential<kPsiSS>(r, k, bad);
+            else pseudopotential<kPsiCS>(r, k, bad);
+        }
         if (bad) flag[0] = kFlagBadInput;
     }
-    // psi (FP64) on the 5 x 5 block around (x, y): the force of Eq. (7) at the
-    // nine sites this one pulls from.  Rows beyond a wall take the adjacent
+    // psi (FP64, Eq. (24) or Eq. (23)) on the 5 x 5 block around (x, y): the force
+    // of Eq. (7) at the nine sites this one pulls from.  Rows beyond a wall take the adjacent
     // fluid row; they are read only by sites inside the lattice.
     double psi[5][5];
 #pragma unroll
@@ -345,8 +348,7 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
             int xx = x + i - 2;
             xx = xx < 0 ? xx + k.nx : (xx >= k.nx ? xx - k.nx : xx);
             const double r = rho0[(long long)yy * k.nx + xx];
-            const double s2 = 2.0 * (p_eos_f64(r, ic.b4, ic.RT, ic.a) - r / 3.0) / ic.G;
-            psi[j][i] = s2 > 0.0 ? sqrt(s2) : 0.0;
+            psi[j][i] = sqrt(psi2_f64(r, ic.psi));
         }
     }
 #pragma unroll
@@ -374,7 +376,7 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
             sy += w * ps * EY[c];
         }
         const double pc = psi[2 + dy][2 + dx];
-        const double Fx = -ic.G * pc * sx, Fy = -ic.G * pc * sy;
+        const double Fx = -ic.psi.G * pc * sx, Fy = -ic.psi.G * pc * sy;
         const long long i = (long long)ys * k.nx + xs;
         const double r = rho0[i];
         // Eq. (6): the equilibrium velocity is u0 - F / (2 rho0), so that the
@@ -404,16 +406,27 @@ static int strip_blocks(const StepConst& k)
     return (int)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
-template <int S, bool WALLS, int MODE>
+template <int S, bool WALLS, int MODE, int PSI>
 static hipError_t launch_mode(const void* fin, void* fout, const StepConst& k, int* flag,
                               float* rho, float* ux, float* uy, const DiagConst& dg,
                               double* partial, hipStream_t s)
 {
     using T = typename Codec<S>::T;
-    hipLaunchKernelGGL((d2q9_strip<S, WALLS, MODE>), dim3(strip_blocks(k)),
+    hipLaunchKernelGGL((d2q9_strip<S, WALLS, MODE, PSI>), dim3(strip_blocks(k)),
                        dim3(kWave * kWavesPerBlock), 0, s, static_cast<const T*>(fin),
                        static_cast<T*>(fout), k, flag, rho, ux, uy, dg, partial);
     return hipGetLastError();
+}
+
+// the pseudopotential form of k selects the instantiation
+template <int MODE, int S, bool WALLS>
+static hipError_t launch_psi(const void* fin, void* fout, const StepConst& k, int* flag,
+                             float* rho, float* ux, float* uy, const DiagConst& dg,
+                             double* partial, hipStream_t s)
+{
+    return k.psi_form == kPsiSS
+               ? launch_mode<S, WALLS, MODE, kPsiSS>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+               : launch_mode<S, WALLS, MODE, kPsiCS>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
 }
 
 template <int MODE>
@@ -423,23 +436,23 @@ static hipError_t dispatch(int store, bool walls, const void* fin, void* fout, c
 {
     switch (store) {
     case kStoreF32:
-        return walls ? launch_mode<kStoreF32, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
-                     : launch_mode<kStoreF32, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+        return walls ? launch_psi<MODE, kStoreF32, true>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_psi<MODE, kStoreF32, false>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
     case kStoreF16:
-        return walls ? launch_mode<kStoreF16, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
-                     : launch_mode<kStoreF16, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+        return walls ? launch_psi<MODE, kStoreF16, true>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_psi<MODE, kStoreF16, false>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
     case kStoreBF16:
-        return walls ? launch_mode<kStoreBF16, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
-                     : launch_mode<kStoreBF16, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+        return walls ? launch_psi<MODE, kStoreBF16, true>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_psi<MODE, kStoreBF16, false>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
     case kStoreF16Local:
-        return walls ? launch_mode<kStoreF16Local, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
-                     : launch_mode<kStoreF16Local, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+        return walls ? launch_psi<MODE, kStoreF16Local, true>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_psi<MODE, kStoreF16Local, false>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
     case kStoreBF16Local:
-        return walls ? launch_mode<kStoreBF16Local, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
-                     : launch_mode<kStoreBF16Local, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+        return walls ? launch_psi<MODE, kStoreBF16Local, true>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_psi<MODE, kStoreBF16Local, false>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
     case kStoreF16Dest:
-        return walls ? launch_mode<kStoreF16Dest, true, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
-                     : launch_mode<kStoreF16Dest, false, MODE>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
+        return walls ? launch_psi<MODE, kStoreF16Dest, true>(fin, fout, k, flag, rho, ux, uy, dg, partial, s)
+                     : launch_psi<MODE, kStoreF16Dest, false>(fin, fout, k, flag, rho, ux, uy, dg, partial, s);
     default:
         return hipErrorInvalidValue;
     }
@@ -450,7 +463,7 @@ int step_blocks_per_cu(int store, bool walls)
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
 #define LBMP_OCC(S_, W_)                                                                              \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, d2q9_strip<S_, W_, kModeStep>,              \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, d2q9_strip<S_, W_, kModeStep, kPsiCS>,              \
                                                      kWave * kWavesPerBlock, 0)
     switch (store) {
     case kStoreF32: if (walls) LBMP_OCC(kStoreF32, true); else LBMP_OCC(kStoreF32, false); break;
@@ -473,13 +486,19 @@ hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const
                                nullptr, s);
 }
 
-hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n, int steps, int parity,
-                        unsigned long long* clocks, hipStream_t s)
+hipError_t launch_batch(int store, bool walls, int psi, const BatchInstance* inst, int n, int steps,
+                        int parity, unsigned long long* clocks, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
 #define LBMP_BATCH(S_, W_)                                                                         \
-    hipLaunchKernelGGL((d2q9_batch<S_, W_>), dim3(n), dim3(kWave * kBatchWaves), 0, s, inst,         \
-                       steps, parity, clocks)
+    do {                                                                                           \
+        if (psi == kPsiSS)                                                                         \
+            hipLaunchKernelGGL((d2q9_batch<S_, W_, kPsiSS>), dim3(n), dim3(kWave * kBatchWaves), 0, s, \
+                               inst, steps, parity, clocks);                                       \
+        else                                                                                       \
+            hipLaunchKernelGGL((d2q9_batch<S_, W_, kPsiCS>), dim3(n), dim3(kWave * kBatchWaves), 0, s, \
+                               inst, steps, parity, clocks);                                       \
+    } while (0)
     switch (store) {
     case kStoreF32: if (walls) LBMP_BATCH(kStoreF32, true); else LBMP_BATCH(kStoreF32, false); break;
     case kStoreF16Local: if (walls) LBMP_BATCH(kStoreF16Local, true); else LBMP_BATCH(kStoreF16Local, false); break;
@@ -490,14 +509,22 @@ hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_flat(int store, bool walls, const BatchInstance* inst, const int* tile_start,
+hipError_t launch_batch_flat(int store, bool walls, int psi, const BatchInstance* inst, const int* tile_start,
                              const int* wg_first, int ntotal, int parity, hipStream_t s)
 {
     if (ntotal <= 0) return hipSuccess;
     const int blocks = (ntotal + kWavesPerBlock - 1) / kWavesPerBlock;
 #define LBMP_FLAT(S_, W_)                                                                          \
-    hipLaunchKernelGGL((d2q9_batch_flat<S_, W_>), dim3(blocks), dim3(kWave * kWavesPerBlock), 0, s, \
-                       inst, tile_start, wg_first, ntotal, parity)
+    do {                                                                                           \
+        if (psi == kPsiSS)                                                                         \
+            hipLaunchKernelGGL((d2q9_batch_flat<S_, W_, kPsiSS>), dim3(blocks),                    \
+                               dim3(kWave * kWavesPerBlock), 0, s, inst, tile_start, wg_first,     \
+                               ntotal, parity);                                                    \
+        else                                                                                       \
+            hipLaunchKernelGGL((d2q9_batch_flat<S_, W_, kPsiCS>), dim3(blocks),                    \
+                               dim3(kWave * kWavesPerBlock), 0, s, inst, tile_start, wg_first,     \
+                               ntotal, parity);                                                    \
+    } while (0)
     switch (store) {
     case kStoreF32: if (walls) LBMP_FLAT(kStoreF32, true); else LBMP_FLAT(kStoreF32, false); break;
     case kStoreF16Local: if (walls) LBMP_FLAT(kStoreF16Local, true); else LBMP_FLAT(kStoreF16Local, false); break;

@@ -8,20 +8,22 @@
 namespace lbmp {
 
 // One time step: pull from `fin`, collide, store into `fout` (both the
-// post-collision layout).  Sets flag[0] on an unstable site.
+// post-collision layout).  Sets flag[0] on an unstable site.  The pseudopotential
+// form is k.psi_form (also for the moments and diagnostics passes).
 hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
                        int* flag, hipStream_t s);
 
 // Persistent batched step: workgroup i advances lattice inst[i] by `steps`
 // steps starting from buffer `parity`; clocks[2i], clocks[2i+1] receive the
-// wall clock at the workgroup's start and end.  Stores: F32, F16 local.
-hipError_t launch_batch(int store, bool walls, const BatchInstance* inst, int n, int steps, int parity,
-                        unsigned long long* clocks, hipStream_t s);
+// wall clock at the workgroup's start and end.  Stores: F32, F16 local, F16
+// destination-scaled; `psi` (kPsiCS / kPsiSS) is shared by all lattices.
+hipError_t launch_batch(int store, bool walls, int psi, const BatchInstance* inst, int n, int steps,
+                        int parity, unsigned long long* clocks, hipStream_t s);
 
 // Flat batched step: one step of every lattice in one launch over the global
 // tile list (tile_start: n+1 prefix sums; wg_first: lattice of each
 // workgroup's first tile, indexed by the renumbered workgroup id).
-hipError_t launch_batch_flat(int store, bool walls, const BatchInstance* inst, const int* tile_start,
+hipError_t launch_batch_flat(int store, bool walls, int psi, const BatchInstance* inst, const int* tile_start,
                              const int* wg_first, int ntotal, int parity, hipStream_t s);
 
 // Resident step workgroups per compute unit (0 if the query fails).

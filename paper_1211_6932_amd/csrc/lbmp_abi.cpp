@@ -108,10 +108,16 @@ lb_status validate(const lb_params* p)
     if (p->bc != LB_BC_PERIODIC && p->bc != LB_BC_WALLS_Y) return fail(LB_EINVAL, "unknown bc");
     if (p->store < LB_STORE_F32 || p->store > LB_STORE_F16_DEST) return fail(LB_EINVAL, "unknown store");
     if (!finite_all({p->a, p->b, p->R, p->T, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta, p->s_j,
-                     p->s_q, p->nu_l, p->nu_g, p->rho_switch, p->rho_ref}))
+                     p->s_q, p->nu_l, p->nu_g, p->rho_switch, p->rho_ref, p->psi_eps}))
         return fail(LB_EINVAL, "non-finite parameter");
-    if (!(p->b > 0.0) || !(p->T > 0.0) || !(p->R > 0.0) || !(p->a >= 0.0))
-        return fail(LB_EINVAL, "need a >= 0, b > 0, R > 0, T > 0");
+    if (p->psi_form == LB_PSI_CS) {
+        if (!(p->b > 0.0) || !(p->T > 0.0) || !(p->R > 0.0) || !(p->a >= 0.0))
+            return fail(LB_EINVAL, "need a >= 0, b > 0, R > 0, T > 0");
+    } else if (p->psi_form == LB_PSI_SS) {
+        if (!(p->psi_eps >= 0.0)) return fail(LB_EINVAL, "need psi_eps >= 0 (Eq. 23)");
+    } else {
+        return fail(LB_EINVAL, "unknown psi_form");
+    }
     if (!(p->G < 0.0)) return fail(LB_EINVAL, "need G < 0 (Eq. 24 radicand)");
     if (!(p->sigma >= 0.0)) return fail(LB_EINVAL, "need sigma >= 0");
     if (!rate_ok(p->s_rho) || !rate_ok(p->s_e) || !rate_ok(p->s_zeta) || !rate_ok(p->s_j) ||
@@ -122,6 +128,11 @@ lb_status validate(const lb_params* p)
     if ((p->store == LB_STORE_F16_OFFSET || p->store == LB_STORE_BF16_OFFSET) && !(p->rho_ref >= 0.0))
         return fail(LB_EINVAL, "rho_ref must be >= 0");
     return LB_OK;
+}
+
+lbmp::PsiConst psi_const(const lb_params& p)
+{
+    return lbmp::PsiConst{p.b / 4.0, p.R * p.T, p.a, p.G, p.psi_eps, p.psi_form};
 }
 
 lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
@@ -149,6 +160,9 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
     const double G2 = p.G * p.G;
     k.c_e = (float)(12.0 * p.sigma * G2 * p.s_e);
     k.c_z = (float)(12.0 * p.sigma * G2 * p.s_zeta);
+    k.psi_form = p.psi_form;
+    k.psi_eps = (float)p.psi_eps;
+    k.inv_psi_eps = p.psi_eps > 0.0 ? (float)(1.0 / p.psi_eps) : 0.0f;
     static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     const bool global16 = p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET;
@@ -334,7 +348,7 @@ lb_status init_ctx(lb_ctx** out, const lb_params* p, void* workspace, size_t wor
     hipError_t e = hipMemsetAsync(c->flag, 0, kAlign, c->stream);
     if (e == hipSuccess)
         e = lbmp::launch_init(p->store, p->bc == LB_BC_WALLS_Y, rho0, ux0, uy0, c->f[0], c->k,
-                              lbmp::InitConst{p->b / 4.0, p->R * p->T, p->a, p->G}, c->flag, c->stream);
+                              lbmp::InitConst{psi_const(*p)}, c->flag, c->stream);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "init launch");
@@ -409,8 +423,7 @@ static lbmp::DiagConst diag_const(const lb_ctx* c, const lb_region* in, const lb
 {
     return lbmp::DiagConst{in->cx, in->cy, in->r_min, in->r_max,
                            outr->cx, outr->cy, outr->r_min, outr->r_max,
-                           c->p.b / 4.0, c->p.R * c->p.T, c->p.a,
-                           c->p.bc == LB_BC_PERIODIC ? 1 : 0};
+                           psi_const(c->p), c->p.bc == LB_BC_PERIODIC ? 1 : 0};
 }
 
 // Host lb_diag from the finalised sums [mass, mom_x, mom_y, sum p_in, sum p_out,
@@ -564,7 +577,7 @@ struct lb_batch {
     lbmp::BatchInstance* desc;       // device descriptors in dispatch order
     unsigned long long* clocks;      // device, 2 per workgroup
     hipStream_t stream;
-    int store, bc;
+    int store, bc, psi;
     bool poisoned;
 };
 
@@ -634,7 +647,7 @@ hipError_t write_batch_descriptors(lb_batch* b)
 
 hipError_t batch_flat_launch(lb_batch* b, int parity)
 {
-    return lbmp::launch_batch_flat(b->store, b->bc == LB_BC_WALLS_Y, b->desc, b->tile_start, b->wg_first,
+    return lbmp::launch_batch_flat(b->store, b->bc == LB_BC_WALLS_Y, b->psi, b->desc, b->tile_start, b->wg_first,
                                    b->ntotal, parity, b->stream);
 }
 
@@ -668,8 +681,8 @@ lb_status validate_batch(const lb_params* p, int32_t n)
     for (int i = 0; i < n; ++i) {
         lb_status st = validate(p + i);
         if (st != LB_OK) return fail(st, "lattice " + std::to_string(i) + ": " + g_last_error);
-        if (p[i].store != p[0].store || p[i].bc != p[0].bc)
-            return fail(LB_EINVAL, "all lattices of a batch share store and bc");
+        if (p[i].store != p[0].store || p[i].bc != p[0].bc || p[i].psi_form != p[0].psi_form)
+            return fail(LB_EINVAL, "all lattices of a batch share store, bc and psi_form");
     }
     if (p[0].store != LB_STORE_F32 && p[0].store != LB_STORE_F16_LOCAL && p[0].store != LB_STORE_F16_DEST)
         return fail(LB_EINVAL, "batched storage must be LB_STORE_F32, LB_STORE_F16_LOCAL or LB_STORE_F16_DEST");
@@ -705,6 +718,7 @@ lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* wor
     b->stream = static_cast<hipStream_t>(stream);
     b->store = p[0].store;
     b->bc = p[0].bc;
+    b->psi = p[0].psi_form;
     char* ws = static_cast<char*>(workspace);
     size_t hoff = 0;
     b->desc = reinterpret_cast<lbmp::BatchInstance*>(ws + hoff);
@@ -772,7 +786,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t nsteps)
     int parity = b->inst[0]->cur;
     hipError_t e = hipSuccess;
     if (b->mode == LB_BATCH_PERSISTENT) {
-        e = lbmp::launch_batch(b->store, b->bc == LB_BC_WALLS_Y, b->desc, b->n, (int)nsteps, parity, b->clocks,
+        e = lbmp::launch_batch(b->store, b->bc == LB_BC_WALLS_Y, b->psi, b->desc, b->n, (int)nsteps, parity, b->clocks,
                                b->stream);
     } else {
         e = hipEventRecord(b->ev[0], b->stream);

@@ -42,8 +42,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    # lb_params: 4 int32 + 15 doubles; lb_diag: 11 doubles + 2 int32 + int64
-    assert ctypes.sizeof(B.lb_params) == 16 + 15 * 8
+    # lb_params: 4 int32 + 15 doubles + 2 int32 + 1 double; lb_diag: 11 doubles + 2 int32 + int64
+    assert ctypes.sizeof(B.lb_params) == 16 + 15 * 8 + 8 + 8
     assert ctypes.sizeof(B.lb_diag) == 11 * 8 + 8 + 8
     assert ctypes.sizeof(B.lb_region) == 32
 
@@ -64,7 +64,7 @@ def test_validate_accepts_paper_parameters():
     ("nx", 2), ("ny", 0), ("nx", (1 << 20) + 1), ("bc", 2), ("store", 6), ("store", -1), ("b", 0.0), ("T", -1.0),
     ("G", 0.0), ("G", 1.0), ("sigma", -0.1), ("s_e", 0.0), ("s_e", 2.0), ("s_q", 2.5),
     ("s_rho", -1.0), ("s_j", 2.0), ("nu_l", 0.0), ("nu_g", -0.1), ("a", float("nan")),
-    ("R", 0.0), ("T", float("inf")),
+    ("R", 0.0), ("T", float("inf")), ("psi_form", 2), ("psi_form", -1), ("psi_eps", float("nan")),
 ])
 def test_validate_rejects(field, value):
     p = good()
@@ -73,6 +73,25 @@ def test_validate_rejects(field, value):
     assert B.lb_last_error() != ""
     assert B.lb_workspace_bytes(p) == 0
     assert B.lb_state_bytes(p) == 0
+
+
+def test_validate_eq23_pseudopotential():
+    """LB_PSI_SS (Eq. 23) needs G < 0 and psi_eps >= 0; the Carnahan-Starling constants
+    are then unused and not checked."""
+    p = B.make_params(W.ss_params(64, 64, -2.7, 1.0, sigma=0.023))
+    assert p.psi_form == B.LB_PSI_SS
+    assert B.lb_validate_params(p) == B.LB_OK
+    p.b, p.T, p.R = 0.0, 0.0, 0.0
+    assert B.lb_validate_params(p) == B.LB_OK
+    for field, value in (("psi_eps", -0.5), ("G", 0.5)):
+        q = B.make_params(W.ss_params(64, 64, -2.7, 1.0))
+        setattr(q, field, value)
+        assert B.lb_validate_params(q) == B.LB_EINVAL
+    # lattices of one batch share the pseudopotential form
+    a = B.make_params(W.stationary_droplet(n=64).params)
+    b = B.make_params(W.ss_params(64, 64, -2.7, 1.0))
+    assert B.lb_batch_workspace_bytes((B.lb_params * 2)(a, b), 2) == 0
+    assert B.lb_batch_workspace_bytes((B.lb_params * 2)(b, b), 2) > 0
 
 
 def test_sizes():
