@@ -16,6 +16,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 
@@ -63,11 +64,17 @@ def _counter_by_kernel(d, counter):
     return vals
 
 
+def _is_step_kernel(name):
+    """The time-step instantiation d2q9_strip<store, walls, MODE = 0, psi form>."""
+    m = re.search(r"d2q9_strip<(\d+), (true|false), (\d+), (\d+)>", name)
+    return bool(m) and m.group(3) == "0"
+
+
 def traffic(fetch_dir, write_dir, store, sites):
     res = {}
     for counter, d, key in (("FETCH_SIZE", fetch_dir, "read"), ("WRITE_SIZE", write_dir, "write")):
         vals = _counter_by_kernel(d, counter)
-        step = [v for k, v in vals.items() if "d2q9_strip" in k and ", 0>" in k]
+        step = [v for k, v in vals.items() if _is_step_kernel(k)]
         copy = [v for k, v in vals.items() if "copy_probe" in k]
         if not step or not copy:
             raise RuntimeError(f"{counter}: step or copy-probe dispatches missing in {d}")
@@ -76,7 +83,7 @@ def traffic(fetch_dir, write_dir, store, sites):
         scale = COPY_BYTES / (copy_kib * 1024.0)
         res[key] = dict(counter_kib_per_launch=step_kib, copy_counter_kib=copy_kib, scale=scale,
                         bytes_per_launch=step_kib * 1024.0 * scale)
-    bps = {"f32": 72, "f16": 36, "bf16": 36, "f16local": 44, "bf16local": 44}[store]
+    bps = {"f32": 72, "f16": 36, "bf16": 36, "f16local": 44, "bf16local": 44, "f16dest": 40}[store]
     total = res["read"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
     return dict(store=store, sites=sites, kernel_sha=kernel_hash(), bytes_per_launch=total,
                 algorithmic_bytes=bps * sites, ratio=total / (bps * sites), detail=res)

@@ -71,3 +71,13 @@ def test_spread_half_width_matches_closed_form_and_oracle():
         if y > film + 1.0:
             dy = (film + R - 4.0) - y  # circle centre above the line
             assert abs(got - math.sqrt(R * R - dy * dy)) < 0.01
+
+
+def test_profile_parser_picks_the_time_step_instantiation():
+    """prof.traffic reads the counters of d2q9_strip<store, walls, MODE 0, psi form> only."""
+    from paper_1211_6932_amd import prof
+    assert prof._is_step_kernel("void lbmp::d2q9_strip<0, true, 0, 0>(lbmp::Codec<0>::T const*, ...)")
+    assert prof._is_step_kernel("void lbmp::d2q9_strip<5, false, 0, 1>(lbmp::Codec<5>::T const*, ...)")
+    assert not prof._is_step_kernel("void lbmp::d2q9_strip<0, true, 2, 0>(lbmp::Codec<0>::T const*, ...)")
+    assert not prof._is_step_kernel("void lbmp::d2q9_strip<0, true, 1, 0>(lbmp::Codec<0>::T const*, ...)")
+    assert not prof._is_step_kernel("void lbmp::d2q9_batch<0, true, 0>(lbmp::BatchInstance const*, ...)")
