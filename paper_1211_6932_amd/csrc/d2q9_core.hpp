@@ -39,6 +39,19 @@ constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies, one
 constexpr int kDiagFields = 10;       // doubles per wave partial in the diagnostics pass
 
 enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2, kStoreF16Local = 3, kStoreBF16Local = 4, kStoreF16Dest = 5 };
+
+#ifndef LBMP_WAVES_PER_BLOCK_DEST
+#define LBMP_WAVES_PER_BLOCK_DEST 4
+#endif
+// Wavefronts per workgroup of the single-lattice strip kernels, by storage.  The
+// FP32 step is bound by HBM and streams best with one 16-wave workgroup per CU
+// (the resident waves then cover the fewest rows); the destination-scaled FP16
+// step is bound by latency and issue, and gains from more, smaller workgroups
+// per CU (measured on the 8192 x 4096 splash: 106k vs 98k MLUPS with 4 waves).
+constexpr int step_waves_per_block(int store)
+{
+    return store == kStoreF16Dest ? LBMP_WAVES_PER_BLOCK_DEST : kWavesPerBlock;
+}
 enum : int { kModeStep = 0, kModeMoments = 1, kModeDiag = 2 };
 enum : int { kFlagUnstable = 1, kFlagBadInput = 2 };
 enum : int { kPsiCS = 0, kPsiSS = 1 };  // psi of Eq. (24) from Eq. (30), or of Eq. (23)
@@ -91,9 +104,9 @@ struct DiagConst {
 };
 
 // ---------------------------------------------------------------- storage codecs
-// Element access by 32-bit byte offset from a (wave-uniform) row pointer: the
-// compiler can then address with a scalar base and a 32-bit vector offset.
-// Valid because a padded row is limited to < 4 GiB (host validation).
+// Element access by 32-bit byte offset from a (wave-uniform) row pointer (the
+// initial-state kernel).  Valid because a padded row is limited to < 4 GiB
+// (host validation).
 template <class T>
 __device__ __forceinline__ T& at(T* p, unsigned byte_off)
 {
@@ -105,29 +118,51 @@ __device__ __forceinline__ const T& at(const T* p, unsigned byte_off)
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
 }
 
-#ifndef LBMP_NT_LOAD
-#define LBMP_NT_LOAD 0
-#endif
-#ifndef LBMP_NT_STORE
-#define LBMP_NT_STORE 0
-#endif
-template <class T>
-__device__ __forceinline__ T ld(const T* p, unsigned byte_off)
+// Step-loop accesses go through buffer instructions: a buffer resource made from
+// the (wave-uniform) start of a lattice row, the population slot's byte offset
+// as the scalar offset and the column's byte offset as the 32-bit vector offset.
+// The hardware adds the three, so no 64-bit address is formed per lane and
+// access, and the nine slots of a row share one resource.  The record count is
+// the maximum, so no range check applies (every offset stays inside the row,
+// which host validation keeps below 4 GiB).
+constexpr int kRsrcFlags = 0x00020000;  // dword 3 of a raw (stride 0) gfx9 buffer resource
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* row)
 {
-#if LBMP_NT_LOAD
-    return __builtin_nontemporal_load(&at(p, byte_off));
-#else
-    return at(p, byte_off);
-#endif
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), (short)0, (int)0xffffffff, kRsrcFlags);
+}
+
+// The slot offset is wave-uniform by construction; saying so keeps it in a
+// scalar register (a value the compiler cannot prove uniform would otherwise be
+// served by a loop over its distinct lane values).
+__device__ __forceinline__ int uniform(unsigned v) { return __builtin_amdgcn_readfirstlane((int)v); }
+
+template <class T>
+__device__ __forceinline__ T ld(const void* row, unsigned slot_off, unsigned col)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 2, "32- or 16-bit elements");
+    const __amdgpu_buffer_rsrc_t r = row_rsrc(row);
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)col, uniform(slot_off), 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)col, uniform(slot_off), 0));
 }
 template <class T>
-__device__ __forceinline__ void st(T* p, unsigned byte_off, T v)
+__device__ __forceinline__ void st(void* row, unsigned slot_off, unsigned col, T v)
 {
-#if LBMP_NT_STORE
-    __builtin_nontemporal_store(v, &at(p, byte_off));
-#else
-    at(p, byte_off) = v;
-#endif
+    static_assert(sizeof(T) == 4 || sizeof(T) == 2, "32- or 16-bit elements");
+    const __amdgpu_buffer_rsrc_t r = row_rsrc(row);
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)col, uniform(slot_off), 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)col, uniform(slot_off), 0);
+}
+
+// Byte offset of population slot a (or the density slots, a = 9) within a lattice row.
+template <class T>
+__device__ __forceinline__ unsigned slot_bytes(const StepConst& k, int a)
+{
+    return (unsigned)a * (unsigned)k.pitch * (unsigned)sizeof(T);
 }
 
 // Lattice weight of population a (4/9 rest, 1/9 axis, 1/36 diagonal).
@@ -148,10 +183,10 @@ template <> struct Codec<kStoreF32> {
     static constexpr int kRowSlots = 9;  // T-sized row slots per lattice row
     static constexpr bool kDestScaled = false;
     static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
-        return ld(row + a * k.pitch, col);
+        return ld<T>(row, slot_bytes<T>(k, a), col);
     }
     static __device__ __forceinline__ void store(T* row, const StepConst& k, int a, unsigned col, float v, float) {
-        st(row + a * k.pitch, col, v);
+        st<T>(row, slot_bytes<T>(k, a), col, v);
     }
     static __device__ __forceinline__ void store_density(T*, const StepConst&, unsigned, float) {}
     static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v, double,
@@ -167,10 +202,10 @@ template <class H> struct CodecGlobal {
     static constexpr int kRowSlots = 9;
     static constexpr bool kDestScaled = false;
     static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
-        return static_cast<float>(ld(row + a * k.pitch, col)) + k.off[a];
+        return static_cast<float>(ld<T>(row, slot_bytes<T>(k, a), col)) + k.off[a];
     }
     static __device__ __forceinline__ void store(T* row, const StepConst& k, int a, unsigned col, float v, float) {
-        st(row + a * k.pitch, col, static_cast<T>(v - k.off[a]));  // round to nearest even
+        st<T>(row, slot_bytes<T>(k, a), col, static_cast<T>(v - k.off[a]));  // round to nearest even
     }
     static __device__ __forceinline__ void store_density(T*, const StepConst&, unsigned, float) {}
     static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v, double,
@@ -189,19 +224,16 @@ template <class H> struct CodecLocal {
     using T = H;
     static constexpr int kRowSlots = 11;
     static constexpr bool kDestScaled = false;
-    static __device__ __forceinline__ const float* dens(const T* row, const StepConst& k) {
-        return reinterpret_cast<const float*>(row + 9 * k.pitch);
-    }
     static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
-        const float rho = ld(dens(row, k), 2u * col);
-        return rho * (lattice_weight(a) + static_cast<float>(ld(row + a * k.pitch, col)));
+        const float rho = ld<float>(row, slot_bytes<T>(k, 9), 2u * col);
+        return rho * (lattice_weight(a) + static_cast<float>(ld<T>(row, slot_bytes<T>(k, a), col)));
     }
     static __device__ __forceinline__ void store(T* row, const StepConst& k, int a, unsigned col, float v,
                                                  float inv_rho) {
-        st(row + a * k.pitch, col, static_cast<T>(fmaf(v, inv_rho, -lattice_weight(a))));
+        st<T>(row, slot_bytes<T>(k, a), col, static_cast<T>(fmaf(v, inv_rho, -lattice_weight(a))));
     }
     static __device__ __forceinline__ void store_density(T* row, const StepConst& k, unsigned col, float rho) {
-        st(reinterpret_cast<float*>(row + 9 * k.pitch), 2u * col, rho);
+        st<float>(row, slot_bytes<T>(k, 9), 2u * col, rho);
     }
     static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v,
                                                       double rho, double) {
@@ -226,25 +258,22 @@ struct CodecDest {
     using T = _Float16;
     static constexpr int kRowSlots = 10;
     static constexpr bool kDestScaled = true;
-    static __device__ __forceinline__ const __bf16* dens(const T* row, const StepConst& k) {
-        return reinterpret_cast<const __bf16*>(row + 9 * k.pitch);
-    }
     static __device__ __forceinline__ float round_scale(float rho) {
         return static_cast<float>(static_cast<__bf16>(rho));
     }
     static __device__ __forceinline__ float scale(const T* row, const StepConst& k, unsigned col) {
-        return static_cast<float>(ld(dens(row, k), col));
+        return static_cast<float>(ld<__bf16>(row, slot_bytes<T>(k, 9), col));
     }
     // g_a only: pull_row forms rhohat g_a + rhohat w_a with the puller's own scale
     static __device__ __forceinline__ float load(const T* row, const StepConst& k, int a, unsigned col) {
-        return static_cast<float>(ld(row + a * k.pitch, col));
+        return static_cast<float>(ld<T>(row, slot_bytes<T>(k, a), col));
     }
     static __device__ __forceinline__ void store(T* row, const StepConst& k, int a, unsigned col, float v,
                                                  float inv_scale_dest) {
-        st(row + a * k.pitch, col, static_cast<T>(fmaf(v, inv_scale_dest, -lattice_weight(a))));
+        st<T>(row, slot_bytes<T>(k, a), col, static_cast<T>(fmaf(v, inv_scale_dest, -lattice_weight(a))));
     }
     static __device__ __forceinline__ void store_density(T* row, const StepConst& k, unsigned col, float rho) {
-        st(reinterpret_cast<__bf16*>(row + 9 * k.pitch), col, static_cast<__bf16>(rho));
+        st<__bf16>(row, slot_bytes<T>(k, 9), col, static_cast<__bf16>(rho));
     }
     static __device__ __forceinline__ void store_init(T* row, const StepConst& k, int a, unsigned col, double v,
                                                       double rho, double rho_dest) {

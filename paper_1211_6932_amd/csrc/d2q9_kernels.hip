@@ -54,36 +54,41 @@ __device__ __forceinline__ void strip_tile(
     const int y1 = min(y0 + k.strip_rows, k.ny);
 
     bool bad = false;
-    float f[9], fn[9], fq[9];
+    // Three row buffers (rows y, y+1, y+2 in flight), three psi windows and three
+    // windows of 1/rhohat (destination-scaled storage) for rows y-1, y, y+1, each a
+    // value and its two x-neighbours, and three densities.  The row loop below is
+    // unrolled three times with the roles rotated, so sliding the window down moves
+    // no data.
+    struct Win { float L, C, R; };
+    float fa[9], fb[9], fc[9];
+    Win wa{0.0f, 0.0f, 0.0f}, wb{0.0f, 0.0f, 0.0f}, wc{0.0f, 0.0f, 0.0f};
+    Win ia{0.0f, 0.0f, 0.0f}, ib{0.0f, 0.0f, 0.0f}, ic{0.0f, 0.0f, 0.0f};
+    float ra = 0.0f, rb = 0.0f, rc = 0.0f;
 
     // psi of the row above the strip (y0 - 1), or its mirror at a wall
-    float pm = 0.0f;
-    // destination-scaled storage: 1/rhohat of rows y-1, y, y+1 at columns x-1, x, x+1
-    float im = 0.0f, imL = 0.0f, imR = 0.0f, ic = 0.0f, icL = 0.0f, icR = 0.0f;
+    float pm = 0.0f, im = 0.0f;
     int yh = y0 - 1;
     if (!WALLS && yh < 0) yh += k.ny;
     if (yh >= 0) {
-        pull_row<S, WALLS>(fin, k, yh, xm, xc, xp, fn);
-        const float rm = density(fn);
+        pull_row<S, WALLS>(fin, k, yh, xm, xc, xp, fb);
+        const float rm = density(fb);
         pm = pseudopotential<PSI>(rm, k, bad);
         if constexpr (C::kDestScaled) im = recip(C::round_scale(rm));
     }
-    pull_row<S, WALLS>(fin, k, y0, xm, xc, xp, f);
+    pull_row<S, WALLS>(fin, k, y0, xm, xc, xp, fa);
     // row y0 + 1 is requested before row y0 is consumed (two rows in flight)
     const bool has1 = !WALLS || y0 + 1 < k.ny;
-    if (has1) pull_row<S, WALLS>(fin, k, (y0 + 1 < k.ny) ? y0 + 1 : y0 + 1 - k.ny, xm, xc, xp, fn);
-    float rc = density(f);
-    float pc = pseudopotential<PSI>(rc, k, bad);
-    if (WALLS && y0 == 0) pm = pc;
-    float pmL = lane_from_left(pm), pmR = lane_from_right(pm);
-    float pcL = lane_from_left(pc), pcR = lane_from_right(pc);
+    if (has1) pull_row<S, WALLS>(fin, k, (y0 + 1 < k.ny) ? y0 + 1 : y0 + 1 - k.ny, xm, xc, xp, fb);
+    ra = density(fa);
+    const float pc0 = pseudopotential<PSI>(ra, k, bad);
+    if (WALLS && y0 == 0) pm = pc0;
+    wa = Win{lane_from_left(pm), pm, lane_from_right(pm)};
+    wb = Win{lane_from_left(pc0), pc0, lane_from_right(pc0)};
     if constexpr (C::kDestScaled) {
-        ic = recip(C::round_scale(rc));
-        if (WALLS && y0 == 0) im = ic;
-        imL = lane_from_left(im);
-        imR = lane_from_right(im);
-        icL = lane_from_left(ic);
-        icR = lane_from_right(ic);
+        const float ic0 = recip(C::round_scale(ra));
+        if (WALLS && y0 == 0) im = ic0;
+        ia = Win{lane_from_left(im), im, lane_from_right(im)};
+        ib = Win{lane_from_left(ic0), ic0, lane_from_right(ic0)};
     }
 
     double acc[kDiagFields];
@@ -91,9 +96,12 @@ __device__ __forceinline__ void strip_tile(
         for (int i = 0; i < kDiagFields; ++i) acc[i] = 0.0;
     }
 
-    for (int y = y0; y < y1; ++y) {
-        // rows in flight: fn = row y + 1 (issued one iteration ago), fq = row y + 2
-        // (issued now, needed only by the next iteration's psi halo)
+    // One row y.  f: row y (pulled), fn: row y+1 (pulled), fq: receives row y+2;
+    // r: density of row y, rn: receives the density of row y+1; psi windows m, c
+    // (rows y-1, y) and p (receives row y+1); likewise the 1/rhohat windows.
+    auto row = [&](const int y, float (&f)[9], float (&fn)[9], float (&fq)[9], float& r, float& rn,
+                   const Win& m, const Win& c, Win& p, const Win& dm, const Win& dc, Win& dp)
+                   __attribute__((always_inline)) {
         const bool has_n = !WALLS || y + 1 < k.ny;
         const bool has_q = (y + 2 <= y1) && (!WALLS || y + 2 < k.ny);
         if (has_q) {
@@ -101,99 +109,92 @@ __device__ __forceinline__ void strip_tile(
             if (yq >= k.ny) yq -= k.ny;
             pull_row<S, WALLS>(fin, k, yq, xm, xc, xp, fq);
         }
-        float pp, rn = 0.0f;
+        float pp;
+        rn = 0.0f;
         if (has_n) {
             rn = density(fn);
             pp = pseudopotential<PSI>(rn, k, bad);
         } else {
-            pp = pc;  // mirror beyond the top wall
+            pp = c.C;  // mirror beyond the top wall
         }
-        const float ppL = lane_from_left(pp), ppR = lane_from_right(pp);
-        float in = 0.0f, inL = 0.0f, inR = 0.0f;
+        p = Win{lane_from_left(pp), pp, lane_from_right(pp)};
         if constexpr (C::kDestScaled) {
-            in = has_n ? recip(C::round_scale(rn)) : ic;
-            inL = lane_from_left(in);
-            inR = lane_from_right(in);
+            const float in = has_n ? recip(C::round_scale(rn)) : dc.C;
+            dp = Win{lane_from_left(in), in, lane_from_right(in)};
         }
 
         float Fx, Fy, Fs2;
-        force_stencil(pmL, pm, pmR, pcL, pc, pcR, ppL, pp, ppR, k, Fx, Fy, Fs2);
+        force_stencil(m.L, m.C, m.R, c.L, c.C, c.R, p.L, p.C, p.R, k, Fx, Fy, Fs2);
         const float jx = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));
         const float jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
-        const float inv_rho = recip(rc);
+        const float inv_rho = recip(r);
         const float vx = fmaf(0.5f, Fx, jx) * inv_rho;
         const float vy = fmaf(0.5f, Fy, jy) * inv_rho;
 
         if (MODE == kModeStep) {
-            collide(f, rc, vx, vy, Fx, Fy, Fs2, k);
+            collide(f, r, vx, vy, Fx, Fy, Fs2, k);
             if (live) {
-                typename C::T* row = fout + (long long)y * k.row_stride;
+                typename C::T* out = fout + (long long)y * k.row_stride;
                 if constexpr (C::kDestScaled) {
                     // 1/rhohat of the site that pulls population a next step: the
                     // neighbour at x + e_a, or this site for a population that
                     // reflects at a wall
                     const bool bot = WALLS && y == 0, top = WALLS && y == k.ny - 1;
                     float id[9];
-                    id[0] = ic;
-                    id[1] = icR;
-                    id[3] = icL;
-                    id[2] = top ? ic : in;
-                    id[5] = top ? ic : inR;
-                    id[6] = top ? ic : inL;
-                    id[4] = bot ? ic : im;
-                    id[7] = bot ? ic : imL;
-                    id[8] = bot ? ic : imR;
+                    id[0] = dc.C;
+                    id[1] = dc.R;
+                    id[3] = dc.L;
+                    id[2] = top ? dc.C : dp.C;
+                    id[5] = top ? dc.C : dp.R;
+                    id[6] = top ? dc.C : dp.L;
+                    id[4] = bot ? dc.C : dm.C;
+                    id[7] = bot ? dc.C : dm.L;
+                    id[8] = bot ? dc.C : dm.R;
 #pragma unroll
-                    for (int a = 0; a < 9; ++a) C::store(row, k, a, xc, f[a], id[a]);
+                    for (int a = 0; a < 9; ++a) C::store(out, k, a, xc, f[a], id[a]);
                 } else {
 #pragma unroll
-                    for (int a = 0; a < 9; ++a) C::store(row, k, a, xc, f[a], inv_rho);
+                    for (int a = 0; a < 9; ++a) C::store(out, k, a, xc, f[a], inv_rho);
                 }
-                C::store_density(row, k, xc, rc);
+                C::store_density(out, k, xc, r);
             }
         } else if (MODE == kModeMoments) {
             if (live) {
                 const long long o = (long long)y * k.nx + xci;
-                if (rho_out) rho_out[o] = rc;
+                if (rho_out) rho_out[o] = r;
                 if (ux_out) ux_out[o] = vx;
                 if (uy_out) uy_out[o] = vy;
             }
         } else {
             if (live) {
-                const double r = rc;
-                const double p = pressure_f64(r, dg.psi);
-                acc[0] += r;
-                acc[1] += r * (double)vx;
-                acc[2] += r * (double)vy;
+                const double rr = r;
+                const double pr = pressure_f64(rr, dg.psi);
+                acc[0] += rr;
+                acc[1] += rr * (double)vx;
+                acc[2] += rr * (double)vy;
                 double dx = fabs((double)xci - dg.in_cx);
                 dx = fmin(dx, (double)k.nx - dx);
                 double dy = fabs((double)y - dg.in_cy);
                 if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
                 double d = sqrt(dx * dx + dy * dy);
-                if (d >= dg.in_r0 && d < dg.in_r1) { acc[3] += p; acc[5] += r; acc[7] += 1.0; }
+                if (d >= dg.in_r0 && d < dg.in_r1) { acc[3] += pr; acc[5] += rr; acc[7] += 1.0; }
                 dx = fabs((double)xci - dg.out_cx);
                 dx = fmin(dx, (double)k.nx - dx);
                 dy = fabs((double)y - dg.out_cy);
                 if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
                 d = sqrt(dx * dx + dy * dy);
-                if (d >= dg.out_r0 && d < dg.out_r1) { acc[4] += p; acc[6] += r; acc[8] += 1.0; }
+                if (d >= dg.out_r0 && d < dg.out_r1) { acc[4] += pr; acc[6] += rr; acc[8] += 1.0; }
                 acc[9] = fmax(acc[9], (double)sqrtf(vx * vx + vy * vy));
             }
         }
+    };
 
-        // slide the window one row down
-        pmL = pcL; pm = pc; pmR = pcR;
-        pcL = ppL; pc = pp; pcR = ppR;
-        rc = rn;
-        if constexpr (C::kDestScaled) {
-            imL = icL; im = ic; imR = icR;
-            icL = inL; ic = in; icR = inR;
-        }
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            f[a] = fn[a];
-            fn[a] = fq[a];
-        }
+    for (int y = y0; y < y1; y += 3) {
+        row(y, fa, fb, fc, ra, rb, wa, wb, wc, ia, ib, ic);
+        if (y + 1 >= y1) break;
+        row(y + 1, fb, fc, fa, rb, rc, wb, wc, wa, ib, ic, ia);
+        if (y + 2 >= y1) break;
+        row(y + 2, fc, fa, fb, rc, ra, wc, wa, wb, ic, ia, ib);
     }
 
     if (MODE == kModeDiag) {
@@ -207,7 +208,7 @@ __device__ __forceinline__ void strip_tile(
 }
 
 template <int S, bool WALLS, int MODE, int PSI>
-__global__ __launch_bounds__(kWave * kWavesPerBlock)
+__global__ __launch_bounds__(kWave * step_waves_per_block(S))
 __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
     const typename Codec<S>::T* __restrict__ fin, typename Codec<S>::T* __restrict__ fout,
     StepConst k, int* __restrict__ flag, float* __restrict__ rho_out, float* __restrict__ ux_out,
@@ -217,7 +218,7 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
     // the wave index is uniform across the wave: keep it (and every row address
     // derived from it) in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = logical_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+    const int tile = logical_block(blockIdx.x, gridDim.x) * step_waves_per_block(S) + wave;
     if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
     strip_tile<S, WALLS, MODE, PSI>(fin, fout, k, tile, lane, flag, rho_out, ux_out, uy_out, dg, partial);
 }
@@ -400,10 +401,10 @@ __global__ __launch_bounds__(256) void copy_probe(const float4* __restrict__ src
 
 // ---------------------------------------------------------------- launchers
 
-static int strip_blocks(const StepConst& k)
+static int strip_blocks(const StepConst& k, int waves_per_block)
 {
     const long long tiles = (long long)k.tiles_x * k.tiles_y;
-    return (int)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    return (int)((tiles + waves_per_block - 1) / waves_per_block);
 }
 
 template <int S, bool WALLS, int MODE, int PSI>
@@ -412,8 +413,9 @@ static hipError_t launch_mode(const void* fin, void* fout, const StepConst& k, i
                               double* partial, hipStream_t s)
 {
     using T = typename Codec<S>::T;
-    hipLaunchKernelGGL((d2q9_strip<S, WALLS, MODE, PSI>), dim3(strip_blocks(k)),
-                       dim3(kWave * kWavesPerBlock), 0, s, static_cast<const T*>(fin),
+    constexpr int wpb = step_waves_per_block(S);
+    hipLaunchKernelGGL((d2q9_strip<S, WALLS, MODE, PSI>), dim3(strip_blocks(k, wpb)),
+                       dim3(kWave * wpb), 0, s, static_cast<const T*>(fin),
                        static_cast<T*>(fout), k, flag, rho, ux, uy, dg, partial);
     return hipGetLastError();
 }
@@ -464,7 +466,7 @@ int step_blocks_per_cu(int store, bool walls)
     hipError_t e = hipErrorInvalidValue;
 #define LBMP_OCC(S_, W_)                                                                              \
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, d2q9_strip<S_, W_, kModeStep, kPsiCS>,              \
-                                                     kWave * kWavesPerBlock, 0)
+                                                     kWave * step_waves_per_block(S_), 0)
     switch (store) {
     case kStoreF32: if (walls) LBMP_OCC(kStoreF32, true); else LBMP_OCC(kStoreF32, false); break;
     case kStoreF16: if (walls) LBMP_OCC(kStoreF16, true); else LBMP_OCC(kStoreF16, false); break;

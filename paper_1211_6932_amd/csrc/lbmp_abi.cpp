@@ -179,19 +179,21 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
 // strips, down to 2 rows.
 int auto_strip_rows(const lb_params& p)
 {
-    // preferred height (measured on the 8192 x 4096 splash): 3 rows for FP32 and
-    // the source-density encodings; the issue-bound 16-bit encodings gain from
-    // fewer recomputed halo rows: 4 rows for the global offsets, 8 for the
+    // preferred height (measured on the 8192 x 4096 splash): 3 rows for FP32;
+    // the issue-bound 16-bit encodings gain from fewer recomputed halo rows:
+    // 4 rows for the source-density ones, 8 for the global offsets and the
     // destination-scaled one
     int preferred = kMinStripRows;
-    if (p.store == LB_STORE_F16_DEST) preferred = 8;
-    else if (p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET) preferred = 4;
+    if (p.store == LB_STORE_F16_DEST || p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET)
+        preferred = 8;
+    else if (p.store == LB_STORE_F16_LOCAL || p.store == LB_STORE_BF16_LOCAL)
+        preferred = 4;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
         return preferred;
     const int nb = std::max(1, lbmp::step_blocks_per_cu(p.store, p.bc == LB_BC_WALLS_Y));
-    const long long resident = (long long)nb * lbmp::kWavesPerBlock * ncu;
+    const long long resident = (long long)nb * lbmp::step_waves_per_block(p.store) * ncu;
     const long long tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
     const long long strips_wanted = (resident + tiles_x - 1) / tiles_x;
     const long long h = std::max<long long>(2, p.ny / strips_wanted);
