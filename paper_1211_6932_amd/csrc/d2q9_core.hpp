@@ -68,8 +68,15 @@ struct StepConst {
     float two_over_G;           // 2 / G  (Eq. 24 with c = 1)
     float negG;                 // -G     (Eq. 7)
     float rho_switch;           // nu_l for rho >= rho_switch, nu_g below
-    float s_e, s_z, s_q, s_nu_l, s_nu_g;
-    float c_e, c_z;             // 12 sigma G^2 s_e, 12 sigma G^2 s_zeta (Eq. 25 through I - Lambda/2)
+    // Relaxation of the non-conserved moments (Eqs. 2-4, 25), with the column norms of
+    // M^-1 folded in (e, eps: 36; q: 12; p: 4): for the e moment
+    //   (m*_e - m_e) / 36 = -a_e (m_e - m_e^eq) + b_e v.F + c_e |Fs|^2,
+    // a_e = s_e / 36, b_e = 6 (1 - s_e/2) / 36, c_e = 12 sigma G^2 s_e / 36, and
+    // likewise for eps (a_z, b_z, c_z), q (a_q = s_q / 12, b_q = (1 - s_q/2) / 12) and
+    // the two shear moments (a_nu = s_nu / 4 per phase; b_nu = (1 - s_nu/2) / 2 for
+    // p_xx, whose forcing term is 2 (vx Fx - vy Fy), and half of it for p_xy).
+    float a_e, b_e, c_e, a_z, b_z, c_z, a_q, b_q;
+    float a_nu_l, b_nu_l, a_nu_g, b_nu_g;
     int psi_form;               // kPsiCS or kPsiSS
     float psi_eps, inv_psi_eps; // epsilon of Eq. (23) and 1/epsilon (0 when epsilon = 0)
     float off[9];               // w_a rho_ref: offsets of the 16-bit storage (0 for FP32)
@@ -476,52 +483,55 @@ __device__ __forceinline__ void force_stencil(float mL, float mC, float mR, floa
 // With v from Eq. (6): m*_rho - m_rho = 0 and m*_j - m_j = F exactly.
 // (1 - s/2) times the extra Eq. (25) terms equals +12 sigma G^2 s_e |Fs|^2 for e
 // and -12 sigma G^2 s_zeta |Fs|^2 for eps.
+// Every expression is written so that mirroring the site in x or in y (which
+// negates vx, Fx, m_qx, m_xy or their y counterparts) negates or keeps each
+// intermediate exactly: a mirror-symmetric state stays mirror-symmetric.
 __device__ __forceinline__ void collide(float f[9], float rho, float vx, float vy, float Fx,
                                         float Fy, float Fs2, const StepConst& k)
 {
-    const float ax = f[1] + f[2] + f[3] + f[4];
-    const float dg = f[5] + f[6] + f[7] + f[8];
+    const float s13 = f[1] + f[3], s24 = f[2] + f[4];
+    const float s57 = f[5] + f[7], s68 = f[6] + f[8];
+    const float ax = s13 + s24;
+    const float dg = s57 + s68;
     const float m_e = fmaf(-4.0f, f[0], fmaf(2.0f, dg, -ax));
     const float m_z = fmaf(4.0f, f[0], fmaf(-2.0f, ax, dg));
     const float d57 = f[5] - f[7], d68 = f[6] - f[8];
     const float m_qx = fmaf(-2.0f, f[1] - f[3], d57 - d68);
     const float m_qy = fmaf(-2.0f, f[2] - f[4], d57 + d68);
-    const float m_xx = (f[1] + f[3]) - (f[2] + f[4]);
-    const float m_xy = (f[5] + f[7]) - (f[6] + f[8]);
+    const float m_xx = s13 - s24;
+    const float m_xy = s57 - s68;
 
     const float vF = vx * Fx + vy * Fy;
     const float v2 = vx * vx + vy * vy;
-    const float s_nu = (rho >= k.rho_switch) ? k.s_nu_l : k.s_nu_g;
+    const bool liq = rho >= k.rho_switch;
+    const float a_nu = liq ? k.a_nu_l : k.a_nu_g;
+    const float b_nu = liq ? k.b_nu_l : k.b_nu_g;
 
-    // m* - m for the non-conserved moments (Eq. 4, Eq. 3, Eq. 25)
-    const float dm_e = -k.s_e * (m_e - rho * fmaf(3.0f, v2, -2.0f))
-                       + (1.0f - 0.5f * k.s_e) * 6.0f * vF + k.c_e * Fs2;
-    const float dm_z = -k.s_z * (m_z - rho * fmaf(-3.0f, v2, 1.0f))
-                       - (1.0f - 0.5f * k.s_z) * 6.0f * vF - k.c_z * Fs2;
-    const float hq = 1.0f - 0.5f * k.s_q;
-    const float dm_qx = -k.s_q * (m_qx + rho * vx) - hq * Fx;
-    const float dm_qy = -k.s_q * (m_qy + rho * vy) - hq * Fy;
-    const float hn = 1.0f - 0.5f * s_nu;
-    const float dm_xx = -s_nu * (m_xx - rho * (vx * vx - vy * vy)) + hn * 2.0f * (vx * Fx - vy * Fy);
-    const float dm_xy = -s_nu * (m_xy - rho * vx * vy) + hn * (vx * Fy + vy * Fx);
+    // (m* - m) / norm for the non-conserved moments (Eq. 4, Eq. 3, Eq. 25)
+    const float te = fmaf(-k.a_e, fmaf(-rho, fmaf(3.0f, v2, -2.0f), m_e), fmaf(k.b_e, vF, k.c_e * Fs2));
+    const float tz = fmaf(-k.a_z, fmaf(-rho, fmaf(-3.0f, v2, 1.0f), m_z), -fmaf(k.b_z, vF, k.c_z * Fs2));
+    const float qx = fmaf(-k.a_q, fmaf(rho, vx, m_qx), -k.b_q * Fx);
+    const float qy = fmaf(-k.a_q, fmaf(rho, vy, m_qy), -k.b_q * Fy);
+    const float pxx = fmaf(-a_nu, fmaf(-rho, vx * vx - vy * vy, m_xx), b_nu * (vx * Fx - vy * Fy));
+    const float pxy = fmaf(-a_nu, fmaf(-rho, vx * vy, m_xy), (0.5f * b_nu) * (vx * Fy + vy * Fx));
 
     // f* = f + M^-1 dm  (column k of M^-1 is row k of M divided by its norm)
-    const float te = dm_e * (1.0f / 36.0f), tz = dm_z * (1.0f / 36.0f);
     const float jx = Fx * (1.0f / 6.0f), jy = Fy * (1.0f / 6.0f);
-    const float qx = dm_qx * (1.0f / 12.0f), qy = dm_qy * (1.0f / 12.0f);
-    const float pxx = dm_xx * 0.25f, pxy = dm_xy * 0.25f;
-    const float c_ax = -te - 2.0f * tz;
-    const float c_dg = 2.0f * te + tz;
+    const float c_ax = fmaf(-2.0f, tz, -te);
+    const float c_dg = fmaf(2.0f, te, tz);
     f[0] += 4.0f * (tz - te);
-    f[1] += c_ax + jx - 2.0f * qx + pxx;
-    f[3] += c_ax - jx + 2.0f * qx + pxx;
-    f[2] += c_ax + jy - 2.0f * qy - pxx;
-    f[4] += c_ax - jy + 2.0f * qy - pxx;
+    const float ux = fmaf(-2.0f, qx, jx), uy = fmaf(-2.0f, qy, jy);
+    const float t13 = c_ax + pxx, t24 = c_ax - pxx;
+    f[1] += t13 + ux;
+    f[3] += t13 - ux;
+    f[2] += t24 + uy;
+    f[4] += t24 - uy;
     const float xp = jx + qx, yp = jy + qy;
-    f[5] += c_dg + xp + yp + pxy;
-    f[6] += c_dg - xp + yp - pxy;
-    f[7] += c_dg - xp - yp + pxy;
-    f[8] += c_dg + xp - yp - pxy;
+    const float d57p = c_dg + pxy, d68p = c_dg - pxy;
+    f[5] += (d57p + xp) + yp;
+    f[6] += (d68p - xp) + yp;
+    f[7] += (d57p - xp) - yp;
+    f[8] += (d68p + xp) - yp;
 }
 
 // Workgroups are dispatched round-robin over the XCDs (block b runs on XCD

@@ -152,14 +152,20 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
     k.two_over_G = (float)(2.0 / p.G);
     k.negG = (float)(-p.G);
     k.rho_switch = (float)p.rho_switch;
-    k.s_e = (float)p.s_e;
-    k.s_z = (float)p.s_zeta;
-    k.s_q = (float)p.s_q;
-    k.s_nu_l = (float)(1.0 / (3.0 * p.nu_l + 0.5));
-    k.s_nu_g = (float)(1.0 / (3.0 * p.nu_g + 0.5));
+    k.a_e = (float)(p.s_e / 36.0);
+    k.b_e = (float)(6.0 * (1.0 - 0.5 * p.s_e) / 36.0);
+    k.a_z = (float)(p.s_zeta / 36.0);
+    k.b_z = (float)(6.0 * (1.0 - 0.5 * p.s_zeta) / 36.0);
+    k.a_q = (float)(p.s_q / 12.0);
+    k.b_q = (float)((1.0 - 0.5 * p.s_q) / 12.0);
+    const double s_nu_l = 1.0 / (3.0 * p.nu_l + 0.5), s_nu_g = 1.0 / (3.0 * p.nu_g + 0.5);
+    k.a_nu_l = (float)(s_nu_l / 4.0);
+    k.b_nu_l = (float)((1.0 - 0.5 * s_nu_l) / 2.0);
+    k.a_nu_g = (float)(s_nu_g / 4.0);
+    k.b_nu_g = (float)((1.0 - 0.5 * s_nu_g) / 2.0);
     const double G2 = p.G * p.G;
-    k.c_e = (float)(12.0 * p.sigma * G2 * p.s_e);
-    k.c_z = (float)(12.0 * p.sigma * G2 * p.s_zeta);
+    k.c_e = (float)(12.0 * p.sigma * G2 * p.s_e / 36.0);
+    k.c_z = (float)(12.0 * p.sigma * G2 * p.s_zeta / 36.0);
     k.psi_form = p.psi_form;
     k.psi_eps = (float)p.psi_eps;
     k.inv_psi_eps = p.psi_eps > 0.0 ? (float)(1.0 / p.psi_eps) : 0.0f;
