@@ -355,7 +355,7 @@ def main():
     ap.add_argument("--train-runs", type=int, default=4096)
     ap.add_argument("--eval-droplets", type=int, default=256)
     ap.add_argument("--relax-steps", type=int, default=30000)
-    ap.add_argument("--train-steps", type=int, default=8000)
+    ap.add_argument("--train-steps", type=int, default=20000)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--batch-mode", default="stepwise", choices=["stepwise", "persistent"])
     ap.add_argument("--gpus", type=int, default=1)

@@ -9,7 +9,14 @@ the tanh base profile (the same Eq. (31) recipe the lattice starts from),
 convergence detection on the recorded diagnostics.
 
 Features: (a, T/T_c, R0, nu_g/nu_l).  Outputs: L_k = log rho(r_k),
-r_k = R0 + (k - 63.5) / 2, predicted as tanh base + network correction.
+r_k = R + (k - 63.5) / 2, predicted as tanh base + network correction.  The
+training profiles are sampled around the relaxed droplet's equimolar radius
+R = sqrt((M - rho_out N) / (pi (rho_in - rho_out))), not around R0: mass is
+conserved, so where the interface settles is fixed by the start's mass, and at
+inference the predicted profile is moved radially until it carries the tanh
+start's mass.  The network then learns only the shape of the profile; the
+position, which jumps with the lattice as R0 varies (the tanh start's mass is a
+lattice sum), comes from the mass of the droplet at hand.
 
 Convergence of one run (checked every `every` steps), against the values a
 tanh-started run of the same droplet reaches at the end of the window:
@@ -98,10 +105,16 @@ def n_conv(U, DP, u_ref, dp_ref, every, strict=False):
     return out
 
 
-def relaxed_profiles(batch, ws, members):
+def equimolar_radius(mass, rho_in, rho_out, sites):
+    """Radius of the disc of density rho_in in a background rho_out that holds `mass`."""
+    return math.sqrt(max(mass - rho_out * sites, 0.0) / (math.pi * (rho_in - rho_out)))
+
+
+def relaxed_profiles(batch, ws, members, centres=None):
     """Least-squares profile of the current density field of batch lattices `members`
-    (descriptions `ws`), [n][128] device tensor.  The fits run on the batch's stream,
-    ordered after the moments they read."""
+    (descriptions `ws`), sampled around radius centres[i] (default R0), [n][128]
+    device tensor.  The fits run on the batch's stream, ordered after the moments
+    they read."""
     import torch
     out = torch.empty((len(ws), N_OUT), dtype=torch.float32, device=batch.device)
     scratch = torch.empty(max(lbmp.lbml_profile_scratch_bytes(w.params["ny"]) for w in ws), dtype=torch.uint8,
@@ -109,7 +122,8 @@ def relaxed_profiles(batch, ws, members):
     s = batch.stream.cuda_stream
     for i, (m, w) in enumerate(zip(members, ws)):
         rho = batch.moments(int(m))[0]
-        lbmp.profile_extract(rho, w.info["cx"], w.info["cy"], w.info["R0"], out=out[i], scratch=scratch, stream=s)
+        R = w.info["R0"] if centres is None else float(centres[i])
+        lbmp.profile_extract(rho, w.info["cx"], w.info["cy"], R, out=out[i], scratch=scratch, stream=s)
         rho.record_stream(batch.stream)
     batch.stream.synchronize()
     return out
@@ -131,10 +145,13 @@ def generate(ws, steps, every=1000, log=None):
         if log:
             log(f"training runs: step {done}/{steps}  {time.time() - t0:.1f} s")
     rin, rout = zip(*[regions(w) for w in ws])
-    kept = np.array([not d["unstable"] for d in batch.diagnostics_all(rin, rout)])
+    diag = batch.diagnostics_all(rin, rout)
+    kept = np.array([not d["unstable"] for d in diag])
     members = np.nonzero(kept)[0]
     keep = [ws[i] for i in members]
-    prof = relaxed_profiles(batch, keep, members).cpu().numpy().astype(np.float64)
+    centres = [equimolar_radius(diag[i]["mass"], diag[i]["rho_in"], diag[i]["rho_out"],
+                                ws[i].params["nx"] * ws[i].params["ny"]) for i in members]
+    prof = relaxed_profiles(batch, keep, members, centres).cpu().numpy().astype(np.float64)
     batch.close()
     finite = np.all(np.isfinite(prof), axis=1)
     kept[members[~finite]] = False
