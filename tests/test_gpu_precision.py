@@ -70,7 +70,9 @@ def raw_state(s, store):
     enc = h16.float().cpu().numpy().astype(np.float64).reshape(9, s.ny, s.nx)
     rho = None
     if store in LOCAL:
-        rho = buf[2 * n:].view(torch.float32).cpu().numpy().astype(np.float64).reshape(s.ny, s.nx)
+        # the FP32 densities follow 9 nx ny halves: copy them out before viewing as
+        # floats (the packed offset is not 4-byte aligned when 9 nx ny is odd)
+        rho = buf[2 * n:].clone().view(torch.float32).cpu().numpy().astype(np.float64).reshape(s.ny, s.nx)
     elif store in DEST:
         rho = buf[2 * n:].view(torch.bfloat16).float().cpu().numpy().astype(np.float64).reshape(s.ny, s.nx)
     return enc, rho
@@ -106,17 +108,11 @@ def ulp16(x, store):
     return 2.0 ** (e - 10)
 
 
-@pytest.mark.parametrize("store", GLOBAL + LOCAL + DEST)
-@pytest.mark.parametrize("case", ["droplet_periodic", "splash_walls"])
-def test_one_step_is_the_oracle_rounded_once(store, case):
-    if case == "droplet_periodic":
-        w = W.stationary_droplet(n=96, R0=20)
-    else:
-        w = W.splash(nx=192, ny=96, Re=200)
-        w.info["R"] = 100
-    print(f"[gpu-case] precision one-step store={store} case={case}", flush=True)
+def one_step_excess(w, store, strip_rows):
+    """Largest excess of |GPU step - oracle step| over the bound of one rounding of the
+    encoding (plus the FP32 arithmetic allowance), from the same stored state."""
     rho_ref = w.info.get("rho_l", 0.4) if store in GLOBAL else 0.0
-    s = make_sim(w, store, strip_rows=16)
+    s = make_sim(w, store, strip_rows=strip_rows)
     s.step(5)
     e5, r5 = raw_state(s, store)
     s.step(1)
@@ -137,8 +133,36 @@ def test_one_step_is_the_oracle_rounded_once(store, case):
     else:
         bound = 0.5 * ulp16(ref - (WEIGHTS * rho_ref)[:, None, None], store)
     bound = bound + 2e-6 * np.abs(ref).max()
-    excess = np.abs(got - ref) - bound
-    assert excess.max() <= 0.0, (store, case, float(excess.max()))
+    return float((np.abs(got - ref) - bound).max())
+
+
+@pytest.mark.parametrize("store", GLOBAL + LOCAL + DEST)
+@pytest.mark.parametrize("case", ["droplet_periodic", "splash_walls"])
+def test_one_step_is_the_oracle_rounded_once(store, case):
+    if case == "droplet_periodic":
+        w = W.stationary_droplet(n=96, R0=20)
+    else:
+        w = W.splash(nx=192, ny=96, Re=200)
+        w.info["R"] = 100
+    print(f"[gpu-case] precision one-step store={store} case={case}", flush=True)
+    excess = one_step_excess(w, store, strip_rows=16)
+    assert excess <= 0.0, (store, case, excess)
+
+
+@pytest.mark.parametrize("store", ["f16local", "f16dest"])
+@pytest.mark.parametrize("shape", [(3, 3), (5, 3), (3, 70), (64, 3), (63, 125)])
+def test_one_step_on_tiny_and_ragged_grids(store, shape):
+    """The 16-bit encodings (their own workgroup shapes and strip heights) on single-tile
+    grids down to 3 x 3 and ragged tiles, periodic and with walls."""
+    ny, nx = shape
+    rng = np.random.default_rng(nx * 1000 + ny)
+    rho0 = 0.2 + 0.02 * rng.standard_normal((ny, nx))
+    for bc in (0, 1):
+        p = W.base_params(nx, ny, a=0.5, t_over_tc=0.8, bc=bc)
+        w = W.Workload("tiny", p, rho0, info=dict(rho_l=0.2))
+        print(f"[gpu-case] precision one-step store={store} shape={shape} bc={bc}", flush=True)
+        excess = one_step_excess(w, store, strip_rows=0)
+        assert excess <= 0.0, (store, shape, bc, excess)
 
 
 @pytest.mark.parametrize("store", GLOBAL + LOCAL + DEST)
