@@ -1,11 +1,13 @@
 // d2q9_kernels.hip -- gfx950 kernels of the improved MRT pseudopotential D2Q9
 // method and their host-side launchers.
 //
-//   d2q9_strip<MODE>  one template walks a wavefront strip (pull, density,
-//                     psi, force, velocity) and then, by MODE, collides and
-//                     stores (the time step), writes rho/v (moments), or
-//                     accumulates FP64 reductions (diagnostics).
+//   d2q9_strip<store, walls, MODE, psi form>
+//                     one template walks a wavefront strip (pull, density,
+//                     psi of Eq. (24) or Eq. (23), force, velocity) and then, by
+//                     MODE, collides and stores (the time step), writes rho/v
+//                     (moments), or accumulates FP64 reductions (diagnostics).
 //   d2q9_batch        persistent multi-instance step (one workgroup per lattice)
+//   d2q9_batch_flat   one step of many lattices in one launch over their strips
 //   d2q9_init         equilibrium initial state, written "pre-streamed" so
 //                     that the first pull returns f_eq(rho0, u0)
 //   diag_finalize     fixed-order FP64 reduction of the per-wave partials
