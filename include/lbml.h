@@ -9,7 +9,7 @@
  * the tanh profile by the relaxed profile predicted by a small network trained
  * on profiles that the lattice itself produced, so that a run starts close to
  * its equilibrium.  The tanh profile stays the fallback; the lattice run
- * judges the prediction.
+ * measures the prediction's error.
  *
  * Network: 4 features (a, T/T_c, R, nu_g/nu_l), standardised with a mean and
  * standard deviation fixed at lbml_init -> 3 hidden layers of 256 units with
