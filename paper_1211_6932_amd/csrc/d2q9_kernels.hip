@@ -21,6 +21,17 @@ namespace lbmp {
 #define LBMP_STEP_WAVES_PER_EU 1
 #endif
 
+// Wave priorities (s_setprio) while a wavefront issues loads: the prologue of a
+// strip (its first rows) above the prefetch of the next row inside the walk,
+// both above everything else (arithmetic and stores).  A wave that has just
+// started then gets its first requests out ahead of the resident waves, and
+// those issue their prefetches ahead of other waves' arithmetic.  Measured on
+// the 8192 x 4096 splash, FP32: 78.6k MLUPS against 76.1k without priorities,
+// 77.4k with the prologue raised alone and 77.4k with both raised to the same
+// level.
+constexpr short kPrioPrologue = 2;
+constexpr short kPrioPrefetch = 1;
+
 // Strips of alternate direction (see strip_tile): 0 never, 1 for the 16-bit
 // encodings, 2 for every encoding.
 #ifndef LBMP_ALT_WALK
@@ -70,6 +81,7 @@ __device__ __forceinline__ void strip_walk(
     float pm = 0.0f, im = 0.0f;
     const int yh = ys - DIR;
     const bool has_h = inside(yh);
+    __builtin_amdgcn_s_setprio(kPrioPrologue);
     if (has_h) {
         pull_row<S, WALLS>(fin, k, wrap(yh), xm, xc, xp, fb);
         const float rm = density(fb);
@@ -79,6 +91,7 @@ __device__ __forceinline__ void strip_walk(
     pull_row<S, WALLS>(fin, k, ys, xm, xc, xp, fa);
     // the second row is requested before the first is consumed (two rows in flight)
     if (inside(ys + DIR)) pull_row<S, WALLS>(fin, k, wrap(ys + DIR), xm, xc, xp, fb);
+    __builtin_amdgcn_s_setprio(0);
     ra = density(fa);
     const float pc0 = pseudopotential<PSI>(ra, k, bad);
     if (!has_h) pm = pc0;
@@ -106,7 +119,9 @@ __device__ __forceinline__ void strip_walk(
         const int y = ys + DIR * i;
         const bool has_n = inside(y + DIR);
         // rows up to one beyond the strip's last are pulled
+        __builtin_amdgcn_s_setprio(kPrioPrefetch);
         if (i + 2 <= n && inside(y + 2 * DIR)) pull_row<S, WALLS>(fin, k, wrap(y + 2 * DIR), xm, xc, xp, fq);
+        __builtin_amdgcn_s_setprio(0);
         float pa;
         rn = 0.0f;
         if (has_n) {
