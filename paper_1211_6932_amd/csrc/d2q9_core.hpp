@@ -24,6 +24,11 @@ namespace lbmp {
 
 constexpr int kWave = 64;
 constexpr int kTileW = kWave - 2;     // output columns per wavefront strip
+constexpr int kPairTileW = 2 * kWave - 4;  // output columns per wavefront, two columns per lane
+#ifndef LBMP_PAIR_WAVES
+#define LBMP_PAIR_WAVES 4
+#endif
+constexpr int kPairWaves = LBMP_PAIR_WAVES;  // wavefronts per workgroup, two columns per lane
 #ifndef LBMP_WAVES_PER_BLOCK
 #define LBMP_WAVES_PER_BLOCK 16
 #endif

@@ -292,6 +292,315 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
     strip_tile<S, WALLS, MODE, PSI>(fin, fout, k, tile, lane, flag, rho_out, ux_out, uy_out, dg, partial);
 }
 
+// ---------------------------------------------------------------- two columns per lane
+// Time step of the destination-scaled FP16 storage with two neighbouring
+// columns per lane.  The 16-bit step is bound by the number of vector memory
+// instructions, not by bytes: one 16-bit element per lane moves 128 bytes per
+// instruction.  Here every access is an aligned 32-bit pair (256 bytes per
+// instruction, half the instructions per site), and the one-column shift of the
+// pull along x comes from the neighbouring lane's pair (a lane shuffle) instead
+// of an unaligned load.  A wavefront covers 128 columns: lanes 1..62 own the 124
+// output columns, lane 0's second column and the first column right of the
+// output are the psi halo.  Each site's arithmetic is that of strip_walk, so the
+// results are bitwise those of the one-column kernel.  Needs an even nx, so that
+// no pair straddles the periodic seam.
+#ifndef LBMP_PAIR_BLOCKS_PER_CU
+#define LBMP_PAIR_BLOCKS_PER_CU 0
+#endif
+#ifndef LBMP_PAIR
+#define LBMP_PAIR 1
+#endif
+
+__device__ __forceinline__ float f16_lo(unsigned w)
+{
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w & 0xffffu)));
+}
+__device__ __forceinline__ float f16_hi(unsigned w)
+{
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w >> 16)));
+}
+__device__ __forceinline__ float bf16_lo(unsigned w)
+{
+    return static_cast<float>(__builtin_bit_cast(__bf16, static_cast<unsigned short>(w & 0xffffu)));
+}
+__device__ __forceinline__ float bf16_hi(unsigned w)
+{
+    return static_cast<float>(__builtin_bit_cast(__bf16, static_cast<unsigned short>(w >> 16)));
+}
+__device__ __forceinline__ unsigned pack_f16(float lo, float hi)
+{
+    return static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<_Float16>(lo))) |
+           (static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<_Float16>(hi))) << 16);
+}
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
+{
+    return static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<__bf16>(lo))) |
+           (static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<__bf16>(hi))) << 16);
+}
+
+// Raw pairs of lattice row y for the pull (Eq. 5): w[a] holds population a's
+// pair from the row it streams from (the row itself for a population that
+// reflects at a wall), w[9] the row's own bf16 scale pair.  qb: byte offset of
+// the lane's pair within a row.
+template <bool WALLS>
+__device__ __forceinline__ void pull_pair(const _Float16* __restrict__ fin, const StepConst& k, int y,
+                                          unsigned qb, unsigned w[10])
+{
+    int ya = y - 1, yb = y + 1;
+    bool bot = false, top = false;
+    if (WALLS) {
+        bot = ya < 0;
+        top = yb >= k.ny;
+    } else {
+        if (ya < 0) ya += k.ny;
+        if (yb >= k.ny) yb -= k.ny;
+    }
+    const _Float16* r0 = fin + (long long)y * k.row_stride;
+    const _Float16* ra = fin + (long long)(bot ? y : ya) * k.row_stride;
+    const _Float16* rb = fin + (long long)(top ? y : yb) * k.row_stride;
+    using T = _Float16;
+    w[0] = ld<unsigned>(r0, slot_bytes<T>(k, 0), qb);
+    w[1] = ld<unsigned>(r0, slot_bytes<T>(k, 1), qb);
+    w[3] = ld<unsigned>(r0, slot_bytes<T>(k, 3), qb);
+    w[2] = ld<unsigned>(ra, slot_bytes<T>(k, bot ? 4 : 2), qb);
+    w[5] = ld<unsigned>(ra, slot_bytes<T>(k, bot ? 7 : 5), qb);
+    w[6] = ld<unsigned>(ra, slot_bytes<T>(k, bot ? 8 : 6), qb);
+    w[4] = ld<unsigned>(rb, slot_bytes<T>(k, top ? 2 : 4), qb);
+    w[7] = ld<unsigned>(rb, slot_bytes<T>(k, top ? 5 : 7), qb);
+    w[8] = ld<unsigned>(rb, slot_bytes<T>(k, top ? 6 : 8), qb);
+    w[9] = ld<unsigned>(r0, slot_bytes<T>(k, 9), qb);
+}
+
+// Pulled populations of the lane's two sites (f0: left column, f1: right
+// column) from the raw pairs of row y.  A population moving in +x comes from
+// the column on the left: the high half of the left lane's pair for the first
+// site, the low half of the own pair for the second; one moving in -x from the
+// right; a population that reflects at a wall from the own column.
+template <bool WALLS>
+__device__ __forceinline__ void decode_pair(const StepConst& k, int y, const unsigned w[10], float f0[9],
+                                            float f1[9])
+{
+    const bool bot = WALLS && y == 0, top = WALLS && y == k.ny - 1;
+    const unsigned l1 = __shfl_up(w[1], 1, kWave), l5 = __shfl_up(w[5], 1, kWave);
+    const unsigned l8 = __shfl_up(w[8], 1, kWave);
+    const unsigned r3 = __shfl_down(w[3], 1, kWave), r6 = __shfl_down(w[6], 1, kWave);
+    const unsigned r7 = __shfl_down(w[7], 1, kWave);
+    f0[0] = f16_lo(w[0]); f1[0] = f16_hi(w[0]);
+    f0[2] = f16_lo(w[2]); f1[2] = f16_hi(w[2]);
+    f0[4] = f16_lo(w[4]); f1[4] = f16_hi(w[4]);
+    f0[1] = f16_hi(l1);   f1[1] = f16_lo(w[1]);
+    f0[3] = f16_hi(w[3]); f1[3] = f16_lo(r3);
+    f0[5] = bot ? f16_lo(w[5]) : f16_hi(l5);
+    f1[5] = bot ? f16_hi(w[5]) : f16_lo(w[5]);
+    f0[6] = bot ? f16_lo(w[6]) : f16_hi(w[6]);
+    f1[6] = bot ? f16_hi(w[6]) : f16_lo(r6);
+    f0[7] = top ? f16_lo(w[7]) : f16_hi(w[7]);
+    f1[7] = top ? f16_hi(w[7]) : f16_lo(r7);
+    f0[8] = top ? f16_lo(w[8]) : f16_hi(l8);
+    f1[8] = top ? f16_hi(w[8]) : f16_lo(w[8]);
+    // f_a = rhohat (w_a + g_a) with the puller's own scale (as pull_row)
+    const float sc[2] = {bf16_lo(w[9]), bf16_hi(w[9])};
+    float* f[2] = {f0, f1};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float sw0 = sc[j] * (4.0f / 9.0f), sw1 = sc[j] * (1.0f / 9.0f), sw2 = sc[j] * (1.0f / 36.0f);
+        f[j][0] = fmaf(f[j][0], sc[j], sw0);
+#pragma unroll
+        for (int a = 1; a < 5; ++a) f[j][a] = fmaf(f[j][a], sc[j], sw1);
+#pragma unroll
+        for (int a = 5; a < 9; ++a) f[j][a] = fmaf(f[j][a], sc[j], sw2);
+    }
+}
+
+// Values of a row at the lane's two sites and at the sites next to them: s0, s1
+// (own), L (left lane's second site), R (right lane's first site).
+struct PairWin { float s0, s1, L, R; };
+__device__ __forceinline__ PairWin pair_window(float v0, float v1)
+{
+    return PairWin{v0, v1, lane_from_left(v1), lane_from_right(v0)};
+}
+
+template <bool WALLS, int PSI, int DIR>
+__device__ __forceinline__ void pair_walk(const _Float16* __restrict__ fin, _Float16* __restrict__ fout,
+                                          const StepConst& k, const int ty, const bool live, const unsigned qb,
+                                          int* __restrict__ flag)
+{
+    using C = Codec<kStoreF16Dest>;
+    const int y0 = ty * k.strip_rows;
+    const int y1 = min(y0 + k.strip_rows, k.ny);
+    const int n = y1 - y0;
+    const int ys = DIR > 0 ? y0 : y1 - 1;
+    auto inside = [&](const int y) __attribute__((always_inline)) { return !WALLS || (y >= 0 && y < k.ny); };
+    auto wrap = [&](const int y) __attribute__((always_inline)) {
+        return y < 0 ? y + k.ny : (y >= k.ny ? y - k.ny : y);
+    };
+    // the unstable flag counts output sites only (every site is an output site of one lane)
+    bool bad = false;
+    auto psi2 = [&](const float r0, const float r1, float& p0, float& p1) __attribute__((always_inline)) {
+        bool b = false;
+        p0 = pseudopotential<PSI>(r0, k, b);
+        p1 = pseudopotential<PSI>(r1, k, b);
+        bad = bad || (b && live);
+    };
+
+    float fa0[9], fa1[9], fb0[9], fb1[9];
+    unsigned wa[10], wb[10];
+    PairWin pm, pc, im, ic;
+    float ra0, ra1;
+
+    // row before the first one walked (or its mirror at a wall), then the first
+    // two rows in flight
+    const int yh = ys - DIR;
+    const bool has_h = inside(yh);
+    __builtin_amdgcn_s_setprio(kPrioPrologue);
+    float h0 = 0.0f, h1 = 0.0f, hi0 = 0.0f, hi1 = 0.0f;
+    if (has_h) {
+        pull_pair<WALLS>(fin, k, wrap(yh), qb, wa);
+        decode_pair<WALLS>(k, wrap(yh), wa, fb0, fb1);
+        const float rm0 = density(fb0), rm1 = density(fb1);
+        psi2(rm0, rm1, h0, h1);
+        hi0 = recip(C::round_scale(rm0));
+        hi1 = recip(C::round_scale(rm1));
+    }
+    pull_pair<WALLS>(fin, k, ys, qb, wa);
+    if (inside(ys + DIR)) pull_pair<WALLS>(fin, k, wrap(ys + DIR), qb, wb);
+    __builtin_amdgcn_s_setprio(0);
+    decode_pair<WALLS>(k, ys, wa, fa0, fa1);
+    ra0 = density(fa0);
+    ra1 = density(fa1);
+    float c0, c1;
+    psi2(ra0, ra1, c0, c1);
+    const float ci0 = recip(C::round_scale(ra0)), ci1 = recip(C::round_scale(ra1));
+    if (!has_h) {
+        h0 = c0; h1 = c1;
+        hi0 = ci0; hi1 = ci1;
+    }
+    pm = pair_window(h0, h1);
+    pc = pair_window(c0, c1);
+    im = pair_window(hi0, hi1);
+    ic = pair_window(ci0, ci1);
+
+    // Row y at walk position i: f (decoded row y) and its densities r; wn holds
+    // the raw pairs of row y+DIR, wq receives those of row y+2 DIR; g receives
+    // the decoded row y+DIR.  Windows b, c: psi of rows y-DIR, y (likewise the
+    // 1/rhohat windows db, dc); on return b, db hold row y+DIR's windows
+    // (c, dc are left for the caller to rotate).
+    auto row = [&](const int i, float (&f0)[9], float (&f1)[9], float& r0, float& r1, float (&g0)[9],
+                   float (&g1)[9], const unsigned (&wn)[10], unsigned (&wq)[10], PairWin& b, const PairWin& c,
+                   PairWin& db, const PairWin& dc) __attribute__((always_inline)) {
+        const int y = ys + DIR * i;
+        const bool has_n = inside(y + DIR);
+        float rn0 = 0.0f, rn1 = 0.0f, pa0, pa1, in0, in1;
+        if (has_n) decode_pair<WALLS>(k, wrap(y + DIR), wn, g0, g1);
+        __builtin_amdgcn_s_setprio(kPrioPrefetch);
+        if (i + 2 <= n && inside(y + 2 * DIR)) pull_pair<WALLS>(fin, k, wrap(y + 2 * DIR), qb, wq);
+        __builtin_amdgcn_s_setprio(0);
+        if (has_n) {
+            rn0 = density(g0);
+            rn1 = density(g1);
+            psi2(rn0, rn1, pa0, pa1);
+            in0 = recip(C::round_scale(rn0));
+            in1 = recip(C::round_scale(rn1));
+        } else {  // mirror beyond a wall
+            pa0 = c.s0; pa1 = c.s1;
+            in0 = dc.s0; in1 = dc.s1;
+        }
+        const PairWin a = pair_window(pa0, pa1);
+        const PairWin da = pair_window(in0, in1);
+        // windows of rows y - 1 and y + 1
+        const PairWin& m = DIR > 0 ? b : a;
+        const PairWin& p = DIR > 0 ? a : b;
+        const PairWin& dm = DIR > 0 ? db : da;
+        const PairWin& dp = DIR > 0 ? da : db;
+
+        float Fx0, Fy0, Fs20, Fx1, Fy1, Fs21;
+        force_stencil(m.L, m.s0, m.s1, c.L, c.s0, c.s1, p.L, p.s0, p.s1, k, Fx0, Fy0, Fs20);
+        force_stencil(m.s0, m.s1, m.R, c.s0, c.s1, c.R, p.s0, p.s1, p.R, k, Fx1, Fy1, Fs21);
+        {
+            const float jx = (f0[1] - f0[3]) + ((f0[5] - f0[7]) + (f0[8] - f0[6]));
+            const float jy = (f0[2] - f0[4]) + ((f0[5] - f0[7]) + (f0[6] - f0[8]));
+            const float inv_rho = recip(r0);
+            collide(f0, r0, fmaf(0.5f, Fx0, jx) * inv_rho, fmaf(0.5f, Fy0, jy) * inv_rho, Fx0, Fy0, Fs20, k);
+        }
+        {
+            const float jx = (f1[1] - f1[3]) + ((f1[5] - f1[7]) + (f1[8] - f1[6]));
+            const float jy = (f1[2] - f1[4]) + ((f1[5] - f1[7]) + (f1[6] - f1[8]));
+            const float inv_rho = recip(r1);
+            collide(f1, r1, fmaf(0.5f, Fx1, jx) * inv_rho, fmaf(0.5f, Fy1, jy) * inv_rho, Fx1, Fy1, Fs21, k);
+        }
+        if (live) {
+            _Float16* out = fout + (long long)y * k.row_stride;
+            // 1/rhohat of the site that pulls population a next step (as strip_walk)
+            const bool bot = WALLS && y == 0, top = WALLS && y == k.ny - 1;
+            float id0[9], id1[9];
+            id0[0] = dc.s0;                   id1[0] = dc.s1;
+            id0[1] = dc.s1;                   id1[1] = dc.R;
+            id0[3] = dc.L;                    id1[3] = dc.s0;
+            id0[2] = top ? dc.s0 : dp.s0;     id1[2] = top ? dc.s1 : dp.s1;
+            id0[5] = top ? dc.s0 : dp.s1;     id1[5] = top ? dc.s1 : dp.R;
+            id0[6] = top ? dc.s0 : dp.L;      id1[6] = top ? dc.s1 : dp.s0;
+            id0[4] = bot ? dc.s0 : dm.s0;     id1[4] = bot ? dc.s1 : dm.s1;
+            id0[7] = bot ? dc.s0 : dm.L;      id1[7] = bot ? dc.s1 : dm.s0;
+            id0[8] = bot ? dc.s0 : dm.s1;     id1[8] = bot ? dc.s1 : dm.R;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const float wgt = lattice_weight(a);
+                st<unsigned>(out, slot_bytes<_Float16>(k, a), qb,
+                             pack_f16(fmaf(f0[a], id0[a], -wgt), fmaf(f1[a], id1[a], -wgt)));
+            }
+            st<unsigned>(out, slot_bytes<_Float16>(k, 9), qb, pack_bf16(r0, r1));
+        }
+        r0 = rn0;
+        r1 = rn1;
+        b = a;
+        db = da;
+    };
+
+    // two row buffers and two raw buffers alternate; the psi windows rotate
+    float rb0 = 0.0f, rb1 = 0.0f;
+    for (int i = 0; i < n; i += 2) {
+        // row i: f = a, g = b; windows (pm, pc) -> pm := row y+DIR
+        row(i, fa0, fa1, ra0, ra1, fb0, fb1, wb, wa, pm, pc, im, ic);
+        rb0 = ra0; rb1 = ra1;
+        // now pc holds row y, pm row y+DIR: swap roles so that (b, c) = (row y, row y+DIR)
+        { const PairWin t = pm; pm = pc; pc = t; }
+        { const PairWin t = im; im = ic; ic = t; }
+        if (i + 1 >= n) break;
+        row(i + 1, fb0, fb1, rb0, rb1, fa0, fa1, wa, wb, pm, pc, im, ic);
+        ra0 = rb0; ra1 = rb1;
+        { const PairWin t = pm; pm = pc; pc = t; }
+        { const PairWin t = im; im = ic; ic = t; }
+    }
+    if (bad) flag[0] = kFlagUnstable;
+}
+
+template <bool WALLS, int PSI>
+__global__ __launch_bounds__(kWave * kPairWaves)
+__attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_pair(
+    const _Float16* __restrict__ fin, _Float16* __restrict__ fout, StepConst k, int* __restrict__ flag)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = logical_block(blockIdx.x, gridDim.x) * kPairWaves + wave;
+    if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
+    // tiles in bands of `band` strips, as strip_tile (k.tiles_x counts 124-column tiles)
+    const int band0 = (tile / (k.tiles_x * k.band)) * k.band;
+    const int band_h = min(k.band, k.tiles_y - band0);
+    const int r = tile - band0 * k.tiles_x;
+    const int tx = r / band_h;
+    const int ty = band0 + r % band_h;
+    // first column of the lane's pair; the pair index wraps in x (nx even)
+    const int c0 = tx * kPairTileW - 2 + 2 * lane;
+    const bool live = (lane >= 1) && (lane <= kPairTileW / 2) && (c0 < k.nx);
+    const int q = c0 < 0 ? (k.nx >> 1) - 1 : (c0 >= k.nx ? 0 : (c0 >> 1));
+    const unsigned qb = (unsigned)q * 4u;
+    // odd strips walk towards decreasing y (as the one-column 16-bit step)
+    if (ty & 1)
+        pair_walk<WALLS, PSI, -1>(fin, fout, k, ty, live, qb, flag);
+    else
+        pair_walk<WALLS, PSI, 1>(fin, fout, k, ty, live, qb, flag);
+}
+
 // Persistent multi-instance step: one workgroup owns one lattice and advances
 // it `steps` time steps; its kBatchWaves wavefronts share the strips of each step and
 // meet at a workgroup barrier between steps (the barrier orders the global
@@ -575,9 +884,44 @@ int step_blocks_per_cu(int store, bool walls)
     return e == hipSuccess ? nb : 0;
 }
 
+// The two-columns-per-lane step of the destination-scaled FP16 storage (even nx).
+template <bool WALLS, int PSI>
+static hipError_t launch_pair_psi(const void* fin, void* fout, const StepConst& k, int* flag, hipStream_t s)
+{
+    StepConst kp = k;
+    kp.tiles_x = (k.nx + kPairTileW - 1) / kPairTileW;
+    const long long tiles = (long long)kp.tiles_x * kp.tiles_y;
+    const int blocks = (int)((tiles + kPairWaves - 1) / kPairWaves);
+    hipLaunchKernelGGL((d2q9_pair<WALLS, PSI>), dim3(blocks), dim3(kWave * kPairWaves),
+                       occupancy_cap_lds(LBMP_PAIR_BLOCKS_PER_CU), s, static_cast<const _Float16*>(fin),
+                       static_cast<_Float16*>(fout), kp, flag);
+    return hipGetLastError();
+}
+
+bool pair_step(int store, int nx)
+{
+    return LBMP_PAIR && store == kStoreF16Dest && nx % 2 == 0 && nx >= 4;
+}
+
+int pair_blocks_per_cu(bool walls)
+{
+    int nb = 0;
+    const hipError_t e =
+        walls ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, d2q9_pair<true, kPsiCS>, kWave * kPairWaves, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, d2q9_pair<false, kPsiCS>, kWave * kPairWaves, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
 hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
                        int* flag, hipStream_t s)
 {
+    if (pair_step(store, k.nx)) {
+        if (walls)
+            return k.psi_form == kPsiSS ? launch_pair_psi<true, kPsiSS>(fin, fout, k, flag, s)
+                                        : launch_pair_psi<true, kPsiCS>(fin, fout, k, flag, s);
+        return k.psi_form == kPsiSS ? launch_pair_psi<false, kPsiSS>(fin, fout, k, flag, s)
+                                    : launch_pair_psi<false, kPsiCS>(fin, fout, k, flag, s);
+    }
     DiagConst dg{};
     return dispatch<kModeStep>(store, walls, fin, fout, k, flag, nullptr, nullptr, nullptr, dg,
                                nullptr, s);

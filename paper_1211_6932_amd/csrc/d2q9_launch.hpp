@@ -13,6 +13,13 @@ namespace lbmp {
 hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
                        int* flag, hipStream_t s);
 
+// Whether launch_step runs the two-columns-per-lane kernel for this store type
+// and lattice width (destination-scaled FP16, even nx).
+bool pair_step(int store, int nx);
+
+// Resident workgroups per compute unit of the two-columns-per-lane step (0 if the query fails).
+int pair_blocks_per_cu(bool walls);
+
 // Persistent batched step: workgroup i advances lattice inst[i] by `steps`
 // steps starting from buffer `parity`; clocks[2i], clocks[2i+1] receive the
 // wall clock at the workgroup's start and end.  Stores: F32, F16 local, F16

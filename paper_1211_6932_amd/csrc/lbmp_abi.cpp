@@ -188,9 +188,12 @@ int auto_strip_rows(const lb_params& p)
     // preferred height (measured on the 8192 x 4096 splash): 3 rows for FP32;
     // the issue-bound 16-bit encodings gain from fewer recomputed halo rows:
     // 4 rows for the source-density ones, 8 for the global offsets and the
-    // destination-scaled one
+    // destination-scaled one with one column per lane, 4 for the latter with two
+    const bool pair = lbmp::pair_step(p.store, p.nx);
     int preferred = kMinStripRows;
-    if (p.store == LB_STORE_F16_DEST || p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET)
+    if (pair)
+        preferred = 4;
+    else if (p.store == LB_STORE_F16_DEST || p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET)
         preferred = 8;
     else if (p.store == LB_STORE_F16_LOCAL || p.store == LB_STORE_BF16_LOCAL)
         preferred = 4;
@@ -198,9 +201,11 @@ int auto_strip_rows(const lb_params& p)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
         return preferred;
-    const int nb = std::max(1, lbmp::step_blocks_per_cu(p.store, p.bc == LB_BC_WALLS_Y));
-    const long long resident = (long long)nb * lbmp::step_waves_per_block(p.store) * ncu;
-    const long long tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
+    const bool walls = p.bc == LB_BC_WALLS_Y;
+    const int nb = std::max(1, pair ? lbmp::pair_blocks_per_cu(walls) : lbmp::step_blocks_per_cu(p.store, walls));
+    const long long resident = (long long)nb * (pair ? lbmp::kPairWaves : lbmp::step_waves_per_block(p.store)) * ncu;
+    const int tile_w = pair ? lbmp::kPairTileW : lbmp::kTileW;
+    const long long tiles_x = (p.nx + tile_w - 1) / tile_w;
     const long long strips_wanted = (resident + tiles_x - 1) / tiles_x;
     const long long h = std::max<long long>(2, p.ny / strips_wanted);
     return (int)std::min<long long>(h, preferred);

@@ -67,7 +67,10 @@ def _counter_by_kernel(d, counter):
 
 
 def _is_step_kernel(name):
-    """The time-step instantiation d2q9_strip<store, walls, MODE = 0, psi form>."""
+    """A time-step kernel: d2q9_strip<store, walls, MODE = 0, psi form>, or the
+    two-columns-per-lane d2q9_pair<walls, psi form>."""
+    if re.search(r"d2q9_pair(<|I)", name):  # the profiler may leave this name mangled
+        return True
     m = re.search(r"d2q9_strip<(\d+), (true|false), (\d+), (\d+)>", name)
     return bool(m) and m.group(3) == "0"
 

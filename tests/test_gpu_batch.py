@@ -67,6 +67,30 @@ def test_batch_is_bitwise_equal_to_single_runs(store, bc, mode):
     b.close()
 
 
+@pytest.mark.parametrize("bc", [0, 1])
+def test_two_column_step_is_bitwise_the_one_column_step(bc):
+    """Destination-scaled FP16 with an even nx steps with two columns per lane; a batch
+    runs the one-column kernel.  Ragged width (250 = 2 x 124 + 2) and height, strip
+    heights from 1 to 7 (both walk directions), walls and periodic."""
+    nx, ny = 250, 77
+    p = W.base_params(nx, ny, a=0.5, t_over_tc=0.6, bc=bc)
+    rl, rg = W.coexistence(0.6)
+    rho0 = W.droplet_field(nx, ny, 20.0, rl, rg, periodic_y=(bc == 0))
+    print(f"[gpu-case] two-column step bc={bc} shape=({ny}, {nx})", flush=True)
+    b = B.Batch([p], [f32(rho0)], store="f16dest")
+    b.step(40)
+    assert b.check() == (B.LB_OK, 0)
+    ref = b.get_state(0, B.lb_state_bytes(B.make_params(p, "f16dest"))).cpu().numpy()
+    b.close()
+    for rows in (1, 2, 3, 4, 7):
+        s = B.Sim(p, f32(rho0), store="f16dest")
+        s.set_launch(strip_rows=rows)
+        s.step(40)
+        s.check()
+        assert np.array_equal(s.get_state().cpu().numpy(), ref), rows
+        s.close()
+
+
 def test_batch_times_and_moments():
     ws = mixed_lattices()
     b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws])
