@@ -150,10 +150,13 @@ def test_one_step_is_the_oracle_rounded_once(store, case):
 
 
 @pytest.mark.parametrize("store", ["f16local", "f16dest"])
-@pytest.mark.parametrize("shape", [(3, 3), (5, 3), (3, 70), (64, 3), (63, 125)])
+@pytest.mark.parametrize("shape", [(3, 3), (5, 3), (3, 70), (64, 3), (63, 125), (3, 4), (5, 6), (4, 126),
+                                   (7, 248)])
 def test_one_step_on_tiny_and_ragged_grids(store, shape):
     """The 16-bit encodings (their own workgroup shapes and strip heights) on single-tile
-    grids down to 3 x 3 and ragged tiles, periodic and with walls."""
+    grids down to 3 x 3 and ragged tiles, periodic and with walls.  Even widths run the
+    two-columns-per-lane step for f16dest: 4 (smallest), 126 (a full 124-column tile and
+    a 2-column one), 248 (two full tiles)."""
     ny, nx = shape
     rng = np.random.default_rng(nx * 1000 + ny)
     rho0 = 0.2 + 0.02 * rng.standard_normal((ny, nx))
