@@ -188,11 +188,11 @@ int auto_strip_rows(const lb_params& p)
     // preferred height (measured on the 8192 x 4096 splash): 3 rows for FP32;
     // the issue-bound 16-bit encodings gain from fewer recomputed halo rows:
     // 4 rows for the source-density ones, 8 for the global offsets and the
-    // destination-scaled one with one column per lane, 4 for the latter with two
+    // destination-scaled one with one column per lane, 5 for the latter with two
     const bool pair = lbmp::pair_step(p.store, p.nx);
     int preferred = kMinStripRows;
     if (pair)
-        preferred = 4;
+        preferred = 5;
     else if (p.store == LB_STORE_F16_DEST || p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET)
         preferred = 8;
     else if (p.store == LB_STORE_F16_LOCAL || p.store == LB_STORE_BF16_LOCAL)
