@@ -6,6 +6,10 @@
 //                     psi of Eq. (24) or Eq. (23), force, velocity) and then, by
 //                     MODE, collides and stores (the time step), writes rho/v
 //                     (moments), or accumulates FP64 reductions (diagnostics).
+//   d2q9_pair<walls, psi form>
+//                     the time step of the destination-scaled FP16 storage
+//                     with two columns per lane (even nx), bitwise the same
+//                     as d2q9_strip's
 //   d2q9_batch        persistent multi-instance step (one workgroup per lattice)
 //   d2q9_batch_flat   one step of many lattices in one launch over their strips
 //   d2q9_init         equilibrium initial state, written "pre-streamed" so
@@ -780,7 +784,7 @@ __global__ __launch_bounds__(256) void copy_probe(const float4* __restrict__ src
 // ---------------------------------------------------------------- launchers
 
 // Dynamic LDS that caps the resident workgroups of a strip kernel at `cap` per CU
-// (0: no cap).  The destination-scaled FP16 step runs fastest with five 4-wave
+// (0: no cap).  The one-column destination-scaled FP16 step runs fastest with five 4-wave
 // workgroups per CU (measured on the 8192 x 4096 splash: 107.9k MLUPS, against
 // 102.8k with the six its registers allow and 105.5k with four); the LDS is
 // reserved only to limit occupancy and is never accessed.
