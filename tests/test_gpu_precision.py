@@ -149,6 +149,36 @@ def test_one_step_is_the_oracle_rounded_once(store, case):
     assert excess <= 0.0, (store, case, excess)
 
 
+def test_full_size_sampled_one_step_f16dest():
+    """8192 x 4096 splash in the launch shape bench.py times for f16dest (two columns per
+    lane, default strip height): the sixth step at 40,000 sampled sites, plus samples at
+    tile and strip edges, is the oracle's collision of the decoded, streamed fifth state
+    within one rounding of the encoding plus the FP32 allowance."""
+    store = "f16dest"
+    w = W.splash(scale=4, Re=200)
+    ny, nx = w.params["ny"], w.params["nx"]
+    print(f"[gpu-case] precision full-size sampled store={store} shape=({ny}, {nx})", flush=True)
+    s = make_sim(w, store)
+    s.step(5)
+    e5, r5 = raw_state(s, store)
+    s.step(1)
+    e6, r6 = raw_state(s, store)
+    s.close()
+    p = O.Params(**w.params)
+    f5 = O.stream(p, decode(e5, r5, store, 0.0, walls=True))
+    del e5
+    rng = np.random.default_rng(2025)
+    ys = np.concatenate([rng.integers(0, ny, 40000), [0, 0, ny - 1, ny - 1, 4, 5, 9, 10]])
+    xs = np.concatenate([rng.integers(0, nx, 40000), [0, nx - 1, 0, nx - 1, 123, 124, 247, 248]])
+    ref = O.collide_at(p, f5, ys.astype(np.int64) * nx + xs).T  # [9][samples]
+    sd = dest_scales(r6, True)[:, ys, xs]
+    got = sd * (WEIGHTS[:, None] + e6[:, ys, xs])
+    enc_ref = ref / sd - WEIGHTS[:, None]
+    bound = 0.5 * ulp16(enc_ref, store) * sd + 2e-6 * np.abs(ref).max()
+    excess = float((np.abs(got - ref) - bound).max())
+    assert excess <= 0.0, excess
+
+
 @pytest.mark.parametrize("store", ["f16local", "f16dest"])
 @pytest.mark.parametrize("shape", [(3, 3), (5, 3), (3, 70), (64, 3), (63, 125), (3, 4), (5, 6), (4, 126),
                                    (7, 248)])
