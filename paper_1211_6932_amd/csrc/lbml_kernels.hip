@@ -116,7 +116,17 @@ __global__ void bias_grad(const __bf16* __restrict__ dZ, float* __restrict__ db,
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float acc = 0.0f;
-    for (int m = 0; m < B; ++m) acc += static_cast<float>(dZ[(long long)m * N + n]);
+    int m = 0;
+    // 16 rows loaded ahead, then added in row order: the loads overlap, the sum and
+    // its rounding stay those of the plain sequential loop
+    for (; m + 16 <= B; m += 16) {
+        float v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = static_cast<float>(dZ[(long long)(m + j) * N + n]);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc += v[j];
+    }
+    for (; m < B; ++m) acc += static_cast<float>(dZ[(long long)m * N + n]);
     db[n] = acc;
 }
 
