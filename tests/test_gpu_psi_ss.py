@@ -88,19 +88,21 @@ def test_eq23_flat_interface_follows_maxwell_on_gpu():
     assert r[0, 0] == pytest.approx(orho[0, 0], rel=1e-5)
 
 
-def test_eq23_batch_is_bitwise_equal_to_single_runs():
+@pytest.mark.parametrize("store", ["f32", "f16dest"])
+def test_eq23_batch_is_bitwise_equal_to_single_runs(store):
+    # f16dest single runs of even width use the two-columns-per-lane step
     ws = [case(0.0, f=1.15, n=67, R0=15.0, improved=False), case(1.0, n=100, R0=22.0),
           case(0.5, f=1.3, n=40, R0=9.0)]
-    print("[gpu-case] Eq. (23) batch bitwise, 3 lattices", flush=True)
+    print(f"[gpu-case] Eq. (23) batch bitwise, 3 lattices, store={store}", flush=True)
     for mode in (B.LB_BATCH_STEPWISE, B.LB_BATCH_PERSISTENT):
-        b = B.Batch([w.params for w in ws], [torch.from_numpy(f32(w.rho0)) for w in ws])
+        b = B.Batch([w.params for w in ws], [torch.from_numpy(f32(w.rho0)) for w in ws], store=store)
         b.set_launch(mode)
         b.step(37)
         assert b.check() == (B.LB_OK, 0)
         for i, w in enumerate(ws):
-            p = B.make_params(w.params)
+            p = B.make_params(w.params, store)
             got = b.get_state(i, B.lb_state_bytes(p)).cpu().numpy()
-            s = B.Sim(w.params, torch.from_numpy(f32(w.rho0)))
+            s = B.Sim(w.params, torch.from_numpy(f32(w.rho0)), store=store)
             s.step(37)
             ref = s.get_state().cpu().numpy()
             s.close()
