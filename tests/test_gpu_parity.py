@@ -305,14 +305,17 @@ def test_diagnostics_match_oracle_postprocessing():
 
 # ------------------------------------------------------------------ failure handling
 
-def test_unstable_run_is_flagged_and_poisons():
+@pytest.mark.parametrize("store", ["f32", "f16dest"])
+def test_unstable_run_is_flagged_and_poisons(store):
     """The original forcing (sigma = 0) below T/T_c ~ 0.8 drives the vapour density
-    out of the EOS domain (the oracle fails the same way)."""
+    out of the EOS domain (the oracle fails the same way).  f16dest on this even width
+    runs the two-columns-per-lane step, whose flag counts output sites."""
     w = W.stationary_droplet(n=64, R0=14, t_over_tc=0.6, sigma=0.0)
+    print_case("unstable", store=store, shape=(64, 64))
     o = make_oracle(w)
     with pytest.raises(O.OracleError):
         o.step(400)
-    s = make_sim(w)
+    s = make_sim(w, store=store)
     s.step(400)
     with pytest.raises(B.LbError) as e:
         s.check()
