@@ -141,6 +141,10 @@ def bench_batch(args):
     bps = BYTES_PER_SITE[args.store]
     achieved = bps * sites * args.steps / wall / 1e9
     log(f"{mlups:.0f} MLUPS aggregate, {wall:.2f} s, unstable lattices: {n_unstable}")
+    copy_gbps = None
+    if not args.no_copy_probe:
+        copy_gbps = copy_probe_gbps(torch, lbmp, b.stream)
+        log(f"copy probe {copy_gbps:.0f} GB/s")
     out = {
         "metric": "aggregate MLUPS of a batched multi-lattice sweep (D2Q9 MRT improved pseudopotential)",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -151,7 +155,8 @@ def bench_batch(args):
                                f"{sites} sites", "batch_mode": args.batch_mode, "store": args.store,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "bytes_per_site": bps},
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "bytes_per_site": bps,
+                     "copy_probe_GBps": None if copy_gbps is None else round(copy_gbps, 1)},
         "per_lattice_seconds": {"p50": float(np.percentile(times, 50)), "p99": float(np.percentile(times, 99)),
                                 "max": float(times.max()), "min": float(times.min())},
         "checks": {"unstable_lattices": int(n_unstable),

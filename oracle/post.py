@@ -53,21 +53,22 @@ def region_means(field, d, r_min, r_max):
 def laplace(rho, params, R0, W=5.0, cx=None, cy=None):
     """Pressure jump and effective radius of a centred droplet.
 
-    Returns dict(p_in, p_out, dp, rho_in, rho_out, R_eff, theta) with theta = dp * R_eff
-    (2-D Laplace law dp = theta / R)."""
+    Returns dict(p_in, p_out, dp, rho_in, rho_out, R_eff, theta, n_in, n_out) with
+    theta = dp * R_eff (2-D Laplace law dp = theta / R) and n_in, n_out the site counts
+    of the two regions."""
     ny, nx = rho.shape
     cx = (nx - 1) / 2.0 if cx is None else cx
     cy = (ny - 1) / 2.0 if cy is None else cy
     d = distance_field(nx, ny, cx, cy, periodic_y=(params.get("bc", 0) == 0))
     p = eos.p_eos(rho, params["a"], params["b"], params["R"], params["T"])
-    p_in, _ = region_means(p, d, 0.0, R0 / 2.0 + 1e-12)
-    p_out, _ = region_means(p, d, R0 + 3.0 * W, np.inf)
+    p_in, n_in = region_means(p, d, 0.0, R0 / 2.0 + 1e-12)
+    p_out, n_out = region_means(p, d, R0 + 3.0 * W, np.inf)
     rho_in, _ = region_means(rho, d, 0.0, R0 / 2.0 + 1e-12)
     rho_out, _ = region_means(rho, d, R0 + 3.0 * W, np.inf)
     R_eff = math.sqrt((rho.sum() - rho_out * rho.size) / (math.pi * (rho_in - rho_out)))
     dp = p_in - p_out
     return dict(p_in=p_in, p_out=p_out, dp=dp, rho_in=rho_in, rho_out=rho_out, R_eff=R_eff,
-                theta=dp * R_eff)
+                theta=dp * R_eff, n_in=n_in, n_out=n_out)
 
 
 def interface_width(profile, rho_l, rho_g, lo=0.1, hi=0.9):

@@ -6,6 +6,7 @@ Readings used here (also listed in the design notes):
     far in the vapour of a flat-interface run (periodic 4 x 200 box, slab 100 thick);
   * interface thickness = W of the best fit of the Eq. (31) tanh profile;
   * Laplace pressure jump from post.laplace (p = p_EOS, inner / outer regions)."""
+import functools
 import math
 
 import numpy as np
@@ -127,6 +128,29 @@ def test_moment_form_equals_velocity_form_on_tiny_grids(shape, bc):
     assert np.abs(a.f - b.f).max() <= 1e-13
 
 
+@pytest.mark.parametrize("bc", [0, 1])
+def test_collide_at_then_stream_equals_the_full_step(bc):
+    """lbref_collide_at (the one-step reference of the GPU parity tests) evaluates
+    psi, the Eq. (7) force, the Eq. (6) velocity and the Eq. (4) collision from each
+    site's own 3 x 3 neighbourhood, with its own wall clamp.  Collided at every site and
+    streamed (Eq. 5), it must reproduce lbref_step exactly, wall rows 0 and ny-1
+    included.  A perturbed droplet with random velocities exercises every term."""
+    nx, ny = 23, 17
+    rl, rg = W.coexistence(0.6)
+    p = W.base_params(nx, ny, bc=bc)
+    rng = np.random.default_rng(3 + bc)
+    rho0 = W.droplet_field(nx, ny, 6.0, rl, rg, periodic_y=(bc == 0)) * (1 + 0.02 * rng.random((ny, nx)))
+    ux0, uy0 = 0.02 * rng.standard_normal((2, ny, nx))
+    P = O.Params(**p)
+    s = O.State(P, rho0, ux0, uy0).step(7)
+    fstar = O.collide_at(P, s.f, np.arange(nx * ny)).T.reshape(9, ny, nx)
+    streamed = O.stream(P, fstar)
+    s.step(1)
+    assert np.abs(streamed - s.f).max() <= 1e-15
+    # the wall rows are where collide_at's clamp and the streaming's reflection act
+    assert np.abs(s.f[:, [0, ny - 1], :]).min() > 0.0
+
+
 # ------------------------------------------------------------------ transport: rates and walls
 
 @pytest.mark.parametrize("rho,nu", [(0.4, 0.1), (0.01, 0.3)])
@@ -213,20 +237,49 @@ def test_improved_forcing_restores_maxwell_vapour_branch():
     assert rl1 == pytest.approx(ml, rel=1e-3)
 
 
-def test_table2_row_at_reduced_temperature_0_6(golden):
-    """Table II, a = 0.5, sigma = 0.11, tau_nu = 0.8, T/Tc = 0.6.  The liquid density is
-    reproduced to 0.3 %; the vapour density of this implementation sits 15 % below
-    the printed 0.00298 (the vapour branch is very sensitive to sigma: ~10 % per 0.01),
-    which is recorded here as a bound rather than a match."""
+@functools.lru_cache(maxsize=None)
+def droplet_coexistence(tb, R0, steps, n=None):
+    """Inner and outer mean densities of a stationary droplet (Sec. IV.A geometry:
+    periodic n x n box, n = 4 R0 by default, tanh start, tau_nu = 0.8, a = 0.5)."""
+    w = W.coexistence_droplets([tb], tau_nu=0.8, n=int(n or 4 * R0), R0=float(R0))[0]
+    s = state(w.params, w.rho0).step(steps)
+    lp = post.laplace(s.moments()[0], w.params, float(R0))
+    return lp["rho_in"], lp["rho_out"]
+
+
+@pytest.mark.slow
+def test_table2_row_at_reduced_temperature_0_6_in_the_droplet_geometry(golden):
+    """Table II, a = 0.5, sigma = 0.11, tau_nu = 0.8, T/Tc = 0.6, measured as the paper
+    measures it (Sec. IV.A-B): a droplet of radius 50 in a 200 x 200 periodic box.  The
+    inner and outer densities after 12,000 steps reproduce the printed 0.4077 / 0.00298
+    (to 0.02 % and 0.1 %; they are converged to 1e-4 by then)."""
     row = golden["table2"]["rows"][0]
-    rl, rg, _ = flat_interface(0.5, 0.6, 0.11)
-    assert rl == pytest.approx(row[1], rel=3e-3)
-    assert 0.80 * row[2] <= rg <= 1.05 * row[2]
+    rl, rg = droplet_coexistence(0.6, 50, 12000)
+    assert rl == pytest.approx(row[1], rel=2e-3)
+    assert rg == pytest.approx(row[2], rel=3e-2)
+
+
+@pytest.mark.slow
+def test_vapour_density_shifts_with_curvature():
+    """Why a flat interface does not reproduce Table II's vapour density: the outer
+    density of a droplet sits above the flat-interface value by an amount proportional
+    to the curvature 1/R (the Laplace pressure of the droplet, Sec. IV.B).  With the
+    flat slab as the R -> infinity limit, halving the radius doubles the shift, and the
+    flat value itself lies clearly below the droplet's (by about 15 % at R = 50)."""
+    rl_f, rg_f, _ = flat_interface(0.5, 0.6, 0.11)
+    _, rg25 = droplet_coexistence(0.6, 25, 12000)
+    _, rg50 = droplet_coexistence(0.6, 50, 12000)
+    assert (rg25 - rg_f) / (rg50 - rg_f) == pytest.approx(2.0, rel=0.1)
+    assert rg50 / rg_f - 1.0 > 0.1
 
 
 def test_interface_width_scales_as_inverse_sqrt_a(golden):
     """Sec. IV.B / Fig. 3: widths for a = 0.25 and 0.5 are about 1.9 and 1.4 times the
-    a = 1.0 width (tanh-fit width of a flat interface, T/Tc = 0.7 and 0.6)."""
+    a = 1.0 width, flat interfaces at T/Tc = 0.7 and 0.6, with the width taken as the W
+    of the best Eq. (31) tanh fit.  The 10-90 % width (post.interface_width) of the same
+    interfaces lies 0-12 % above W ln 3 (its value for an exact tanh): linear
+    interpolation across an interface only ~3 sites wide (a = 1) and the longer
+    vapour-side tail inflate it, so its ratios come out lower and are only reported."""
     g = golden["interface_width_ratio"]
 
     def width(a, tb):
@@ -238,27 +291,105 @@ def test_interface_width_scales_as_inverse_sqrt_a(golden):
         r = s.moments()[0][: ny // 2, 0]
         f = lambda y, yc, Wd, l, gg: 0.5 * (l + gg) + 0.5 * (l - gg) * np.tanh(2 * (y - yc) / Wd)
         popt, _ = curve_fit(f, np.arange(ny // 2, dtype=float), r, p0=[ny / 4, 4, r.max(), r.min()])
-        return abs(popt[1])
+        # scanned from the liquid side
+        return abs(popt[1]), post.interface_width(r[::-1], r.max(), r.min())
 
     for tb in (0.7, 0.6):
         w1, w05, w025 = width(1.0, tb), width(0.5, tb), width(0.25, tb)
-        assert w05 / w1 == pytest.approx(g["a0.5_over_a1"], rel=0.1)
-        assert w025 / w1 == pytest.approx(g["a0.25_over_a1"], rel=0.1)
+        assert w05[0] / w1[0] == pytest.approx(g["a0.5_over_a1"], rel=0.1)
+        assert w025[0] / w1[0] == pytest.approx(g["a0.25_over_a1"], rel=0.1)
+        print(f"T/Tc={tb}: 10-90 width ratios {w05[1] / w1[1]:.3f} {w025[1] / w1[1]:.3f}")
+        for w in (w1, w05, w025):
+            assert 1.0 <= w[1] / (w[0] * math.log(3.0)) <= 1.12
 
 
+@pytest.mark.slow
 def test_laplace_law():
-    """Pressure jump of equilibrated droplets against 1/R (2-D Laplace law,
-    used by the paper in Sec. IV.B and IV.C to evaluate the surface tension)."""
+    """Pressure jump of equilibrated droplets against 1/R (2-D Laplace law, which the
+    paper uses in Sec. IV.B and IV.C to evaluate the surface tension): 128 x 128
+    periodic, R0 = 15 ... 35, T/Tc = 0.6, a = 0.5, 16,000 steps (the fit's intercept
+    moves by 0.1 % of max Delta p between 16,000 and 40,000 steps).  The straight line in 1/R_eff
+    has R^2 >= 0.9995; its intercept (3 % of the largest Delta p) is the second-order
+    term of a finite-width interface, Delta p = theta/R (1 - 2 delta/R): fitting
+    c + s/R + q/R^2 leaves no constant pressure offset (|c| <= 1 % of max Delta p)."""
     xs, ys = [], []
-    for R0 in (8, 10, 12, 14, 16):
-        w = W.stationary_droplet(n=64, R0=R0)
-        s = state(w.params, w.rho0).step(2500)
+    for R0 in (15, 20, 25, 30, 35):
+        w = W.stationary_droplet(n=128, R0=R0)
+        s = state(w.params, w.rho0).step(16000)
         lp = post.laplace(s.moments()[0], w.params, R0)
         xs.append(1 / lp["R_eff"])
         ys.append(lp["dp"])
     slope, icpt, r2 = post.linear_fit(xs, ys)
-    assert slope > 0 and r2 >= 0.999
-    assert abs(icpt) <= 0.1 * max(ys)
+    assert slope > 0 and r2 >= 0.9995
+    x, y = np.array(xs), np.array(ys)
+    A = np.vstack([np.ones_like(x), x, x * x]).T
+    (c, s1, q), *_ = np.linalg.lstsq(A, y, rcond=None)
+    assert s1 > 0 and q < 0
+    assert abs(c) <= 0.01 * y.max()
+    assert np.abs(A @ np.array([c, s1, q]) - y).max() <= 1e-3 * y.max()
+
+
+def _disc_count(n_x, n_y, cx2, cy2, r2x4, periodic_y, strict):
+    """Number of lattice sites (i, j) with |2 (i, j) - (cx2, cy2)|^2 < r2x4 (or <=), all in
+    integers: cx2 = 2 cx, cy2 = 2 cy and r2x4 = 4 r^2; minimum image in x (and y)."""
+    count = 0
+    for j in range(n_y):
+        dy = abs(2 * j - cy2)
+        if periodic_y:
+            dy = min(dy, 2 * n_y - dy)
+        for i in range(n_x):
+            dx = abs(2 * i - cx2)
+            dx = min(dx, 2 * n_x - dx)
+            q = dx * dx + dy * dy
+            count += (q < r2x4) if strict else (q <= r2x4)
+    return count
+
+
+@pytest.mark.parametrize("bc,cx,cy", [(0, 63.5, 63.5), (0, 10.5, 120.0), (1, 70.0, 47.5)])
+def test_laplace_post_processing_on_a_stepped_disc(bc, cx, cy):
+    """post.laplace on a field whose answers are known exactly: density rho_a on a disc of
+    radius 20, rho_b on the annulus 20 <= d < 33 and rho_c beyond.  Then p_in and p_out
+    are p_EOS(rho_a) and p_EOS(rho_c) (evaluated by the C oracle, Eq. 30), the region
+    sizes are integer lattice-point counts (d <= R0/2 = 15 and d >= R0 + 3W = 45 for
+    R0 = 30, W = 5), and R_eff^2 pi (rho_a - rho_c) is the excess mass N_a (rho_a - rho_c)
+    + N_ab (rho_b - rho_c).  The two off-centre cases wrap around the periodic edges (and
+    the walls case does not wrap in y)."""
+    nx, ny = 128, 96
+    p = W.base_params(nx, ny, bc=bc)
+    ra, rb, rc = 0.41, 0.2, 0.003
+    d = post.distance_field(nx, ny, cx, cy, periodic_y=(bc == 0))
+    rho = np.where(d < 20.0, ra, np.where(d < 33.0, rb, rc))
+    got = post.laplace(rho, p, 30.0, cx=cx, cy=cy)
+    cx2, cy2 = int(round(2 * cx)), int(round(2 * cy))
+    per = bc == 0
+    n_in = _disc_count(nx, ny, cx2, cy2, 4 * 15 ** 2, per, strict=False)
+    n_out = nx * ny - _disc_count(nx, ny, cx2, cy2, 4 * 45 ** 2, per, strict=True)
+    n_a = _disc_count(nx, ny, cx2, cy2, 4 * 20 ** 2, per, strict=True)
+    n_ab = _disc_count(nx, ny, cx2, cy2, 4 * 33 ** 2, per, strict=True) - n_a
+    P = O.Params(**p)
+    assert got["n_in"] == n_in and got["n_out"] == n_out
+    assert got["p_in"] == pytest.approx(O.p_eos(P, ra), rel=1e-14)
+    assert got["p_out"] == pytest.approx(O.p_eos(P, rc), rel=1e-14)
+    assert got["rho_in"] == pytest.approx(ra, rel=1e-14) and got["rho_out"] == pytest.approx(rc, rel=1e-14)
+    r_eff = math.sqrt((n_a * (ra - rc) + n_ab * (rb - rc)) / (math.pi * (ra - rc)))
+    assert got["R_eff"] == pytest.approx(r_eff, rel=1e-12)
+    # the mass-based radius of the plain disc is close to its geometric radius (Gauss circle)
+    assert math.sqrt(n_a / math.pi) == pytest.approx(20.0, abs=0.1)
+    assert got["dp"] == pytest.approx(O.p_eos(P, ra) - O.p_eos(P, rc), rel=1e-13)
+
+
+@pytest.mark.parametrize("width", [5.0, 12.0])
+def test_ten_ninety_width_of_a_tanh_profile(width):
+    """post.interface_width on the Eq. (31) profile: its 10 % and 90 % points lie at
+    d = -+ (W/2) artanh(0.8), so the 10-90 width is W artanh(0.8) = W ln 3 (up to the
+    linear interpolation between lattice samples)."""
+    rl, rg = 0.4, 0.003
+    d = np.arange(-60.0, 60.0)
+    prof = W.tanh_profile(d + 0.37, rl, rg, W=width)
+    got = post.interface_width(prof, rl, rg)
+    # linear interpolation over unit spacing moves a crossing by at most |phi''/phi'| / 8,
+    # which is 3.2 / W where tanh = +-0.8; the two crossings' errors can add
+    assert abs(got - width * math.log(3.0)) <= 0.8 / width
 
 
 # ------------------------------------------------------------------ Eq. (23) pseudopotential
