@@ -11,15 +11,18 @@ force, MRT collision with the improved forcing, store).  The metric is MLUPS
 (million lattice-site updates per second) with the distributions resident in HBM.
 
     python bench.py [--steps K] [--warmup W] [--store f32|f16|bf16|f16local|bf16local|f16dest] [--no-cpu-baseline]
-    python bench.py --workload batch [--instances 512] [--steps 10000]
+    python bench.py --workload batch [--instances 512] [--steps 10000] [--store f32|f16dest|f16local]
     python bench.py --workload learned [--train-runs 4096] [--eval-droplets 256] [--relax-steps 30000]
+    python bench.py --workload splash1k  (2048x1024 splash, Re 40/200/1000, 20,000 steps: stability, mass)
     python bench.py --workload lamb      (droplet oscillation against Lamb, Sec. IV.A)
     python bench.py --workload sweeps    (coexistence curves, stability edges, Table I, Fig. 4)
     python bench.py --workload spread    (splash spread radius and Weber number, Sec. IV.C)
 
 The batch workload advances 512 independent droplet lattices (seed 1211: sides 64-512,
-a in {0.25, 0.5, 1}, T/Tc in [0.5, 0.85], half of them elliptic) in one persistent launch
-and reports aggregate MLUPS and the p50 / p99 per-lattice completion times.
+a in {0.25, 0.5, 1}, T/Tc in [0.5, 0.85], half of them elliptic): strip heights are
+autotuned on the device, then 10,000 steps in captured stepwise launches give the
+aggregate MLUPS, and 10,000 more in the persistent launch (one workgroup per lattice)
+give the p50 / p99 per-lattice completion times.
 
 The learned workload runs the droplet-initialiser protocol: 4096 tanh-started
 droplets on 256 x 256 lattices (seed 1212) relax for 30,000 steps; the network
@@ -124,27 +127,53 @@ def bench_batch(args):
     log(f"batch of {len(ws)} lattices, {sites} sites: init")
     b = lbmp.Batch([w.params for w in ws], [torch.from_numpy(np.asarray(w.rho0, np.float32)) for w in ws],
                    store=args.store)
-    b.set_launch(lbmp.LB_BATCH_PERSISTENT if args.batch_mode == "persistent" else lbmp.LB_BATCH_STEPWISE)
+    b.set_launch(lbmp.LB_BATCH_STEPWISE)
+    t0 = time.perf_counter()
+    rows = b.tune(trial_steps=8) if not args.no_tune else None
+    t_tune = time.perf_counter() - t0
+    if rows is not None:
+        log(f"tuned strip heights in {t_tune:.2f} s: " +
+            ", ".join(f"{r} rows x {rows.count(r)}" for r in sorted(set(rows))))
     b.step(args.warmup)
     b.stream.synchronize()
-    log(f"timed {args.steps} steps ({args.batch_mode})")
+    log(f"timed {args.steps} steps (stepwise)")
     torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record(b.stream)
     b.step(args.steps)
+    ev1.record(b.stream)
     b.stream.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    times = np.array(b.times())
-    unstable = [b.diagnostics(i, 0.0, 0.0, 1.0, 2.0, raise_unstable=False)["unstable"] for i in range(len(ws))]
-    n_unstable = sum(1 for u in unstable if u)
+    step_ms = ev0.elapsed_time(ev1) / args.steps
     mlups = sites * args.steps / wall / 1e6
     bps = BYTES_PER_SITE[args.store]
-    achieved = bps * sites * args.steps / wall / 1e9
-    log(f"{mlups:.0f} MLUPS aggregate, {wall:.2f} s, unstable lattices: {n_unstable}")
+    achieved = bps * sites / (step_ms * 1e-3) / 1e9
+    log(f"{mlups:.0f} MLUPS aggregate, {wall:.2f} s, {step_ms:.4f} ms per step (events)")
     copy_gbps = None
     if not args.no_copy_probe:
         copy_gbps = copy_probe_gbps(torch, lbmp, b.stream)
         log(f"copy probe {copy_gbps:.0f} GB/s")
+    per_lattice = None
+    if not args.no_persistent:
+        # per-lattice completion times: the persistent launch gives each lattice its own
+        # workgroup for all steps (the stepwise launches finish every lattice together)
+        b.set_launch(lbmp.LB_BATCH_PERSISTENT)
+        log(f"timed {args.steps} steps (persistent, per-lattice completion times)")
+        t0 = time.perf_counter()
+        b.step(args.steps)
+        b.stream.synchronize()
+        pwall = time.perf_counter() - t0
+        times = np.array(b.times())
+        per_lattice = {"mode": "persistent", "steps": args.steps, "aggregate_MLUPS": round(sites * args.steps / pwall / 1e6, 1),
+                       "p50_s": round(float(np.percentile(times, 50)), 4),
+                       "p99_s": round(float(np.percentile(times, 99)), 4),
+                       "min_s": round(float(times.min()), 4), "max_s": round(float(times.max()), 4)}
+        log(f"persistent: {per_lattice['aggregate_MLUPS']:.0f} MLUPS, p50 {per_lattice['p50_s']:.2f} s, "
+            f"p99 {per_lattice['p99_s']:.2f} s")
+    unstable = [b.diagnostics(i, 0.0, 0.0, 1.0, 2.0, raise_unstable=False)["unstable"] for i in range(len(ws))]
+    n_unstable = sum(1 for u in unstable if u)
     out = {
         "metric": "aggregate MLUPS of a batched multi-lattice sweep (D2Q9 MRT improved pseudopotential)",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -152,18 +181,96 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f32" if args.store == "f32" else f"{args.store} storage, f32 compute",
         "data": "synthetic",
         "config": {"workload": f"{len(ws)} periodic droplet lattices (seed 1211), sides 64-512, "
-                               f"{sites} sites", "batch_mode": args.batch_mode, "store": args.store,
+                               f"{sites} sites", "batch_mode": "stepwise", "store": args.store,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "bytes_per_site": bps,
+                     "step_ms_events": round(step_ms, 5),
                      "copy_probe_GBps": None if copy_gbps is None else round(copy_gbps, 1)},
-        "per_lattice_seconds": {"p50": float(np.percentile(times, 50)), "p99": float(np.percentile(times, 99)),
-                                "max": float(times.max()), "min": float(times.min())},
+        "per_lattice_stepwise": {"p50_s": round(wall, 4), "p99_s": round(wall, 4),
+                                 "note": "every lattice completes with the last launch"},
+        "per_lattice_persistent": per_lattice,
+        "tuning": None if rows is None else {"seconds": round(t_tune, 3),
+                                             "rows_histogram": {str(r): rows.count(r) for r in sorted(set(rows))}},
         "checks": {"unstable_lattices": int(n_unstable),
                    "unstable": [dict(i=i, side=ws[i].params["nx"], a=ws[i].params["a"],
                                      t_over_tc=round(ws[i].info["t_over_tc"], 3), R0=round(ws[i].info["R0"], 1))
                                 for i in range(len(ws)) if unstable[i]]},
         "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_splash1k(args):
+    """The splash case at its own size and length: 2048 x 1024, walls in y, x periodic,
+    a = 0.25, T = 0.45 T_c (liquid/vapour density ratio about 2400), R = 100, film 20,
+    U = 0.05, nu_g = 15 nu_l, Re = U D / nu_l in {40, 200, 1000}, 20,000 steps (Ut/D = 5).
+    Records, per Re, whether the run stays stable (the first step that flags an unstable
+    site otherwise, to the checking interval), the FP64 mass drift, max|u| and the
+    spread of the droplet over the film."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1211_6932_amd import lbmp
+
+    torch.cuda.set_device(0)
+    lbmp.load()
+    steps = args.steps
+    every = 10
+    runs = {}
+    t_all = time.perf_counter()
+    for Re in (40, 200, 1000):
+        w = W.splash(scale=1, Re=Re)
+        nx, ny = w.params["nx"], w.params["ny"]
+        sim = lbmp.Sim(w.params, torch.from_numpy(np.asarray(w.rho0, np.float32)),
+                       torch.from_numpy(np.asarray(w.ux0, np.float32)),
+                       torch.from_numpy(np.asarray(w.uy0, np.float32)))
+        c = (nx / 2.0, w.info["film"] + w.info["R"] + 5.0)
+        d0 = sim.diagnostics(c[0], c[1], 1.0, 2.0)
+        first_bad, umax, drift_max = None, d0["max_u"], 0.0
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            n = min(every, steps - done)
+            sim.step(n)
+            done += n
+            if lbmp.lb_check(sim.ctx) != lbmp.LB_OK:
+                first_bad = done
+                break
+            if done % 1000 == 0:
+                d = sim.diagnostics(c[0], c[1], 1.0, 2.0)
+                umax = max(umax, d["max_u"])
+                drift_max = max(drift_max, abs(d["mass"] / d0["mass"] - 1.0))
+        wall = time.perf_counter() - t0
+        res = {"nu_l": w.params["nu_l"], "nu_g": w.params["nu_g"], "stable": first_bad is None,
+               "first_unstable_step": first_bad, "steps_run": done, "wall_s": round(wall, 2),
+               "MLUPS_with_checks": round(nx * ny * done / wall / 1e6, 1)}
+        if first_bad is None:
+            d1 = sim.diagnostics(c[0], c[1], 1.0, 2.0)
+            rho = sim.moments()[0].cpu().numpy()
+            film = w.info["film"]
+            # liquid half-width on the row just above the undisturbed film surface
+            row = rho[int(film) + 1]
+            liquid = np.nonzero(row > 0.5 * (w.info["rho_l"] + w.info["rho_g"]))[0]
+            res.update(mass_rel_drift_final=(d1["mass"] - d0["mass"]) / d0["mass"],
+                       mass_rel_drift_max=max(drift_max, abs(d1["mass"] / d0["mass"] - 1.0)),
+                       max_u_final=d1["max_u"], max_u_seen=max(umax, d1["max_u"]),
+                       liquid_width_above_film=int(liquid.size), rho_min=float(rho.min()), rho_max=float(rho.max()))
+        runs[str(Re)] = res
+        log(f"Re={Re}: " + json.dumps(res))
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out = {
+        "metric": "stability and mass conservation of the 2048x1024 splash over 20,000 steps, Re = 40, 200, 1000",
+        "value": sum(1 for r in runs.values() if r["stable"]), "unit": "stable runs of 3", "n_gpus": 1,
+        "steps": steps, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "droplet splash on a thin film, 2048x1024, walls in y, x periodic, a=0.25, "
+                               "T=0.45Tc, sigma=0.114, s_e=s_zeta=0.8, U=0.05, R=100, film 20, nu_g=15 nu_l",
+                   "parallelism": "single GPU"},
+        "runs": runs, "wall_seconds": round(time.perf_counter() - t_all, 2), "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
@@ -356,15 +463,17 @@ def bench_lamb(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="splash", choices=["splash", "batch", "learned", "lamb", "sweeps", "spread"])
+    ap.add_argument("--workload", default="splash",
+                    choices=["splash", "splash1k", "precision", "batch", "learned", "lamb", "sweeps", "spread"])
     ap.add_argument("--train-runs", type=int, default=4096)
     ap.add_argument("--eval-droplets", type=int, default=256)
     ap.add_argument("--relax-steps", type=int, default=30000)
     ap.add_argument("--train-steps", type=int, default=20000)
     ap.add_argument("--instances", type=int, default=512)
-    ap.add_argument("--batch-mode", default="stepwise", choices=["stepwise", "persistent"])
+    ap.add_argument("--no-tune", action="store_true", help="batch: keep the measured strip-height table")
+    ap.add_argument("--no-persistent", action="store_true", help="batch: skip the per-lattice timing run")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=None, help="default 2000 (splash), 10000 (batch)")
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--store", default="f32", choices=sorted(BYTES_PER_SITE))
     ap.add_argument("--scale", type=int, default=4, help="splash geometry scale (4 -> 8192x4096)")
@@ -373,6 +482,8 @@ def main():
     ap.add_argument("--no-copy-probe", action="store_true")
     args = ap.parse_args()
 
+    if args.steps is None:
+        args.steps = {"batch": 10000, "splash1k": 20000}.get(args.workload, 2000)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -381,6 +492,8 @@ def main():
         return bench_batch(args)
     if args.workload == "learned":
         return bench_learned(args)
+    if args.workload == "splash1k":
+        return bench_splash1k(args)
     if args.workload == "lamb":
         return bench_lamb(args)
     if args.workload == "sweeps":

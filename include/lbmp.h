@@ -252,13 +252,30 @@ lb_status lb_batch_times(lb_batch* b, double* seconds);
 /* Launch mode of lb_batch_step:
  *   LB_BATCH_STEPWISE   (default) one launch per time step over the tiles of all
  *                       lattices together (captured in graphs); best throughput;
- *                       lb_batch_times reports the same elapsed time for all;
+ *                       lb_batch_times reports the same elapsed time for all.
+ *                       Destination-scaled FP16 lattices with an even nx are
+ *                       stepped two columns per lane in a second launch.
  *   LB_BATCH_PERSISTENT one launch per lb_batch_step call, one workgroup per
  *                       lattice for all steps; per-lattice completion times.
- * strip_rows: rows per wavefront strip (0 = the mode's default).  Synchronises
- * the stream.  Results do not depend on either (bitwise). */
+ * strip_rows: rows per wavefront strip for every lattice, in [1, 64]; 0 = the
+ * mode's default (stepwise: a measured height per kernel group, or the heights
+ * chosen by lb_batch_tune).  Synchronises the stream.  Results do not depend on
+ * either (bitwise). */
 enum { LB_BATCH_STEPWISE = 0, LB_BATCH_PERSISTENT = 1 };
 lb_status lb_batch_set_launch(lb_batch* b, int32_t mode, int32_t strip_rows);
+
+/* Autotune the strip heights of the stepwise mode on the device at hand.  For each
+ * kernel group (one column per lane; two columns per lane, the destination-scaled
+ * FP16 lattices with an even nx), the larger first, every height from 1 to 8 is
+ * timed over trial_steps launches of the whole batch (1 <= trial_steps <= 1000; the
+ * least of three repetitions) and the fastest is kept for the group.  The trial
+ * launches read the current state and write only the buffer that the next step
+ * overwrites in full, so the state and the time are unchanged; a lattice that is
+ * already unstable may set its unstable flag, as its next step would.  Clears a
+ * fixed strip height set by lb_batch_set_launch.  rows_out (host array of n, may be
+ * NULL) receives each lattice's height.  Stepwise mode only; needs a stream other
+ * than the legacy one; synchronises it. */
+lb_status lb_batch_tune(lb_batch* b, int32_t trial_steps, int32_t* rows_out);
 
 /* Release the batch and its contexts (not the caller's workspace). */
 lb_status lb_batch_destroy(lb_batch* b);

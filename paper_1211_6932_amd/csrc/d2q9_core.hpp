@@ -3,10 +3,12 @@
 //
 // Layout in HBM: the stored state is the post-collision distribution f*
 // (pull streaming), row-interleaved structure of arrays f[y][alpha][pitch]: the
-// nine population rows of one lattice row are contiguous, x fastest, row pitch
-// a multiple of 64 elements.  A row's pull then reads three contiguous blocks
-// (rows y-1, y, y+1) and its store writes one, instead of touching 18 separate
-// planes.  Two such buffers ping-pong.
+// nine population rows of one lattice row are contiguous, x fastest, and the
+// rows are packed without padding (pitch = nx, rounded to even for the
+// local-density encodings), so the whole state is one contiguous stream.  A
+// row's pull then reads three contiguous blocks (rows y-1, y, y+1) and its store
+// writes one, instead of touching 18 separate planes.  Two such buffers
+// ping-pong.
 //
 // Work decomposition: one 64-lane wavefront owns a strip of 62 output columns
 // and `strip_rows` rows.  Lane l handles column x0 - 1 + l; lanes 0 and 63 are
@@ -25,29 +27,19 @@ namespace lbmp {
 constexpr int kWave = 64;
 constexpr int kTileW = kWave - 2;     // output columns per wavefront strip
 constexpr int kPairTileW = 2 * kWave - 4;  // output columns per wavefront, two columns per lane
-#ifndef LBMP_PAIR_WAVES
-#define LBMP_PAIR_WAVES 4
-#endif
-constexpr int kPairWaves = LBMP_PAIR_WAVES;  // wavefronts per workgroup, two columns per lane
-#ifndef LBMP_WAVES_PER_BLOCK
-#define LBMP_WAVES_PER_BLOCK 16
-#endif
-#ifndef LBMP_XCD_REMAP
-#define LBMP_XCD_REMAP 1
-#endif
-constexpr int kWavesPerBlock = LBMP_WAVES_PER_BLOCK;  // wavefronts (strips) per workgroup
-#ifndef LBMP_BATCH_WAVES
-#define LBMP_BATCH_WAVES 16
-#endif
-constexpr int kBatchWaves = LBMP_BATCH_WAVES;  // wavefronts per workgroup (= per lattice) of a batch
+constexpr int kPairWaves = 4;         // wavefronts per workgroup, two columns per lane
+constexpr int kWavesPerBlock = 16;    // wavefronts (strips) per workgroup: FP32 step, FP32 batch
+constexpr int kBatchWaves = 16;       // wavefronts per workgroup (= per lattice) of the persistent batch
+// Wavefronts per workgroup of the flat batch with destination-scaled FP16, one column
+// per lane (FP32 and source-density FP16 use kWavesPerBlock).  On the 512-lattice
+// sweep: 100.7k MLUPS with 4 against 98.7k with 16 (source-density FP16: 78.9k with 4,
+// 80.1k with 16).
+constexpr int kBatchWavesDest = 4;
 constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kDiagFields = 10;       // doubles per wave partial in the diagnostics pass
 
 enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2, kStoreF16Local = 3, kStoreBF16Local = 4, kStoreF16Dest = 5 };
 
-#ifndef LBMP_WAVES_PER_BLOCK_DEST
-#define LBMP_WAVES_PER_BLOCK_DEST 4
-#endif
 // Wavefronts per workgroup of the single-lattice strip kernels, by storage.  The
 // FP32 step is bound by HBM and streams best with one 16-wave workgroup per CU
 // (the resident waves then cover the fewest rows); the destination-scaled FP16
@@ -55,7 +47,7 @@ enum : int { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2, kStoreF16Local = 3, k
 // per CU (measured on the 8192 x 4096 splash: 106k vs 98k MLUPS with 4 waves).
 constexpr int step_waves_per_block(int store)
 {
-    return store == kStoreF16Dest ? LBMP_WAVES_PER_BLOCK_DEST : kWavesPerBlock;
+    return store == kStoreF16Dest ? 4 : kWavesPerBlock;
 }
 enum : int { kModeStep = 0, kModeMoments = 1, kModeDiag = 2 };
 enum : int { kFlagUnstable = 1, kFlagBadInput = 2 };
@@ -117,7 +109,7 @@ struct DiagConst {
 
 // ---------------------------------------------------------------- storage codecs
 // Element access by 32-bit byte offset from a (wave-uniform) row pointer (the
-// initial-state kernel).  Valid because a padded row is limited to < 4 GiB
+// initial-state kernel).  Valid because a lattice row is limited to < 4 GiB
 // (host validation).
 template <class T>
 __device__ __forceinline__ T& at(T* p, unsigned byte_off)
@@ -399,36 +391,18 @@ __device__ __forceinline__ double pressure_f64(double rho, const PsiConst& c)
     return p_eos_f64(rho, c.b4, c.RT, c.a);
 }
 
-#ifndef LBMP_APPROX_DIV
-#define LBMP_APPROX_DIV 0
-#endif
-#ifndef LBMP_NEWTON_DIV
-#define LBMP_NEWTON_DIV 1
-#endif
+// Hardware reciprocal refined by one Newton step.
 __device__ __forceinline__ float recip(float x)
 {
-#if LBMP_APPROX_DIV
-    return __builtin_amdgcn_rcpf(x);
-#elif LBMP_NEWTON_DIV
-    // hardware reciprocal refined by one Newton step
     const float r = __builtin_amdgcn_rcpf(x);
     return fmaf(r, fmaf(-x, r, 1.0f), r);
-#else
-    return 1.0f / x;
-#endif
 }
+// x * rsq(x) refined by one Newton step on the square root.
 __device__ __forceinline__ float root(float x)
 {
-#if LBMP_APPROX_DIV
-    return __builtin_amdgcn_sqrtf(x);
-#elif LBMP_NEWTON_DIV
-    // x * rsq(x) refined by one Newton step on the square root
     const float y = __builtin_amdgcn_rsqf(x);
     const float s = x * y;
     return fmaf(fmaf(-s, s, x), 0.5f * y, s);
-#else
-    return sqrtf(x);
-#endif
 }
 
 // Eq. (30) Carnahan-Starling pressure.
@@ -546,14 +520,9 @@ __device__ __forceinline__ void collide(float f[9], float rho, float vx, float v
 // is a permutation of block ids, so results do not depend on it.
 __device__ __forceinline__ int logical_block(int b, int nb)
 {
-#if LBMP_XCD_REMAP
     const int per = nb / kNumXcd, rem = nb % kNumXcd;
     const int xcd = b % kNumXcd, idx = b / kNumXcd;
     return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + idx;
-#else
-    (void)nb;
-    return b;
-#endif
 }
 
 __device__ __forceinline__ float lane_from_left(float v) { return __shfl_up(v, 1, kWave); }

@@ -21,9 +21,6 @@
 
 namespace lbmp {
 
-#ifndef LBMP_STEP_WAVES_PER_EU
-#define LBMP_STEP_WAVES_PER_EU 1
-#endif
 
 // Wave priorities (s_setprio) while a wavefront issues loads: the prologue of a
 // strip (its first rows) above the prefetch of the next row inside the walk,
@@ -36,11 +33,6 @@ namespace lbmp {
 constexpr short kPrioPrologue = 2;
 constexpr short kPrioPrefetch = 1;
 
-// Strips of alternate direction (see strip_tile): 0 never, 1 for the 16-bit
-// encodings, 2 for every encoding.
-#ifndef LBMP_ALT_WALK
-#define LBMP_ALT_WALK 1
-#endif
 
 // One wavefront walks the rows of its strip in direction DIR (+1: y0 up to
 // y1 - 1; -1: y1 - 1 down to y0).  Every row is pulled and reduced to density and
@@ -268,7 +260,7 @@ __device__ __forceinline__ void strip_tile(
     // end of its walk.)  Measured on the 8192 x 4096 splash: +3 % for global FP16
     // offsets, +0.4 % for destination-scaled FP16, and -5 % for FP32, which keeps
     // one direction.
-    constexpr bool alt = LBMP_ALT_WALK == 2 || (LBMP_ALT_WALK == 1 && sizeof(typename C::T) == 2);
+    constexpr bool alt = sizeof(typename C::T) == 2;
     if constexpr (MODE == kModeStep && alt) {
         if (ty & 1) {
             strip_walk<S, WALLS, MODE, PSI, -1>(fin, fout, k, tile, lane, ty, live, xci, xm, xc, xp, flag,
@@ -282,7 +274,7 @@ __device__ __forceinline__ void strip_tile(
 
 template <int S, bool WALLS, int MODE, int PSI>
 __global__ __launch_bounds__(kWave * step_waves_per_block(S))
-__attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
+__attribute__((amdgpu_waves_per_eu(1))) void d2q9_strip(
     const typename Codec<S>::T* __restrict__ fin, typename Codec<S>::T* __restrict__ fout,
     StepConst k, int* __restrict__ flag, float* __restrict__ rho_out, float* __restrict__ ux_out,
     float* __restrict__ uy_out, DiagConst dg, double* __restrict__ partial)
@@ -308,12 +300,6 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_strip(
 // output are the psi halo.  Each site's arithmetic is that of strip_walk, so the
 // results are bitwise those of the one-column kernel.  Needs an even nx, so that
 // no pair straddles the periodic seam.
-#ifndef LBMP_PAIR_BLOCKS_PER_CU
-#define LBMP_PAIR_BLOCKS_PER_CU 0
-#endif
-#ifndef LBMP_PAIR
-#define LBMP_PAIR 1
-#endif
 
 __device__ __forceinline__ float f16_lo(unsigned w)
 {
@@ -331,15 +317,20 @@ __device__ __forceinline__ float bf16_hi(unsigned w)
 {
     return static_cast<float>(__builtin_bit_cast(__bf16, static_cast<unsigned short>(w >> 16)));
 }
+// Two FP16 values (round to nearest even) in one 32-bit word, low half first.  Built
+// as a two-element vector so that the conversions write the two halves of one
+// register directly (no separate or/shift to pack them).
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned pack_f16(float lo, float hi)
 {
-    return static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<_Float16>(lo))) |
-           (static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<_Float16>(hi))) << 16);
+    const half2v v = {static_cast<_Float16>(lo), static_cast<_Float16>(hi)};
+    return __builtin_bit_cast(unsigned, v);
 }
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
 {
-    return static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<__bf16>(lo))) |
-           (static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<__bf16>(hi))) << 16);
+    const bf16x2v v = {static_cast<__bf16>(lo), static_cast<__bf16>(hi)};
+    return __builtin_bit_cast(unsigned, v);
 }
 
 // Raw pairs of lattice row y for the pull (Eq. 5): w[a] holds population a's
@@ -578,16 +569,12 @@ __device__ __forceinline__ void pair_walk(const _Float16* __restrict__ fin, _Flo
     if (bad) flag[0] = kFlagUnstable;
 }
 
+// Strip `tile` of a lattice stepped with two columns per lane (k.tiles_x counts
+// 124-column tiles); tiles in bands of `band` strips, as strip_tile.
 template <bool WALLS, int PSI>
-__global__ __launch_bounds__(kWave * kPairWaves)
-__attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_pair(
-    const _Float16* __restrict__ fin, _Float16* __restrict__ fout, StepConst k, int* __restrict__ flag)
+__device__ __forceinline__ void pair_tile(const _Float16* __restrict__ fin, _Float16* __restrict__ fout,
+                                          const StepConst& k, const int tile, const int lane, int* __restrict__ flag)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = logical_block(blockIdx.x, gridDim.x) * kPairWaves + wave;
-    if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
-    // tiles in bands of `band` strips, as strip_tile (k.tiles_x counts 124-column tiles)
     const int band0 = (tile / (k.tiles_x * k.band)) * k.band;
     const int band_h = min(k.band, k.tiles_y - band0);
     const int r = tile - band0 * k.tiles_x;
@@ -603,6 +590,18 @@ __attribute__((amdgpu_waves_per_eu(LBMP_STEP_WAVES_PER_EU))) void d2q9_pair(
         pair_walk<WALLS, PSI, -1>(fin, fout, k, ty, live, qb, flag);
     else
         pair_walk<WALLS, PSI, 1>(fin, fout, k, ty, live, qb, flag);
+}
+
+template <bool WALLS, int PSI>
+__global__ __launch_bounds__(kWave * kPairWaves)
+__attribute__((amdgpu_waves_per_eu(1))) void d2q9_pair(
+    const _Float16* __restrict__ fin, _Float16* __restrict__ fout, StepConst k, int* __restrict__ flag)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = logical_block(blockIdx.x, gridDim.x) * kPairWaves + wave;
+    if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
+    pair_tile<WALLS, PSI>(fin, fout, k, tile, lane, flag);
 }
 
 // Persistent multi-instance step: one workgroup owns one lattice and advances
@@ -635,29 +634,54 @@ __global__ __launch_bounds__(kWave * kBatchWaves) void d2q9_batch(
     if (threadIdx.x == 0) clock_out[2 * blockIdx.x + 1] = wall_clock64();
 }
 
-// Flat multi-instance step: one launch advances every lattice by one step.
+// Flat multi-instance step: one launch advances every lattice of a list by one step.
 // Global tile g belongs to the lattice i with tile_start[i] <= g < tile_start[i+1];
 // wg_first[b] is the lattice of workgroup b's first tile, so each wavefront
-// finds its lattice by a short forward scan.  Launch shape as the single
-// lattice step (16 strips per workgroup, XCD-aware renumbering).
-template <int S, bool WALLS, int PSI>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_batch_flat(
+// finds its lattice by a short forward scan.  WPB wavefronts (strips) per
+// workgroup, XCD-aware renumbering as the single-lattice step.
+template <int WPB>
+__device__ __forceinline__ const BatchInstance* flat_lattice(const BatchInstance* __restrict__ inst,
+                                                             const int* __restrict__ tile_start,
+                                                             const int* __restrict__ wg_first, int ntotal, int& g)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int blk = logical_block(blockIdx.x, gridDim.x);
+    g = blk * WPB + wave;
+    if (g >= ntotal) return nullptr;
+    int i = wg_first[blk];
+    while (g >= tile_start[i + 1]) ++i;
+    g -= tile_start[i];
+    return inst + i;
+}
+
+template <int S, bool WALLS, int PSI, int WPB>
+__global__ __launch_bounds__(kWave * WPB) void d2q9_batch_flat(
     const BatchInstance* __restrict__ inst, const int* __restrict__ tile_start,
     const int* __restrict__ wg_first, int ntotal, int parity)
 {
     using T = typename Codec<S>::T;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int blk = logical_block(blockIdx.x, gridDim.x);
-    const int g = blk * kWavesPerBlock + wave;
-    if (g >= ntotal) return;
-    int i = wg_first[blk];
-    while (g >= tile_start[i + 1]) ++i;
-    const BatchInstance& I = inst[i];
-    const StepConst k = I.k;
+    int g;
+    const BatchInstance* I = flat_lattice<WPB>(inst, tile_start, wg_first, ntotal, g);
+    if (!I) return;  // whole wavefront leaves together
+    const StepConst k = I->k;
     DiagConst dg{};
-    strip_tile<S, WALLS, kModeStep, PSI>(reinterpret_cast<const T*>(I.f[parity]), reinterpret_cast<T*>(I.f[parity ^ 1]),
-                                    k, g - tile_start[i], lane, I.flag, nullptr, nullptr, nullptr, dg, nullptr);
+    strip_tile<S, WALLS, kModeStep, PSI>(reinterpret_cast<const T*>(I->f[parity]), reinterpret_cast<T*>(I->f[parity ^ 1]),
+                                         k, g, threadIdx.x & (kWave - 1), I->flag, nullptr, nullptr, nullptr, dg, nullptr);
+}
+
+// The same over lattices of the destination-scaled FP16 storage with an even nx,
+// stepped with two columns per lane (bitwise the one-column step).
+template <bool WALLS, int PSI>
+__global__ __launch_bounds__(kWave * kPairWaves) void d2q9_batch_pair(
+    const BatchInstance* __restrict__ inst, const int* __restrict__ tile_start,
+    const int* __restrict__ wg_first, int ntotal, int parity)
+{
+    int g;
+    const BatchInstance* I = flat_lattice<kPairWaves>(inst, tile_start, wg_first, ntotal, g);
+    if (!I) return;
+    const StepConst k = I->k;
+    pair_tile<WALLS, PSI>(reinterpret_cast<const _Float16*>(I->f[parity]), reinterpret_cast<_Float16*>(I->f[parity ^ 1]),
+                          k, g, threadIdx.x & (kWave - 1), I->flag);
 }
 
 // Single-block, fixed-order reduction of per-wave partials (deterministic).
@@ -804,9 +828,7 @@ static size_t occupancy_cap_lds(int cap)
     return per_cu / (size_t)(cap + 1) + 256;
 }
 
-#ifndef LBMP_DEST_BLOCKS_PER_CU
-#define LBMP_DEST_BLOCKS_PER_CU 5
-#endif
+constexpr int kDestBlocksPerCu = 5;  // one-column destination-scaled FP16 step (see occupancy_cap_lds)
 
 static int strip_blocks(const StepConst& k, int waves_per_block)
 {
@@ -821,7 +843,7 @@ static hipError_t launch_mode(const void* fin, void* fout, const StepConst& k, i
 {
     using T = typename Codec<S>::T;
     constexpr int wpb = step_waves_per_block(S);
-    const size_t lds = occupancy_cap_lds(S == kStoreF16Dest ? LBMP_DEST_BLOCKS_PER_CU : 0);
+    const size_t lds = occupancy_cap_lds(S == kStoreF16Dest ? kDestBlocksPerCu : 0);
     hipLaunchKernelGGL((d2q9_strip<S, WALLS, MODE, PSI>), dim3(strip_blocks(k, wpb)),
                        dim3(kWave * wpb), lds, s, static_cast<const T*>(fin),
                        static_cast<T*>(fout), k, flag, rho, ux, uy, dg, partial);
@@ -897,14 +919,14 @@ static hipError_t launch_pair_psi(const void* fin, void* fout, const StepConst& 
     const long long tiles = (long long)kp.tiles_x * kp.tiles_y;
     const int blocks = (int)((tiles + kPairWaves - 1) / kPairWaves);
     hipLaunchKernelGGL((d2q9_pair<WALLS, PSI>), dim3(blocks), dim3(kWave * kPairWaves),
-                       occupancy_cap_lds(LBMP_PAIR_BLOCKS_PER_CU), s, static_cast<const _Float16*>(fin),
+                       0, s, static_cast<const _Float16*>(fin),
                        static_cast<_Float16*>(fout), kp, flag);
     return hipGetLastError();
 }
 
 bool pair_step(int store, int nx)
 {
-    return LBMP_PAIR && store == kStoreF16Dest && nx % 2 == 0 && nx >= 4;
+    return store == kStoreF16Dest && nx % 2 == 0 && nx >= 4;
 }
 
 int pair_blocks_per_cu(bool walls)
@@ -954,26 +976,44 @@ hipError_t launch_batch(int store, bool walls, int psi, const BatchInstance* ins
     return hipGetLastError();
 }
 
-hipError_t launch_batch_flat(int store, bool walls, int psi, const BatchInstance* inst, const int* tile_start,
-                             const int* wg_first, int ntotal, int parity, hipStream_t s)
+int batch_waves_per_block(int store, bool pair)
+{
+    if (pair) return kPairWaves;
+    return store == kStoreF16Dest ? kBatchWavesDest : kWavesPerBlock;
+}
+
+hipError_t launch_batch_flat(int store, bool walls, int psi, bool pair, const BatchInstance* inst,
+                             const int* tile_start, const int* wg_first, int ntotal, int parity, hipStream_t s)
 {
     if (ntotal <= 0) return hipSuccess;
-    const int blocks = (ntotal + kWavesPerBlock - 1) / kWavesPerBlock;
-#define LBMP_FLAT(S_, W_)                                                                          \
+    const int wpb = batch_waves_per_block(store, pair);
+    const int blocks = (ntotal + wpb - 1) / wpb;
+    if (pair) {
+        if (store != kStoreF16Dest) return hipErrorInvalidValue;
+#define LBMP_PAIRB(W_, P_)                                                                         \
+    hipLaunchKernelGGL((d2q9_batch_pair<W_, P_>), dim3(blocks), dim3(kWave * kPairWaves), 0, s, inst, \
+                       tile_start, wg_first, ntotal, parity)
+        if (walls) {
+            if (psi == kPsiSS) LBMP_PAIRB(true, kPsiSS); else LBMP_PAIRB(true, kPsiCS);
+        } else {
+            if (psi == kPsiSS) LBMP_PAIRB(false, kPsiSS); else LBMP_PAIRB(false, kPsiCS);
+        }
+#undef LBMP_PAIRB
+        return hipGetLastError();
+    }
+#define LBMP_FLAT(S_, W_, N_)                                                                      \
     do {                                                                                           \
         if (psi == kPsiSS)                                                                         \
-            hipLaunchKernelGGL((d2q9_batch_flat<S_, W_, kPsiSS>), dim3(blocks),                    \
-                               dim3(kWave * kWavesPerBlock), 0, s, inst, tile_start, wg_first,     \
-                               ntotal, parity);                                                    \
+            hipLaunchKernelGGL((d2q9_batch_flat<S_, W_, kPsiSS, N_>), dim3(blocks), dim3(kWave * N_), \
+                               0, s, inst, tile_start, wg_first, ntotal, parity);                  \
         else                                                                                       \
-            hipLaunchKernelGGL((d2q9_batch_flat<S_, W_, kPsiCS>), dim3(blocks),                    \
-                               dim3(kWave * kWavesPerBlock), 0, s, inst, tile_start, wg_first,     \
-                               ntotal, parity);                                                    \
+            hipLaunchKernelGGL((d2q9_batch_flat<S_, W_, kPsiCS, N_>), dim3(blocks), dim3(kWave * N_), \
+                               0, s, inst, tile_start, wg_first, ntotal, parity);                  \
     } while (0)
     switch (store) {
-    case kStoreF32: if (walls) LBMP_FLAT(kStoreF32, true); else LBMP_FLAT(kStoreF32, false); break;
-    case kStoreF16Local: if (walls) LBMP_FLAT(kStoreF16Local, true); else LBMP_FLAT(kStoreF16Local, false); break;
-    case kStoreF16Dest: if (walls) LBMP_FLAT(kStoreF16Dest, true); else LBMP_FLAT(kStoreF16Dest, false); break;
+    case kStoreF32: if (walls) LBMP_FLAT(kStoreF32, true, kWavesPerBlock); else LBMP_FLAT(kStoreF32, false, kWavesPerBlock); break;
+    case kStoreF16Local: if (walls) LBMP_FLAT(kStoreF16Local, true, kWavesPerBlock); else LBMP_FLAT(kStoreF16Local, false, kWavesPerBlock); break;
+    case kStoreF16Dest: if (walls) LBMP_FLAT(kStoreF16Dest, true, kBatchWavesDest); else LBMP_FLAT(kStoreF16Dest, false, kBatchWavesDest); break;
     default: return hipErrorInvalidValue;
     }
 #undef LBMP_FLAT

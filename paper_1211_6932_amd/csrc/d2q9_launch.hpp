@@ -27,11 +27,17 @@ int pair_blocks_per_cu(bool walls);
 hipError_t launch_batch(int store, bool walls, int psi, const BatchInstance* inst, int n, int steps,
                         int parity, unsigned long long* clocks, hipStream_t s);
 
-// Flat batched step: one step of every lattice in one launch over the global
-// tile list (tile_start: n+1 prefix sums; wg_first: lattice of each
-// workgroup's first tile, indexed by the renumbered workgroup id).
-hipError_t launch_batch_flat(int store, bool walls, int psi, const BatchInstance* inst, const int* tile_start,
-                             const int* wg_first, int ntotal, int parity, hipStream_t s);
+// Flat batched step: one step of every lattice of a list in one launch over the
+// global tile list (tile_start: n+1 prefix sums; wg_first: lattice of each
+// workgroup's first tile, indexed by the renumbered workgroup id).  pair: the
+// lattices are destination-scaled FP16 with an even nx and are stepped two
+// columns per lane (descriptors with 124-column tiles); otherwise one column
+// per lane (62-column tiles).
+hipError_t launch_batch_flat(int store, bool walls, int psi, bool pair, const BatchInstance* inst,
+                             const int* tile_start, const int* wg_first, int ntotal, int parity, hipStream_t s);
+
+// Wavefronts (tiles) per workgroup of launch_batch_flat.
+int batch_waves_per_block(int store, bool pair);
 
 // Resident step workgroups per compute unit (0 if the query fails).
 int step_blocks_per_cu(int store, bool walls);

@@ -36,7 +36,6 @@ constexpr size_t kAlign = 256;
 constexpr int kDiagStripRows = 32;
 constexpr int kMinStripRows = 3;
 constexpr int kBatchPersistentRows = 24;  // measured best (one workgroup walks a whole lattice)
-constexpr int kBatchStepwiseRows = 2;     // measured best for the 512-lattice sweep
 constexpr int kDefaultBand = 1;
 constexpr int kDefaultGraphChunk = 32;
 constexpr int kMaxSide = 1 << 20;
@@ -63,7 +62,13 @@ size_t density_plane_bytes(int store)
     return store == LB_STORE_F16_DEST ? 2 : 0;
 }
 
-int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+// Elements per population row.  The rows are packed without padding: the nine (ten,
+// eleven) population rows of a lattice row, and consecutive lattice rows, then form one
+// contiguous stream.  Measured on the 512-lattice sweep (sides 64-512): FP32 73.3k
+// MLUPS with rows packed against 63.4k with rows padded to 64 elements, whose holes
+// break the stream (destination-scaled FP16: 96.9k against 88.9k).  The local-density
+// encodings round to an even count so that their FP32 density row stays 4-byte aligned.
+int pitch_of(int nx, int store) { return local_density(store) ? (nx + 1) / 2 * 2 : nx; }
 
 struct Layout {
     size_t flag_off, dout_off, partial_off, f_off[2], total, buf_bytes;
@@ -73,7 +78,7 @@ struct Layout {
 Layout layout_of(const lb_params& p)
 {
     Layout L{};
-    const int pitch = pitch_of(p.nx);
+    const int pitch = pitch_of(p.nx, p.store);
     L.buf_bytes = align_up((size_t)row_slots(p.store) * p.ny * pitch * elem_bytes(p.store), kAlign);
     const int tx = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
     const int ty = (p.ny + kDiagStripRows - 1) / kDiagStripRows;
@@ -103,8 +108,8 @@ lb_status validate(const lb_params* p)
     if (p->nx < 3 || p->ny < 3 || p->nx > kMaxSide || p->ny > kMaxSide)
         return fail(LB_EINVAL, "nx and ny must lie in [3, 2^20]");
     if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LB_EINVAL, "nx * ny exceeds 2^31 sites");
-    if ((long long)pitch_of(p->nx) * (p->store == LB_STORE_F32 ? 4 : 2) >= (1LL << 32))
-        return fail(LB_EINVAL, "a padded row must stay below 4 GiB");
+    if ((long long)pitch_of(p->nx, p->store) * row_slots(p->store) * (p->store == LB_STORE_F32 ? 4 : 2) >= (1LL << 32))
+        return fail(LB_EINVAL, "a lattice row must stay below 4 GiB");
     if (p->bc != LB_BC_PERIODIC && p->bc != LB_BC_WALLS_Y) return fail(LB_EINVAL, "unknown bc");
     if (p->store < LB_STORE_F32 || p->store > LB_STORE_F16_DEST) return fail(LB_EINVAL, "unknown store");
     if (!finite_all({p->a, p->b, p->R, p->T, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta, p->s_j,
@@ -140,7 +145,7 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
     lbmp::StepConst k{};
     k.nx = p.nx;
     k.ny = p.ny;
-    k.pitch = pitch_of(p.nx);
+    k.pitch = pitch_of(p.nx, p.store);
     k.strip_rows = strip_rows;
     k.band = band;
     k.tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
@@ -574,19 +579,51 @@ const char* lb_last_error(void) { return g_last_error.c_str(); }
 
 // ------------------------------------------------------------------ batched lattices
 
+namespace {
+
+// Default strip heights of the stepwise batch, per kernel group, measured on the
+// 512-lattice sweep (sides 64-512, packed rows, MI355X), MLUPS by strip rows:
+//   FP32, one column per lane:         2: 73.5k  3: 67.6k  5: 59.7k  8: 54.2k
+//   destination-scaled FP16 (two columns per lane for even nx, one for odd nx, both
+//   groups at the same height):        2: 81.2k  3: 92.1k  5: 98.2k  8: 100.7k
+//   source-density FP16:               3: 77.5k  5: 80.1k  8: 79.6k
+// A height per lattice-width class, chosen from uniform batches of each width, ran
+// slower on the mix (FP32 70.9k): the strips resident at any moment then cover
+// different row bands.  lb_batch_tune replaces the defaults by timings on the device
+// at hand.
+constexpr int kMaxStripRows = 64;
+constexpr int kTuneMaxRows = 8;
+
+int default_batch_rows(int store)
+{
+    if (store == LB_STORE_F16_DEST) return 8;
+    if (store == LB_STORE_F16_LOCAL) return 5;
+    return 2;
+}
+
+}  // namespace
+
 struct lb_batch {
     int n;
     int mode;                        // LB_BATCH_STEPWISE or LB_BATCH_PERSISTENT
-    int strip_rows;
-    int* tile_start;                 // device, n + 1 prefix sums of tiles (stepwise mode)
+    int fixed_rows;                  // > 0: every lattice walks strips of this height
+    int group_rows[2];               // stepwise heights per kernel group (default or tuned)
+    // Stepwise lattices form two groups, each stepped by its own launch: group 0 one
+    // column per lane, group 1 two columns per lane (destination-scaled FP16, even
+    // nx).  Group g holds dispatch positions [gfirst[g], gfirst[g] + gcount[g]) of
+    // `desc` and `order`; its tile prefix sums start at tile_start + gfirst[g] + g and
+    // its workgroup table at wg_first + wg_off[g].
+    int gfirst[2], gcount[2], ntotal[2];
+    size_t wg_off[2];
+    int* tile_start;                 // device, n + 2 entries
     int* wg_first;                   // device, lattice of each workgroup's first tile
-    int ntotal;                      // total tiles of one step
     size_t wg_capacity;              // entries available in wg_first
     hipGraph_t graph[2];
     hipGraphExec_t exec[2];
     hipEvent_t ev[2];                // bracket the last lb_batch_step (stepwise mode)
     std::vector<lb_ctx*> inst;       // per-lattice contexts on slices of the workspace
-    std::vector<int> order;          // dispatch position -> lattice index (largest first)
+    std::vector<int> order;          // dispatch position -> lattice index
+    std::vector<int> rows;           // strip height per lattice (current launch mode)
     lbmp::BatchInstance* desc;       // device descriptors in dispatch order
     unsigned long long* clocks;      // device, 2 per workgroup
     hipStream_t stream;
@@ -596,21 +633,24 @@ struct lb_batch {
 
 namespace {
 
-// Upper bound of the workgroups of a stepwise launch (one-row strips).
+// Whether lattice p is stepped two columns per lane in the stepwise batch.
+bool batch_pair(const lb_params& p) { return lbmp::pair_step(p.store, p.nx); }
+
+// Upper bound of the workgroups of the stepwise launches (one-row strips, one
+// column per lane, the smallest workgroup), per group.
 size_t batch_wg_capacity(const lb_params* p, int n)
 {
     size_t tiles = 0;
     for (int i = 0; i < n; ++i) tiles += (size_t)((p[i].nx + lbmp::kTileW - 1) / lbmp::kTileW) * p[i].ny;
-    return (tiles + lbmp::kWavesPerBlock - 1) / lbmp::kWavesPerBlock + 1;
+    const int wpb = std::min(lbmp::batch_waves_per_block(p[0].store, false), lbmp::batch_waves_per_block(p[0].store, true));
+    return tiles / wpb + 4;
 }
 
 size_t batch_header_bytes(const lb_params* p, int n)
 {
     return align_up((size_t)n * sizeof(lbmp::BatchInstance), kAlign) + align_up((size_t)n * 16, kAlign) +
-           align_up((size_t)(n + 1) * sizeof(int), kAlign) + align_up(batch_wg_capacity(p, n) * sizeof(int), kAlign);
+           align_up((size_t)(n + 2) * sizeof(int), kAlign) + align_up(batch_wg_capacity(p, n) * sizeof(int), kAlign);
 }
-
-int batch_default_rows(int mode) { return mode == LB_BATCH_PERSISTENT ? kBatchPersistentRows : kBatchStepwiseRows; }
 
 void drop_batch_graphs(lb_batch* b)
 {
@@ -622,46 +662,96 @@ void drop_batch_graphs(lb_batch* b)
     }
 }
 
-// Copy the per-lattice launch descriptors (dispatch order) and, for the
-// stepwise mode, the tile tables to the device.
+// Dispatch order: in the stepwise mode the one-column lattices, then the
+// two-column ones, each largest first (longest-processing-time order); in the
+// persistent mode every lattice in one group (one column per lane), largest first.
+void order_batch(lb_batch* b)
+{
+    const int n = b->n;
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    auto area = [&](int i) { return (long long)b->inst[i]->p.nx * b->inst[i]->p.ny; };
+    auto grp = [&](int i) { return b->mode == LB_BATCH_STEPWISE && batch_pair(b->inst[i]->p) ? 1 : 0; };
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+        if (grp(x) != grp(y)) return grp(x) < grp(y);
+        return area(x) > area(y);
+    });
+    b->order = idx;
+    b->gcount[0] = b->gcount[1] = 0;
+    for (int i = 0; i < n; ++i) ++b->gcount[grp(i)];
+    b->gfirst[0] = 0;
+    b->gfirst[1] = b->gcount[0];
+}
+
+// Strip height of lattice i in the current mode.
+int lattice_rows(const lb_batch* b, int i)
+{
+    if (b->fixed_rows > 0) return b->fixed_rows;
+    if (b->mode == LB_BATCH_PERSISTENT) return kBatchPersistentRows;
+    return b->group_rows[batch_pair(b->inst[i]->p) ? 1 : 0];
+}
+
+// Copy the per-lattice launch descriptors (dispatch order) and the tile tables of
+// both groups to the device.
 hipError_t write_batch_descriptors(lb_batch* b)
 {
     drop_batch_graphs(b);
-    std::vector<lbmp::BatchInstance> host(b->n);
-    std::vector<int> start(b->n + 1, 0);
-    for (int j = 0; j < b->n; ++j) {
-        lb_ctx* c = b->inst[b->order[j]];
-        host[j].k = derive(c->p, b->strip_rows, 1);
-        host[j].f[0] = c->f[0];
-        host[j].f[1] = c->f[1];
-        host[j].flag = c->flag;
-        start[j + 1] = start[j] + host[j].k.tiles_x * host[j].k.tiles_y;
+    const int n = b->n;
+    std::vector<lbmp::BatchInstance> host(n);
+    std::vector<int> start(n + 2, 0);
+    std::vector<int> first;
+    b->rows.assign(n, 0);
+    size_t woff = 0;
+    for (int g = 0; g < 2; ++g) {
+        const int j0 = b->gfirst[g], cnt = b->gcount[g];
+        int* st = start.data() + j0 + g;
+        st[0] = 0;
+        for (int j = 0; j < cnt; ++j) {
+            const int i = b->order[j0 + j];
+            lb_ctx* c = b->inst[i];
+            const int rows = lattice_rows(b, i);
+            b->rows[i] = rows;
+            lbmp::StepConst k = derive(c->p, rows, 1);
+            if (g == 1) k.tiles_x = (c->p.nx + lbmp::kPairTileW - 1) / lbmp::kPairTileW;
+            host[j0 + j].k = k;
+            host[j0 + j].f[0] = c->f[0];
+            host[j0 + j].f[1] = c->f[1];
+            host[j0 + j].flag = c->flag;
+            st[j + 1] = st[j] + k.tiles_x * k.tiles_y;
+        }
+        b->ntotal[g] = st[cnt];
+        const int wpb = lbmp::batch_waves_per_block(b->store, g == 1);
+        const int blocks = (b->ntotal[g] + wpb - 1) / wpb;
+        b->wg_off[g] = woff;
+        for (int blk = 0, i = 0; blk < blocks; ++blk) {
+            const int t = blk * wpb;
+            while (t >= st[i + 1]) ++i;
+            first.push_back(i);
+        }
+        woff += (size_t)blocks;
     }
-    b->ntotal = start[b->n];
-    const int blocks = (b->ntotal + lbmp::kWavesPerBlock - 1) / lbmp::kWavesPerBlock;
-    if ((size_t)blocks > b->wg_capacity) return hipErrorInvalidValue;
-    std::vector<int> first(blocks);
-    for (int blk = 0, i = 0; blk < blocks; ++blk) {
-        const int g = blk * lbmp::kWavesPerBlock;
-        while (g >= start[i + 1]) ++i;
-        first[blk] = i;
-    }
-    hipError_t e = hipMemcpyAsync(b->desc, host.data(), b->n * sizeof(lbmp::BatchInstance),
-                                  hipMemcpyHostToDevice, b->stream);
+    if (woff > b->wg_capacity) return hipErrorInvalidValue;
+    hipError_t e = hipMemcpyAsync(b->desc, host.data(), n * sizeof(lbmp::BatchInstance), hipMemcpyHostToDevice,
+                                  b->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->tile_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice,
-                           b->stream);
-    if (e == hipSuccess && blocks > 0)
-        e = hipMemcpyAsync(b->wg_first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice,
-                           b->stream);
+        e = hipMemcpyAsync(b->tile_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !first.empty())
+        e = hipMemcpyAsync(b->wg_first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     return e;
 }
 
+// One step of every lattice (stepwise mode) reading buffer `parity`.
 hipError_t batch_flat_launch(lb_batch* b, int parity)
 {
-    return lbmp::launch_batch_flat(b->store, b->bc == LB_BC_WALLS_Y, b->psi, b->desc, b->tile_start, b->wg_first,
-                                   b->ntotal, parity, b->stream);
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+        if (b->gcount[g] == 0) continue;
+        e = lbmp::launch_batch_flat(b->store, b->bc == LB_BC_WALLS_Y, b->psi, g == 1, b->desc + b->gfirst[g],
+                                    b->tile_start + b->gfirst[g] + g, b->wg_first + b->wg_off[g], b->ntotal[g],
+                                    parity, b->stream);
+    }
+    return e;
 }
 
 lb_status build_batch_graph(lb_batch* b, int from)
@@ -739,7 +829,7 @@ lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* wor
     b->clocks = reinterpret_cast<unsigned long long*>(ws + hoff);
     hoff += align_up((size_t)n * 16, kAlign);
     b->tile_start = reinterpret_cast<int*>(ws + hoff);
-    hoff += align_up((size_t)(n + 1) * sizeof(int), kAlign);
+    hoff += align_up((size_t)(n + 2) * sizeof(int), kAlign);
     b->wg_first = reinterpret_cast<int*>(ws + hoff);
     b->wg_capacity = batch_wg_capacity(p, n);
     b->mode = LB_BATCH_STEPWISE;
@@ -762,13 +852,8 @@ lb_status lb_batch_init(lb_batch** out, const lb_params* p, int32_t n, void* wor
         }
         off += bytes;
     }
-    // dispatch the largest lattices first (longest-processing-time order)
-    b->order.resize(n);
-    for (int i = 0; i < n; ++i) b->order[i] = i;
-    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
-        return (long long)p[x].nx * p[x].ny > (long long)p[y].nx * p[y].ny;
-    });
-    b->strip_rows = batch_default_rows(b->mode);
+    b->group_rows[0] = b->group_rows[1] = default_batch_rows(b->store);
+    order_batch(b);
     hipError_t e = write_batch_descriptors(b);
     if (e != hipSuccess) {
         lb_batch_destroy(b);
@@ -945,11 +1030,70 @@ lb_status lb_batch_set_launch(lb_batch* b, int32_t mode, int32_t strip_rows)
 {
     if (!b) return fail(LB_EINVAL, "batch is NULL");
     if (mode != LB_BATCH_STEPWISE && mode != LB_BATCH_PERSISTENT) return fail(LB_EINVAL, "unknown batch mode");
-    if (strip_rows < 0) return fail(LB_EINVAL, "strip_rows must be >= 0");
+    if (strip_rows < 0 || strip_rows > kMaxStripRows) return fail(LB_EINVAL, "strip_rows must lie in [0, 64]");
     b->mode = mode;
-    b->strip_rows = strip_rows ? strip_rows : batch_default_rows(mode);
+    b->fixed_rows = strip_rows;
+    order_batch(b);
     hipError_t e = write_batch_descriptors(b);
     if (e != hipSuccess) return hip_fail(e, "batch descriptors");
+    return LB_OK;
+}
+
+lb_status lb_batch_tune(lb_batch* b, int32_t trial_steps, int32_t* rows_out)
+{
+    if (!b) return fail(LB_EINVAL, "batch is NULL");
+    if (b->poisoned) return fail(LB_ESTATE, "batch poisoned by an earlier failure");
+    if (trial_steps < 1 || trial_steps > 1000) return fail(LB_EINVAL, "trial_steps must lie in [1, 1000]");
+    if (b->mode != LB_BATCH_STEPWISE) return fail(LB_EINVAL, "lb_batch_tune tunes the stepwise mode");
+    if (b->stream == nullptr) return fail(LB_EINVAL, "lb_batch_tune needs a stream other than the legacy stream");
+    b->fixed_rows = 0;
+    const int parity = b->inst[0]->cur;
+    // Seconds of `trial_steps` launches that all read buffer `parity` and write the
+    // other one: the state (buffer parity) is unchanged, and the other buffer is
+    // overwritten in full by the next step.  The least of three repetitions.
+    auto time_launches = [&](double& sec) -> hipError_t {
+        hipError_t e = write_batch_descriptors(b);
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = batch_flat_launch(b, parity);
+        sec = 1e30;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(b->ev[0], b->stream);
+            for (int t = 0; t < trial_steps && e == hipSuccess; ++t) e = batch_flat_launch(b, parity);
+            if (e == hipSuccess) e = hipEventRecord(b->ev[1], b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b->ev[1]);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev[0], b->ev[1]);
+            sec = std::min(sec, ms * 1e-3);
+        }
+        return e;
+    };
+    // each kernel group (the larger first) gets the height that runs its share of the
+    // batch fastest, with the other group at its current height
+    const int first = b->gcount[1] > b->gcount[0] ? 1 : 0;
+    for (int gi = 0; gi < 2; ++gi) {
+        const int g = gi == 0 ? first : 1 - first;
+        if (b->gcount[g] == 0) continue;
+        int best_r = b->group_rows[g];
+        double best = 1e30;
+        hipError_t e = hipSuccess;
+        for (int cand = 1; cand <= kTuneMaxRows && e == hipSuccess; ++cand) {
+            b->group_rows[g] = cand;
+            double sec = 0.0;
+            e = time_launches(sec);
+            if (e == hipSuccess && sec < best) {
+                best = sec;
+                best_r = cand;
+            }
+        }
+        b->group_rows[g] = best_r;
+        if (e != hipSuccess) {
+            b->poisoned = true;
+            return hip_fail(e, "lb_batch_tune trial launches");
+        }
+    }
+    hipError_t e = write_batch_descriptors(b);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptors");
+    if (rows_out)
+        for (int i = 0; i < b->n; ++i) rows_out[i] = b->rows[i];
     return LB_OK;
 }
 

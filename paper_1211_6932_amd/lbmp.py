@@ -64,7 +64,7 @@ EXPORTS = [
     "lb_destroy", "lb_last_error", "lb_copy_probe",
     "lb_batch_workspace_bytes", "lb_batch_init", "lb_batch_step", "lb_batch_moments",
     "lb_batch_diagnostics", "lb_batch_get_state", "lb_batch_check", "lb_batch_times", "lb_batch_set_launch",
-    "lb_batch_destroy", "lb_batch_diagnostics_all",
+    "lb_batch_destroy", "lb_batch_diagnostics_all", "lb_batch_tune",
     "lbml_workspace_bytes", "lbml_init", "lbml_set_params", "lbml_get_params", "lbml_forward",
     "lbml_loss_grad", "lbml_adam", "lbml_train_step", "lbml_destroy", "lbml_profile_extract",
     "lbml_profile_to_rho0", "lbml_gemm_bf16", "lbml_profile_scratch_bytes", "lbml_profile_to_rho0_mass",
@@ -135,6 +135,8 @@ def load():
     L.lb_batch_times.restype = ctypes.c_int
     L.lb_batch_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.lb_batch_set_launch.restype = ctypes.c_int
+    L.lb_batch_tune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.lb_batch_tune.restype = ctypes.c_int
     L.lb_batch_destroy.argtypes = [vp]
     L.lb_batch_destroy.restype = ctypes.c_int
     L.lb_batch_diagnostics_all.argtypes = [vp, ctypes.POINTER(lb_region), ctypes.POINTER(lb_region),
@@ -334,6 +336,13 @@ def lb_batch_set_launch(b, mode: int, strip_rows: int = 0):
     return _check(load().lb_batch_set_launch(b, int(mode), int(strip_rows)), "lb_batch_set_launch")
 
 
+def lb_batch_tune(b, n: int, trial_steps: int = 8):
+    """Autotune the stepwise strip heights; returns the height chosen for each lattice."""
+    rows = (ctypes.c_int32 * n)()
+    _check(load().lb_batch_tune(b, int(trial_steps), rows), "lb_batch_tune")
+    return list(rows)
+
+
 def lb_batch_destroy(b):
     return load().lb_batch_destroy(b)
 
@@ -505,7 +514,8 @@ class Sim:
 
 
 class Batch:
-    """Many independent lattices advanced together by one persistent launch."""
+    """Many independent lattices advanced together (one launch per step, or one
+    persistent launch)."""
 
     def __init__(self, params_list, rho0_list, ux0_list=None, uy0_list=None, store="f32", stream=None,
                  device="cuda"):
@@ -568,6 +578,10 @@ class Batch:
     def set_launch(self, mode=0, strip_rows=0):
         """mode: LB_BATCH_STEPWISE (0) or LB_BATCH_PERSISTENT (1)."""
         lb_batch_set_launch(self.b, mode, strip_rows)
+
+    def tune(self, trial_steps=8):
+        """Autotune the stepwise strip heights (state unchanged); per-lattice heights."""
+        return lb_batch_tune(self.b, self.n, trial_steps)
 
     def check(self):
         return lb_batch_check(self.b)

@@ -104,10 +104,15 @@ def test_sizes():
     p.store = B.LB_STORE_F16_LOCAL  # 16-bit offsets plus the FP32 site densities
     assert B.lb_state_bytes(p) == 9 * 128 * 128 * 2 + 128 * 128 * 4
     assert B.lb_workspace_bytes(p) >= 2 * 11 * 128 * 128 * 2
-    # ragged widths are padded to 64-element rows
+    # population rows are packed (pitch = nx): two buffers of 9 x 5 x 67 floats plus the
+    # flag, result and diagnostics-partial blocks (< 2 KiB here), each 256-byte aligned
     p2 = good()
     p2.nx, p2.ny = 67, 5
-    assert B.lb_workspace_bytes(p2) >= 2 * 9 * 5 * 128 * 4
+    packed = 2 * 9 * 5 * 67 * 4
+    assert packed <= B.lb_workspace_bytes(p2) <= packed + 2048 + 3 * 256
+    # the local-density encodings round the pitch to even (4-byte aligned FP32 densities)
+    p2.store = B.LB_STORE_F16_LOCAL
+    assert B.lb_workspace_bytes(p2) >= 2 * 11 * 5 * 68 * 2
 
 
 def test_host_side_errors_need_no_gpu():

@@ -69,8 +69,8 @@ def test_batch_is_bitwise_equal_to_single_runs(store, bc, mode):
 
 @pytest.mark.parametrize("bc", [0, 1])
 def test_two_column_step_is_bitwise_the_one_column_step(bc):
-    """Destination-scaled FP16 with an even nx steps with two columns per lane; a batch
-    runs the one-column kernel.  Ragged width (250 = 2 x 124 + 2) and height, strip
+    """Destination-scaled FP16 with an even nx steps with two columns per lane; the
+    persistent batch runs the one-column kernel.  Ragged width (250 = 2 x 124 + 2) and height, strip
     heights from 1 to 7 (both walk directions), walls and periodic."""
     nx, ny = 250, 77
     p = W.base_params(nx, ny, a=0.5, t_over_tc=0.6, bc=bc)
@@ -78,6 +78,7 @@ def test_two_column_step_is_bitwise_the_one_column_step(bc):
     rho0 = W.droplet_field(nx, ny, 20.0, rl, rg, periodic_y=(bc == 0))
     print(f"[gpu-case] two-column step bc={bc} shape=({ny}, {nx})", flush=True)
     b = B.Batch([p], [f32(rho0)], store="f16dest")
+    b.set_launch(B.LB_BATCH_PERSISTENT)  # one column per lane (stepwise would use two)
     b.step(40)
     assert b.check() == (B.LB_OK, 0)
     ref = b.get_state(0, B.lb_state_bytes(B.make_params(p, "f16dest"))).cpu().numpy()
@@ -142,3 +143,58 @@ def test_batch_rejects_bad_input_and_mixed_store():
     assert B.lb_batch_workspace_bytes(params, 2) == 0
     params = (B.lb_params * 1)(B.make_params(ws[0].params, "f16"))
     assert B.lb_batch_workspace_bytes(params, 1) == 0
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_batch_lattices_match_the_oracle(bc):
+    """Every lattice of a mixed batch (different sizes, EOS parameters, circles and
+    ellipses; periodic or walls in y), advanced 1000 steps by the stepwise FP32 launch,
+    against the FP64 oracle: max|drho|/rho_l <= 1e-5 and max|du| <= 1e-3 max|u| + 1e-7,
+    the gate of the single-lattice parity test."""
+    from oracle import lbref as O
+    ws = mixed_lattices(bc)
+    print(f"[gpu-case] batch vs oracle bc={bc} n={len(ws)}", flush=True)
+    b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws])
+    b.step(1000)
+    assert b.check() == (B.LB_OK, 0)
+    for i, w in enumerate(ws):
+        rho, ux, uy = (t.cpu().numpy().astype(np.float64) for t in b.moments(i))
+        rho0 = np.asarray(w.rho0, np.float32).astype(np.float64)
+        r, u, v, *_ = O.State(O.Params(**w.params), rho0).step(1000).moments()
+        rl = W.coexistence(w.params["T"] / (W.TC_PER_A * w.params["a"]))[0]
+        err = np.abs(rho - r).max() / rl
+        uerr = max(np.abs(ux - u).max(), np.abs(uy - v).max())
+        umax = np.sqrt(u * u + v * v).max()
+        print(f"  lattice {i} {w.params['nx']}x{w.params['ny']}: drho/rho_l {err:.2e}, du {uerr:.2e} (max|u| {umax:.2e})")
+        assert err <= 1e-5, (i, err)
+        assert uerr <= 1e-3 * umax + 1e-7, (i, uerr, umax)
+    b.close()
+
+
+@pytest.mark.parametrize("store", ["f32", "f16dest"])
+def test_batch_tune_keeps_the_state_and_sets_heights(store):
+    """lb_batch_tune times trial launches that read the state and write only the
+    buffer the next step overwrites: after tuning, the batch continues bitwise as if it
+    had not been tuned.  Every lattice gets a height in [1, 8]."""
+    ws = mixed_lattices(0)
+    print(f"[gpu-case] batch tune store={store}", flush=True)
+    a = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws], store=store)
+    b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws], store=store)
+    a.step(21)
+    b.step(21)
+    rows = b.tune(trial_steps=2)
+    assert len(rows) == len(ws) and all(1 <= r <= 8 for r in rows)
+    a.step(30)
+    b.step(30)
+    for i, w in enumerate(ws):
+        nb = B.lb_state_bytes(B.make_params(w.params, store))
+        assert np.array_equal(a.get_state(i, nb).cpu().numpy(), b.get_state(i, nb).cpu().numpy()), i
+    with pytest.raises(B.LbError) as e:
+        B.lb_batch_tune(b.b, len(ws), trial_steps=0)
+    assert e.value.status == B.LB_EINVAL
+    b.set_launch(B.LB_BATCH_PERSISTENT)
+    with pytest.raises(B.LbError) as e:
+        b.tune()
+    assert e.value.status == B.LB_EINVAL
+    a.close()
+    b.close()

@@ -245,3 +245,99 @@ def test_16bit_laplace_jump_within_one_percent(store):
     assert np.abs(dp / lo["dp"] - 1.0).max() <= 0.03
     rho_out = np.mean([d["rho_out"] for d in samples])
     assert abs(rho_out / lo["rho_out"] - 1.0) <= 0.01
+
+
+# Per-encoding error table of the 512 x 256 splash crop (the splash of the 2048 x 1024
+# case cut down: R = 100, film 20, centre (256, 125), walls in y, a = 0.25,
+# T = 0.45 T_c, sigma = 0.114, s_e = s_zeta = 0.8, Re = 200), 2000 steps against the
+# FP64 oracle from the same FP32-rounded start.  Measured (MI355X) and bounded here:
+# the accurate encodings must stay within about twice what they show, and the
+# encodings that fail must keep failing by the recorded order of magnitude (a change
+# that alters either shows up here).
+CROP_BOUNDS = {
+    # store: (lower, upper) bounds of max|drho|/rho_l
+    "f32": (0.0, 1e-4),
+    "f16local": (1e-3, 5e-2),
+    "f16dest": (1e-3, 5e-2),
+    "bf16local": (0.1, 2.0),
+    "f16": (0.2, 2.0),
+    "bf16": (0.2, 5.0),
+}
+
+
+@pytest.fixture(scope="module")
+def crop_oracle():
+    w = W.splash_crop(Re=200)
+    o = O.State(O.Params(**w.params), f32(w.rho0).astype(np.float64), f32(w.ux0).astype(np.float64),
+                f32(w.uy0).astype(np.float64))
+    m0 = o.f.sum()
+    o.step(2000)
+    r, u, v, *_ = o.moments()
+    return w, r, u, v, o.f.sum() / m0 - 1.0
+
+
+@pytest.mark.parametrize("store", ["f32", "f16local", "f16dest", "bf16local", "f16", "bf16"])
+def test_splash_crop_error_table(store, crop_oracle):
+    """One row of the per-encoding table: max|drho|/rho_l, the largest relative error in
+    the vapour (oracle rho < 2 rho_g), max|du|/U and the mass drift after 2000 steps."""
+    w, r, u, v, _ = crop_oracle
+    rl, rg, U = w.info["rho_l"], w.info["rho_g"], w.info["U"]
+    print(f"[gpu-case] splash crop 512x256 store={store}", flush=True)
+    s = make_sim(w, store)
+    c = (w.params["nx"] / 2.0, 125.0)
+    m0 = s.diagnostics(c[0], c[1], 1.0, 2.0)["mass"]
+    s.step(2000)
+    stable = B.lb_check(s.ctx) == B.LB_OK
+    if stable:
+        rho, ux, uy = (t.cpu().numpy().astype(np.float64) for t in s.moments())
+        drho = np.abs(rho - r).max() / rl
+        vap = r < 2.0 * rg
+        dvap = (np.abs(rho - r)[vap] / r[vap]).max()
+        du = max(np.abs(ux - u).max(), np.abs(uy - v).max()) / U
+        dm = s.diagnostics(c[0], c[1], 1.0, 2.0)["mass"] / m0 - 1.0
+    else:
+        drho = dvap = du = dm = float("inf")
+    s.close()
+    print(f"TABLE store={store:9s} stable={stable} max|drho|/rho_l={drho:.2e} vapour max|drho|/rho={dvap:.2e} "
+          f"max|du|/U={du:.2e} mass drift={dm:+.2e}")
+    lo, hi = CROP_BOUNDS[store]
+    assert lo <= drho <= hi, (store, drho)
+    if store == "f32":
+        # Eqs. (5)-(6) conserve mass; FP32 storage rounding alone moves the FP64 sum
+        assert stable and abs(dm) <= 1e-6
+    elif store in ("f16local", "f16dest"):
+        # a 16-bit store re-rounds every population each step, so mass is conserved
+        # only to the storage precision (reported; bounded at 10 x the measured drift)
+        assert stable and abs(dm) <= 3e-3
+
+
+@pytest.mark.parametrize("store", ["f32", "f16local", "f16dest", "f16", "bf16local"])
+def test_laplace_jump_at_the_splash_temperature(store):
+    """The Laplace pressure jump at the splash's T = 0.45 T_c and a = 0.25 (density ratio
+    about 1400 in the droplet): 128 x 128 periodic droplet, R0 = 30, splash relaxation
+    rates (Re = 200).  The FP64 oracle's jump is converged to 4e-4 by step 12,000; each
+    encoding's jump is averaged over steps 10,000-12,000 (21 samples).  FP32 and the two
+    relative FP16 encodings are within 1 %; the global-offset FP16 and source-density
+    BF16 figures are reported (the test only records that they run)."""
+    p = dict(W.splash(nx=128, ny=128, Re=200).params, bc=0)
+    rl, rg = W.coexistence(0.45)
+    w = W.Workload("droplet_045", p, W.droplet_field(128, 128, 30.0, rl, rg), info=dict(rho_l=rl, rho_g=rg))
+    o = O.State(O.Params(**p), f32(w.rho0).astype(np.float64)).step(12000)
+    lo = post.laplace(o.moments()[0], p, 30.0)
+    print(f"[gpu-case] Laplace 128x128 T=0.45Tc store={store}", flush=True)
+    s = make_sim(w, store)
+    s.step(10000)
+    samples = []
+    for k in range(21):
+        if k:
+            s.step(100)
+        if B.lb_check(s.ctx) != B.LB_OK:
+            break
+        samples.append(post.laplace(s.moments()[0].cpu().numpy().astype(np.float64), p, 30.0)["dp"])
+    s.close()
+    dp = np.array(samples)
+    rel = dp.mean() / lo["dp"] - 1.0 if len(dp) == 21 else float("inf")
+    print(f"LAPLACE store={store:9s} dp {dp.mean() if len(dp) else float('nan'):.6e} vs oracle {lo['dp']:.6e}: "
+          f"{rel:+.3e} (samples {len(dp)})")
+    if store in ("f32", "f16local", "f16dest"):
+        assert abs(rel) <= 0.01
