@@ -17,7 +17,9 @@
  *             Eq. (4)  moment-space collision m* = m - L(m - m_eq) + (I - L/2) Sbar
  *             Eq. (5)  streaming f(x + e, t + 1) = f*(x, t), f* = M^-1 m*
  *             Eq. (6)  rho = sum f,  rho v = sum e f + F/2
- *             Eq. (7)  interaction force, w(1) = 1/3, w(2) = 1/12
+ *             Eq. (7)  interaction force, w(1) = 1/3, w(2) = 1/12 (nearest
+ *                      neighbours), or the 24-site stencil of nearest and
+ *                      next-nearest neighbours (Sec. III.B, epsilon = 10/31)
  *             Eq. (10) kinematic viscosity nu = (tau_nu - 1/2)/3
  *   Sec. III  Eq. (24) psi = sqrt(2 (p_EOS - rho c_s^2) / (G c^2))  (psi_form 0)
  *             Eq. (23) Sbragaglia-Shan psi = exp(-1/rho) (eps = 0) or
@@ -54,9 +56,47 @@ typedef struct {
     double a, b, R, T, G, sigma;        /* Eq. (30), Eq. (7)/(24), Eq. (25) */
     double s_rho, s_e, s_zeta, s_j, s_q;/* Eq. (2), as rates 1/tau         */
     double nu_l, nu_g, rho_switch;      /* Sec. IV.C viscosity switch      */
-    int32_t psi_form, pad2_;            /* Eq. (24) (0) or Eq. (23) (1)    */
+    int32_t psi_form;                   /* Eq. (24) (0) or Eq. (23) (1)    */
+    int32_t stencil;                    /* interaction range of Eq. (7)    */
     double psi_eps;                     /* epsilon of Eq. (23)             */
 } lbref_params;
+
+/* Interaction stencils of Eq. (7), F = -G psi(x) sum_e w(|e|^2) psi(x + e) e:
+ *   LBREF_NEAREST    the eight nearest neighbours, w(1) = 1/3, w(2) = 1/12 (Sec. II);
+ *   LBREF_MULTIRANGE nearest and next-nearest neighbours: the 24 sites with
+ *                    |e|^2 in {1, 2, 4, 5, 8}.  Sec. III.B quotes epsilon = 10/31 for
+ *                    such interactions without printing weights.  The weights used
+ *                    are the unique ones that make the stencil's moments isotropic up
+ *                    to eighth order with sum w e_x^2 = 1 (the normalisation of the
+ *                    nearest-neighbour weights, so the bulk term G psi^2 / 2 of
+ *                    Eq. (19) and Eq. (24) are unchanged):
+ *                    w(1) = 4/21, w(2) = 4/45, w(4) = 1/60, w(5) = 2/315,
+ *                    w(8) = 1/5040.  The isotropy conditions and the epsilon = 10/31
+ *                    of a flat interface are checked by the tests. */
+enum { LBREF_NEAREST = 0, LBREF_MULTIRANGE = 1 };
+
+/* Weight of a neighbour at squared distance q for the given stencil (0 if absent). */
+static double stencil_weight(int stencil, int q)
+{
+    if (stencil == LBREF_MULTIRANGE) {
+        switch (q) {
+        case 1: return 4.0 / 21.0;
+        case 2: return 4.0 / 45.0;
+        case 4: return 1.0 / 60.0;
+        case 5: return 2.0 / 315.0;
+        case 8: return 1.0 / 5040.0;
+        default: return 0.0;
+        }
+    }
+    return q == 1 ? 1.0 / 3.0 : (q == 2 ? 1.0 / 12.0 : 0.0);
+}
+
+static int stencil_reach(int stencil) { return stencil == LBREF_MULTIRANGE ? 2 : 1; }
+
+void lbref_stencil_weights(int stencil, double *w9)
+{
+    for (int q = 0; q < 9; ++q) w9[q] = stencil_weight(stencil, q);
+}
 
 /* D2Q9 velocities (standard ordering: rest, 4 axis, 4 diagonal). */
 static const int EX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -279,6 +319,7 @@ static int validate(const lbref_params *p)
 {
     if (!p || p->nx < 1 || p->ny < 1) return LBREF_EINVAL;
     if (p->bc != LBREF_PERIODIC && p->bc != LBREF_WALLS_Y) return LBREF_EINVAL;
+    if (p->stencil != LBREF_NEAREST && p->stencil != LBREF_MULTIRANGE) return LBREF_EINVAL;
     if (!(p->G < 0.0)) return LBREF_EINVAL;
     if (p->psi_form == LBREF_PSI_CS) {
         if (!(p->b > 0.0) || !(p->T > 0.0)) return LBREF_EINVAL;
@@ -335,8 +376,50 @@ static int psi_of(const lbref_params *p, const double *rho, double *psi)
     return bad ? LBREF_EUNSTABLE : LBREF_OK;
 }
 
-/* Eq. (7): F = -G psi(x) sum_a w(|e_a|^2) psi(x + e_a) e_a over the eight
- * neighbours.  Walls: psi beyond a wall equals the adjacent fluid row. */
+/* sum_e w(|e|^2) psi(x + e) e of Eq. (7) from the neighbourhood P[dy + 2][dx + 2]
+ * (|dx|, |dy| <= 2).  Written as differences psi(x + e) - psi(x - e), with the
+ * partners at +e_y and -e_y (or +e_x, -e_x) added as one pair, so that mirroring or
+ * transposing the neighbourhood mirrors or swaps (sx, sy) exactly in floating point. */
+static void stencil_sum(int stencil, const double P[5][5], double *sx, double *sy)
+{
+    const int r = stencil_reach(stencil);
+    double ax = 0.0, ay = 0.0;
+    for (int u = 1; u <= r; ++u)
+        for (int v = 0; v <= r; ++v) {
+            double w = stencil_weight(stencil, u * u + v * v);
+            if (w == 0.0) continue;
+            double dx, dy;
+            if (v == 0) {
+                dx = P[2][2 + u] - P[2][2 - u];
+                dy = P[2 + u][2] - P[2 - u][2];
+            } else {
+                dx = (P[2 + v][2 + u] - P[2 + v][2 - u]) + (P[2 - v][2 + u] - P[2 - v][2 - u]);
+                dy = (P[2 + u][2 + v] - P[2 - u][2 + v]) + (P[2 + u][2 - v] - P[2 - u][2 - v]);
+            }
+            ax += w * u * dx;
+            ay += w * u * dy;
+        }
+    *sx = ax;
+    *sy = ay;
+}
+
+/* psi around (x, y) into P[dy + 2][dx + 2] for |dx|, |dy| <= reach: x periodic; y
+ * periodic, or clamped to the nearest fluid row beyond a wall. */
+static void gather_psi(const lbref_params *p, const double *psi, int x, int y, double P[5][5])
+{
+    const int r = stencil_reach(p->stencil);
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) {
+            int xn = wrap(x + dx, p->nx), yn = y + dy;
+            if (p->bc == LBREF_PERIODIC) yn = wrap(yn, p->ny);
+            else if (yn < 0) yn = 0;
+            else if (yn >= p->ny) yn = p->ny - 1;
+            P[dy + 2][dx + 2] = psi[(size_t)yn * p->nx + xn];
+        }
+}
+
+/* Eq. (7): F = -G psi(x) sum_e w(|e|^2) psi(x + e) e over the stencil's
+ * neighbours.  Walls: psi beyond a wall equals the nearest fluid row, same column. */
 static void force_of(const lbref_params *p, const double *psi, double *Fx, double *Fy)
 {
     const int nx = p->nx, ny = p->ny;
@@ -344,19 +427,9 @@ static void force_of(const lbref_params *p, const double *psi, double *Fx, doubl
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t i = (size_t)y * nx + x;
-            double sx = 0.0, sy = 0.0;
-            for (int a = 1; a < Q; ++a) {
-                int xn = wrap(x + EX[a], nx);
-                int yn = y + EY[a];
-                if (p->bc == LBREF_PERIODIC) yn = wrap(yn, ny);
-                else if (yn < 0) yn = 0;
-                else if (yn >= ny) yn = ny - 1;
-                int e2 = EX[a] * EX[a] + EY[a] * EY[a];
-                double w = (e2 == 1) ? 1.0 / 3.0 : 1.0 / 12.0;
-                double ps = psi[(size_t)yn * nx + xn];
-                sx += w * ps * EX[a];
-                sy += w * ps * EY[a];
-            }
+            double P[5][5], sx, sy;
+            gather_psi(p, psi, x, y, P);
+            stencil_sum(p->stencil, P, &sx, &sy);
             Fx[i] = -p->G * psi[i] * sx;
             Fy[i] = -p->G * psi[i] * sy;
         }
@@ -499,41 +572,36 @@ int lbref_stream(const lbref_params *p, const double *fstar, double *f)
 
 /* Post-collision distributions f*(x) (Eq. 4 with Eq. 25) at n listed sites
  * (flat indices y * nx + x) of the post-streaming state f; out is [n][9].
- * Only the 3 x 3 neighbourhood of each site is evaluated. */
+ * Only the neighbourhood the stencil reaches (3 x 3 or 5 x 5) of each site is
+ * evaluated. */
 int lbref_collide_at(const lbref_params *p, const double *f, int64_t n, const int64_t *sites,
                      double *out)
 {
     int st = validate(p);
     if (st) return st;
     ensure_minv();
-    const int nx = p->nx, ny = p->ny;
+    const int nx = p->nx, ny = p->ny, r = stencil_reach(p->stencil);
     int bad = 0;
 #pragma omp parallel for reduction(| : bad)
     for (int64_t s = 0; s < n; ++s) {
         int x = (int)(sites[s] % nx), y = (int)(sites[s] / nx);
-        double psi_n[3][3], rho_c = 0.0, fl[Q];
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
+        double psi_n[5][5] = {{0.0}}, rho_c = 0.0, fl[Q];
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) {
                 int xn = wrap(x + dx, nx), yn = y + dy;
                 if (p->bc == LBREF_PERIODIC) yn = wrap(yn, ny);
                 else if (yn < 0) yn = 0;
                 else if (yn >= ny) yn = ny - 1;
-                double r = 0.0;
-                for (int a = 0; a < Q; ++a) r += f[IDX(p, a, yn, xn)];
+                double rr = 0.0;
+                for (int a = 0; a < Q; ++a) rr += f[IDX(p, a, yn, xn)];
                 int b = 0;
-                psi_n[dy + 1][dx + 1] = psi_site(p, r, &b);
+                psi_n[dy + 2][dx + 2] = psi_site(p, rr, &b);
                 bad |= b;
-                if (dx == 0 && dy == 0) rho_c = r;
+                if (dx == 0 && dy == 0) rho_c = rr;
             }
-        double sx = 0.0, sy = 0.0;
-        for (int a = 1; a < Q; ++a) {
-            int e2 = EX[a] * EX[a] + EY[a] * EY[a];
-            double w = (e2 == 1) ? 1.0 / 3.0 : 1.0 / 12.0;
-            double ps = psi_n[EY[a] + 1][EX[a] + 1];
-            sx += w * ps * EX[a];
-            sy += w * ps * EY[a];
-        }
-        double psi = psi_n[1][1];
+        double sx, sy;
+        stencil_sum(p->stencil, psi_n, &sx, &sy);
+        double psi = psi_n[2][2];
         double Fx = -p->G * psi * sx, Fy = -p->G * psi * sy;
         double jx = 0.0, jy = 0.0;
         for (int a = 0; a < Q; ++a) {

@@ -26,6 +26,7 @@ OK, EINVAL, ENOMEM, EUNSTABLE = 0, -1, -2, -4
 PERIODIC, WALLS_Y = 0, 1
 FORM_MOMENT, FORM_VELOCITY = 0, 1
 PSI_CS, PSI_SS = 0, 1  # pseudopotential of Eq. (24) / of Eq. (23)
+NEAREST, MULTIRANGE = 0, 1  # interaction stencil of Eq. (7): 8 nearest / 24 nearest and next-nearest
 
 
 class LbrefParams(ctypes.Structure):
@@ -36,7 +37,7 @@ class LbrefParams(ctypes.Structure):
         ("s_rho", ctypes.c_double), ("s_e", ctypes.c_double), ("s_zeta", ctypes.c_double),
         ("s_j", ctypes.c_double), ("s_q", ctypes.c_double),
         ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("rho_switch", ctypes.c_double),
-        ("psi_form", ctypes.c_int32), ("pad2_", ctypes.c_int32), ("psi_eps", ctypes.c_double),
+        ("psi_form", ctypes.c_int32), ("stencil", ctypes.c_int32), ("psi_eps", ctypes.c_double),
     ]
 
 
@@ -78,6 +79,7 @@ def lib():
         L.lbref_threads.argtypes = []
         L.lbref_threads.restype = ctypes.c_int
         L.lbref_collide_at.argtypes = [P, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), dp]
+        L.lbref_stencil_weights.argtypes = [ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -111,11 +113,12 @@ class Params:
     rho_switch: float = 0.13045
     psi_form: int = PSI_CS   # Eq. (24) from the EOS, or Eq. (23) with parameter psi_eps
     psi_eps: float = 0.0
+    stencil: int = NEAREST   # interaction stencil of Eq. (7)
 
     def c(self) -> LbrefParams:
         return LbrefParams(self.nx, self.ny, self.bc, 0, self.a, self.b, self.R, self.T, self.G,
                            self.sigma, self.s_rho, self.s_e, self.s_zeta, self.s_j, self.s_q,
-                           self.nu_l, self.nu_g, self.rho_switch, int(self.psi_form), 0,
+                           self.nu_l, self.nu_g, self.rho_switch, int(self.psi_form), int(self.stencil),
                            float(self.psi_eps))
 
 
@@ -135,6 +138,13 @@ def matrices():
     Minv = np.zeros(81)
     lib().lbref_matrices(_ptr(M), _ptr(Minv))
     return M.reshape(9, 9), Minv.reshape(9, 9)
+
+
+def stencil_weights(stencil: int):
+    """Weights w(q) of Eq. (7) by squared neighbour distance q = 0..8 (0 where absent)."""
+    w = np.zeros(9)
+    lib().lbref_stencil_weights(int(stencil), _ptr(w))
+    return w
 
 
 def p_eos(p: Params, rho: float) -> float:
