@@ -362,10 +362,12 @@ def bench_sweeps(args):
     nus = [float(v) for v in np.geomspace(0.0015, 0.15, 12)]
     ratios = (1, 20, 50)
     t1 = time.perf_counter()
-    failed = S.survival([W.paper_splash(nu, r) for r in ratios for nu in nus], 4000)
+    failed, failed_u = S.survival([W.paper_splash(nu, r) for r in ratios for nu in nus], 4000)
     t_visc = time.perf_counter() - t1
     visc = {str(r): S.lowest_stable_viscosity(nus, failed[i * len(nus):(i + 1) * len(nus)])
             for i, r in enumerate(ratios)}
+    visc_u = {str(r): S.lowest_stable_viscosity(nus, failed_u[i * len(nus):(i + 1) * len(nus)])
+              for i, r in enumerate(ratios)}
     t2 = {row[0]: row for row in golden["table2"]["rows"]}
     by_t = {c["T_over_Tc"]: c for c in curve}
     worst_l = max(abs(by_t[t]["rho_l"] / t2[t][1] - 1) for t in t2)
@@ -378,7 +380,8 @@ def bench_sweeps(args):
                                "(Sec. IV.C), one batched launch each", "parallelism": "single GPU"},
         "improved_curve_tau0.8": curve, "original_edge": edges,
         "paper_original_edge": {"T_over_Tc": 0.8, "ratio_tau0.6": 30.0, "ratio_tau0.8": 56.5},
-        "table1": table1, "lowest_nu_l": visc, "paper_lowest_nu_l": {"1": 0.075, "20": 0.009, "50": 0.0039},
+        "table1": table1, "lowest_nu_l": visc, "lowest_nu_l_max_u_below_cs": visc_u,
+        "viscosity_grid": nus, "paper_lowest_nu_l": {"1": 0.075, "20": 0.009, "50": 0.0039},
         "wall_seconds": {"droplet_sweep": round(t_sweep, 2), "viscosity_search": round(t_visc, 2)},
         "roofline": None, "cpu_baseline": None,
     }

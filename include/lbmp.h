@@ -83,6 +83,18 @@ typedef enum {
                        that pressure.                                                   */
 } lb_psi_form;
 
+typedef enum {
+    LB_STENCIL_NEAREST = 0,    /* Eq. (7) over the eight nearest neighbours, w(1) = 1/3,
+                                  w(2) = 1/12 (the paper's stencil)                           */
+    LB_STENCIL_MULTIRANGE = 1  /* nearest and next-nearest neighbours (Sec. III.B): the 24 sites
+                                  with |e|^2 in {1, 2, 4, 5, 8}, w = 4/21, 4/45, 1/60, 2/315,
+                                  1/5040, the weights isotropic to eighth order with
+                                  sum w e_x^2 = 1 (the bulk term G psi^2 / 2 is unchanged).
+                                  With sigma = 0 a flat interface follows Eq. (21) at
+                                  epsilon = 10/31, the value Sec. III.B quotes for such
+                                  interactions.  FP32 storage and single lattices only.      */
+} lb_stencil;
+
 /* Run parameters.  Rates are the inverse relaxation times 1/tau of Eq. (2).
  * The shear rate is per site: s_nu = 1/(3 nu + 1/2) with nu = nu_l where
  * rho >= rho_switch and nu_g elsewhere (Sec. IV.C; Eq. (10) gives
@@ -102,7 +114,7 @@ typedef struct {
     double rho_switch;       /* density at which nu switches from nu_g to nu_l           */
     double rho_ref;          /* reference density of LB_STORE_*_OFFSET (ignored otherwise) */
     int32_t psi_form;        /* lb_psi_form: pseudopotential of Eq. (24) or of Eq. (23)    */
-    int32_t reserved_;       /* set to 0                                                 */
+    int32_t stencil;         /* lb_stencil: interaction stencil of Eq. (7)               */
     double psi_eps;          /* epsilon of Eq. (23), >= 0 (LB_PSI_SS only)               */
 } lb_params;
 

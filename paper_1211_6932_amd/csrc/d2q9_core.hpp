@@ -27,6 +27,7 @@ namespace lbmp {
 constexpr int kWave = 64;
 constexpr int kTileW = kWave - 2;     // output columns per wavefront strip
 constexpr int kPairTileW = 2 * kWave - 4;  // output columns per wavefront, two columns per lane
+constexpr int kMrTileW = kWave - 4;   // output columns per wavefront, 24-site stencil (two halo lanes a side)
 constexpr int kPairWaves = 4;         // wavefronts per workgroup, two columns per lane
 constexpr int kWavesPerBlock = 16;    // wavefronts (strips) per workgroup: FP32 step, FP32 batch
 constexpr int kBatchWaves = 16;       // wavefronts per workgroup (= per lattice) of the persistent batch
@@ -52,6 +53,7 @@ constexpr int step_waves_per_block(int store)
 enum : int { kModeStep = 0, kModeMoments = 1, kModeDiag = 2 };
 enum : int { kFlagUnstable = 1, kFlagBadInput = 2 };
 enum : int { kPsiCS = 0, kPsiSS = 1 };  // psi of Eq. (24) from Eq. (30), or of Eq. (23)
+enum : int { kStencilNearest = 0, kStencilMultirange = 1 };  // interaction stencil of Eq. (7)
 
 // Per-launch constants (FP32 copies of FP64 host-derived values).
 struct StepConst {
@@ -75,6 +77,7 @@ struct StepConst {
     float a_e, b_e, c_e, a_z, b_z, c_z, a_q, b_q;
     float a_nu_l, b_nu_l, a_nu_g, b_nu_g;
     int psi_form;               // kPsiCS or kPsiSS
+    int stencil;                // kStencilNearest or kStencilMultirange
     float psi_eps, inv_psi_eps; // epsilon of Eq. (23) and 1/epsilon (0 when epsilon = 0)
     float off[9];               // w_a rho_ref: offsets of the 16-bit storage (0 for FP32)
 };
@@ -454,6 +457,51 @@ __device__ __forceinline__ void force_stencil(float mL, float mC, float mR, floa
     Fy = g * sy;
     // |F|^2 / psi^2 = G^2 |sum w psi e|^2: the improved term of Eq. (25) needs no division
     Fs2 = sx * sx + sy * sy;
+}
+
+// Eq. (7) over the 24 sites with |e|^2 in {1, 2, 4, 5, 8} (nearest and next-nearest
+// neighbours, Sec. III.B), weights 4/21, 4/45, 1/60, 2/315, 1/5040: the weights whose
+// moments are isotropic to eighth order with sum w e_x^2 = 1 (so the bulk term
+// G psi^2 / 2 is that of the nearest-neighbour stencil).  P[j][c] is psi at row
+// y - 2 + j, column x - 2 + c.  Each weight multiplies differences psi(x + e) -
+// psi(x - e) whose +e_y / -e_y partners are added as a pair, and sx, sy are formed
+// in the same order with the roles of x and y swapped, so that mirrored or
+// transposed neighbourhoods give mirrored or swapped (sx, sy) exactly.
+__device__ __forceinline__ void force_stencil_mr(const float (&P)[5][5], const StepConst& k, float& Fx,
+                                                 float& Fy, float& Fs2)
+{
+    constexpr float w1 = 4.0f / 21.0f, w2 = 4.0f / 45.0f, w4 = 1.0f / 60.0f, w5 = 2.0f / 315.0f,
+                    w8 = 1.0f / 5040.0f;
+    // (u, v) = (1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (2, 2): |e|^2 = 1, 2, 5, 4, 5, 8
+    const float dx10 = P[2][3] - P[2][1];
+    const float dy10 = P[3][2] - P[1][2];
+    const float dx11 = (P[3][3] - P[3][1]) + (P[1][3] - P[1][1]);
+    const float dy11 = (P[3][3] - P[1][3]) + (P[3][1] - P[1][1]);
+    const float dx12 = (P[4][3] - P[4][1]) + (P[0][3] - P[0][1]);
+    const float dy12 = (P[3][4] - P[1][4]) + (P[3][0] - P[1][0]);
+    const float dx20 = P[2][4] - P[2][0];
+    const float dy20 = P[4][2] - P[0][2];
+    const float dx21 = (P[3][4] - P[3][0]) + (P[1][4] - P[1][0]);
+    const float dy21 = (P[4][3] - P[0][3]) + (P[4][1] - P[0][1]);
+    const float dx22 = (P[4][4] - P[4][0]) + (P[0][4] - P[0][0]);
+    const float dy22 = (P[4][4] - P[0][4]) + (P[4][0] - P[0][0]);
+    // sum_e w(|e|^2) e_x psi(x + e): weight times |e_x| = u for each pair group
+    float sx = w1 * dx10;
+    sx = fmaf(w2, dx11, sx);
+    sx = fmaf(w5, dx12, sx);
+    sx = fmaf(2.0f * w4, dx20, sx);
+    sx = fmaf(2.0f * w5, dx21, sx);
+    sx = fmaf(2.0f * w8, dx22, sx);
+    float sy = w1 * dy10;
+    sy = fmaf(w2, dy11, sy);
+    sy = fmaf(w5, dy12, sy);
+    sy = fmaf(2.0f * w4, dy20, sy);
+    sy = fmaf(2.0f * w5, dy21, sy);
+    sy = fmaf(2.0f * w8, dy22, sy);
+    const float g = k.negG * P[2][2];
+    Fx = g * sx;
+    Fy = g * sy;
+    Fs2 = sx * sx + sy * sy;  // |F|^2 / psi^2 / G^2, as for the nearest-neighbour stencil
 }
 
 // MRT collision of Eq. (4) with the forcing of Eq. (25), applied as

@@ -34,6 +34,52 @@ constexpr short kPrioPrologue = 2;
 constexpr short kPrioPrefetch = 1;
 
 
+// rho and the Eq. (6) velocity of site (xci, y) into the [ny][nx] output fields.
+__device__ __forceinline__ void write_moments(const StepConst& k, int y, int xci, float r, float vx, float vy,
+                                              float* __restrict__ rho_out, float* __restrict__ ux_out,
+                                              float* __restrict__ uy_out)
+{
+    const long long o = (long long)y * k.nx + xci;
+    if (rho_out) rho_out[o] = r;
+    if (ux_out) ux_out[o] = vx;
+    if (uy_out) uy_out[o] = vy;
+}
+
+// FP64 diagnostics of one site: mass, momentum, pressure (Eq. 30 or the Eq. (23)
+// bulk pressure) and density sums over the two annuli, max |v|.
+__device__ __forceinline__ void diag_accumulate(const StepConst& k, const DiagConst& dg, int y, int xci, float r,
+                                                float vx, float vy, double acc[kDiagFields])
+{
+    const double rr = r;
+    const double pr = pressure_f64(rr, dg.psi);
+    acc[0] += rr;
+    acc[1] += rr * (double)vx;
+    acc[2] += rr * (double)vy;
+    double dx = fabs((double)xci - dg.in_cx);
+    dx = fmin(dx, (double)k.nx - dx);
+    double dy = fabs((double)y - dg.in_cy);
+    if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
+    double d = sqrt(dx * dx + dy * dy);
+    if (d >= dg.in_r0 && d < dg.in_r1) { acc[3] += pr; acc[5] += rr; acc[7] += 1.0; }
+    dx = fabs((double)xci - dg.out_cx);
+    dx = fmin(dx, (double)k.nx - dx);
+    dy = fabs((double)y - dg.out_cy);
+    if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
+    d = sqrt(dx * dx + dy * dy);
+    if (d >= dg.out_r0 && d < dg.out_r1) { acc[4] += pr; acc[6] += rr; acc[8] += 1.0; }
+    acc[9] = fmax(acc[9], (double)sqrtf(vx * vx + vy * vy));
+}
+
+// Wave-reduce the per-lane diagnostics and write the wave's partial for `tile`.
+__device__ __forceinline__ void diag_write(double acc[kDiagFields], int lane, int tile, double* __restrict__ partial)
+{
+    for (int i = 0; i < 9; ++i) acc[i] = wave_sum(acc[i]);
+    acc[9] = wave_max(acc[9]);
+    if (lane == 0) {
+        for (int i = 0; i < kDiagFields; ++i) partial[(long long)tile * kDiagFields + i] = acc[i];
+    }
+}
+
 // One wavefront walks the rows of its strip in direction DIR (+1: y0 up to
 // y1 - 1; -1: y1 - 1 down to y0).  Every row is pulled and reduced to density and
 // psi once; the force at a row needs psi of the rows on both sides, so the walk
@@ -173,33 +219,9 @@ __device__ __forceinline__ void strip_walk(
                 C::store_density(out, k, xc, r);
             }
         } else if (MODE == kModeMoments) {
-            if (live) {
-                const long long o = (long long)y * k.nx + xci;
-                if (rho_out) rho_out[o] = r;
-                if (ux_out) ux_out[o] = vx;
-                if (uy_out) uy_out[o] = vy;
-            }
+            if (live) write_moments(k, y, xci, r, vx, vy, rho_out, ux_out, uy_out);
         } else {
-            if (live) {
-                const double rr = r;
-                const double pr = pressure_f64(rr, dg.psi);
-                acc[0] += rr;
-                acc[1] += rr * (double)vx;
-                acc[2] += rr * (double)vy;
-                double dx = fabs((double)xci - dg.in_cx);
-                dx = fmin(dx, (double)k.nx - dx);
-                double dy = fabs((double)y - dg.in_cy);
-                if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
-                double d = sqrt(dx * dx + dy * dy);
-                if (d >= dg.in_r0 && d < dg.in_r1) { acc[3] += pr; acc[5] += rr; acc[7] += 1.0; }
-                dx = fabs((double)xci - dg.out_cx);
-                dx = fmin(dx, (double)k.nx - dx);
-                dy = fabs((double)y - dg.out_cy);
-                if (dg.periodic_y) dy = fmin(dy, (double)k.ny - dy);
-                d = sqrt(dx * dx + dy * dy);
-                if (d >= dg.out_r0 && d < dg.out_r1) { acc[4] += pr; acc[6] += rr; acc[8] += 1.0; }
-                acc[9] = fmax(acc[9], (double)sqrtf(vx * vx + vy * vy));
-            }
+            if (live) diag_accumulate(k, dg, y, xci, r, vx, vy, acc);
         }
     };
 
@@ -211,13 +233,7 @@ __device__ __forceinline__ void strip_walk(
         row(i + 2, fc, fa, fb, rc, ra, wc, wa, wb, ic, ia, ib);
     }
 
-    if (MODE == kModeDiag) {
-        for (int i = 0; i < 9; ++i) acc[i] = wave_sum(acc[i]);
-        acc[9] = wave_max(acc[9]);
-        if (lane == 0) {
-            for (int i = 0; i < kDiagFields; ++i) partial[(long long)tile * kDiagFields + i] = acc[i];
-        }
-    }
+    if (MODE == kModeDiag) diag_write(acc, lane, tile, partial);
     if (bad) flag[0] = kFlagUnstable;  // vector store from any flagging lane; all write the same value
 }
 
@@ -604,6 +620,138 @@ __attribute__((amdgpu_waves_per_eu(1))) void d2q9_pair(
     pair_tile<WALLS, PSI>(fin, fout, k, tile, lane, flag);
 }
 
+// ---------------------------------------------------------------- 24-site stencil
+// Time step, moments or diagnostics with the interaction stencil of nearest and
+// next-nearest neighbours (FP32 storage).  One wavefront walks a strip of 60 output
+// columns (lanes 2..61; lanes 0, 1, 62, 63 are psi halo columns) and strip_rows rows,
+// keeping the pulled populations of rows y, y+1, y+2 (and y+3 in flight) and the psi
+// windows of rows y-2 .. y+2 in registers; x-neighbours at distance 1 and 2 come from
+// lane shuffles.  Rows beyond a wall take psi of the nearest fluid row (they are
+// pulled as that row).  The walk shifts its row buffers by one row per step (register
+// moves), and the prefetch of row y+3 overlaps the collision of row y.
+template <bool WALLS, int MODE, int PSI>
+__device__ __forceinline__ void mr_walk(const float* __restrict__ fin, float* __restrict__ fout,
+                                        const StepConst& k, const int tile, const int lane, const int ty,
+                                        const bool live, const int xci, const unsigned xm, const unsigned xc,
+                                        const unsigned xp, int* __restrict__ flag, float* __restrict__ rho_out,
+                                        float* __restrict__ ux_out, float* __restrict__ uy_out, const DiagConst& dg,
+                                        double* __restrict__ partial)
+{
+    const int y0 = ty * k.strip_rows;
+    const int y1 = min(y0 + k.strip_rows, k.ny);
+    const int n = y1 - y0;
+    // the lattice row that supplies row y: wrapped (periodic) or clamped (walls)
+    auto src = [&](int y) __attribute__((always_inline)) {
+        if (WALLS) return y < 0 ? 0 : (y >= k.ny ? k.ny - 1 : y);
+        return y < 0 ? y + k.ny : (y >= k.ny ? y - k.ny : y);
+    };
+    bool bad = false;
+    // psi window of one row: columns x-2 .. x+2
+    auto window = [&](float v, float (&w)[5]) __attribute__((always_inline)) {
+        w[0] = __shfl_up(v, 2, kWave);
+        w[1] = __shfl_up(v, 1, kWave);
+        w[2] = v;
+        w[3] = __shfl_down(v, 1, kWave);
+        w[4] = __shfl_down(v, 2, kWave);
+    };
+    float f0[9], f1[9], f2[9], f3[9];
+    float P[5][5];
+    float r0, r1, r2;
+    // rows y0-2, y0-1: psi only
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        pull_row<kStoreF32, WALLS>(fin, k, src(y0 - 2 + j), xm, xc, xp, f3);
+        window(pseudopotential<PSI>(density(f3), k, bad), P[j]);
+    }
+    pull_row<kStoreF32, WALLS>(fin, k, src(y0), xm, xc, xp, f0);
+    pull_row<kStoreF32, WALLS>(fin, k, src(y0 + 1), xm, xc, xp, f1);
+    pull_row<kStoreF32, WALLS>(fin, k, src(y0 + 2), xm, xc, xp, f2);
+    r0 = density(f0);
+    r1 = density(f1);
+    r2 = density(f2);
+    window(pseudopotential<PSI>(r0, k, bad), P[2]);
+    window(pseudopotential<PSI>(r1, k, bad), P[3]);
+    window(pseudopotential<PSI>(r2, k, bad), P[4]);
+
+    double acc[kDiagFields];
+    if (MODE == kModeDiag) {
+        for (int i = 0; i < kDiagFields; ++i) acc[i] = 0.0;
+    }
+    for (int i = 0; i < n; ++i) {
+        const int y = y0 + i;
+        // psi of row y + 3 is needed by the next row of the strip
+        const bool more = i + 1 < n;
+        if (more) pull_row<kStoreF32, WALLS>(fin, k, src(y + 3), xm, xc, xp, f3);
+        float Fx, Fy, Fs2;
+        force_stencil_mr(P, k, Fx, Fy, Fs2);
+        const float jx = (f0[1] - f0[3]) + ((f0[5] - f0[7]) + (f0[8] - f0[6]));
+        const float jy = (f0[2] - f0[4]) + ((f0[5] - f0[7]) + (f0[6] - f0[8]));
+        const float inv_rho = recip(r0);
+        const float vx = fmaf(0.5f, Fx, jx) * inv_rho;
+        const float vy = fmaf(0.5f, Fy, jy) * inv_rho;
+        if (MODE == kModeStep) {
+            collide(f0, r0, vx, vy, Fx, Fy, Fs2, k);
+            if (live) {
+                float* out = fout + (long long)y * k.row_stride;
+#pragma unroll
+                for (int a = 0; a < 9; ++a) Codec<kStoreF32>::store(out, k, a, xc, f0[a], 0.0f);
+            }
+        } else if (MODE == kModeMoments) {
+            if (live) write_moments(k, y, xci, r0, vx, vy, rho_out, ux_out, uy_out);
+        } else {
+            if (live) diag_accumulate(k, dg, y, xci, r0, vx, vy, acc);
+        }
+        // slide the row buffers and psi windows down by one row
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            f0[a] = f1[a];
+            f1[a] = f2[a];
+        }
+        r0 = r1;
+        r1 = r2;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) P[j][c] = P[j + 1][c];
+        if (more) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) f2[a] = f3[a];
+            r2 = density(f2);
+            window(pseudopotential<PSI>(r2, k, bad), P[4]);
+        }
+    }
+    if (MODE == kModeDiag) diag_write(acc, lane, tile, partial);
+    if (bad) flag[0] = kFlagUnstable;
+}
+
+template <bool WALLS, int MODE, int PSI>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void d2q9_mr(
+    const float* __restrict__ fin, float* __restrict__ fout, StepConst k, int* __restrict__ flag,
+    float* __restrict__ rho_out, float* __restrict__ ux_out, float* __restrict__ uy_out, DiagConst dg,
+    double* __restrict__ partial)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = logical_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+    if (tile >= k.tiles_x * k.tiles_y) return;  // whole wavefront leaves together
+    // tiles in bands of `band` strips, as strip_tile (k.tiles_x counts 60-column tiles)
+    const int band0 = (tile / (k.tiles_x * k.band)) * k.band;
+    const int band_h = min(k.band, k.tiles_y - band0);
+    const int r = tile - band0 * k.tiles_x;
+    const int tx = r / band_h;
+    const int ty = band0 + r % band_h;
+    // column of this lane; lanes 0, 1, 62, 63 are the psi halo; columns wrap in x
+    const int xs = tx * kMrTileW - 2 + lane;
+    const bool live = (lane >= 2) && (lane < kMrTileW + 2) && (xs < k.nx);
+    int xci = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
+    if (xs > k.nx + 1) xci = 0;  // beyond the right halo: in-range dummy column, never stored
+    const unsigned xc = (unsigned)xci * 4u;
+    const unsigned xm = (unsigned)((xci == 0) ? k.nx - 1 : xci - 1) * 4u;
+    const unsigned xp = (unsigned)((xci == k.nx - 1) ? 0 : xci + 1) * 4u;
+    mr_walk<WALLS, MODE, PSI>(fin, fout, k, tile, lane, ty, live, xci, xm, xc, xp, flag, rho_out, ux_out, uy_out, dg,
+                              partial);
+}
+
 // Persistent multi-instance step: one workgroup owns one lattice and advances
 // it `steps` time steps; its kBatchWaves wavefronts share the strips of each step and
 // meet at a workgroup barrier between steps (the barrier orders the global
@@ -713,7 +861,7 @@ __global__ __launch_bounds__(256) void diag_finalize(const double* __restrict__ 
 // f_eq = M^-1 m_eq(rho, u) of Eq. (3), i.e. w_a rho (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u^2),
 // evaluated in FP64 and rounded once, so that the stored values sum to rho0 to
 // within the rounding of each population.
-template <int S, bool WALLS>
+template <int S, bool WALLS, int REACH>
 __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
                                                  const float* __restrict__ ux0,
                                                  const float* __restrict__ uy0,
@@ -741,24 +889,28 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
         }
         if (bad) flag[0] = kFlagBadInput;
     }
-    // psi (FP64, Eq. (24) or Eq. (23)) on the 5 x 5 block around (x, y): the force
-    // of Eq. (7) at the nine sites this one pulls from.  Rows beyond a wall take the adjacent
-    // fluid row; they are read only by sites inside the lattice.
-    double psi[5][5];
+    // psi (FP64, Eq. (24) or Eq. (23)) on the block of half-width REACH + 1 around
+    // (x, y): the force of Eq. (7) at the nine sites this one pulls from, for a stencil
+    // of reach REACH.  Rows beyond a wall take the nearest fluid row; they are read only
+    // by sites inside the lattice.
+    constexpr int HB = REACH + 1, NB = 2 * HB + 1;
+    double psi[NB][NB];
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        int yy = y + j - 2;
+    for (int j = 0; j < NB; ++j) {
+        int yy = y + j - HB;
         if (WALLS) yy = yy < 0 ? 0 : (yy >= k.ny ? k.ny - 1 : yy);
-        else yy = yy < 0 ? yy + k.ny : (yy >= k.ny ? yy - k.ny : yy);
+        else yy = ((yy % k.ny) + k.ny) % k.ny;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            int xx = x + i - 2;
-            xx = xx < 0 ? xx + k.nx : (xx >= k.nx ? xx - k.nx : xx);
+        for (int i = 0; i < NB; ++i) {
+            const int xx = ((x + i - HB) % k.nx + k.nx) % k.nx;
             const double r = rho0[(long long)yy * k.nx + xx];
             psi[j][i] = sqrt(psi2_f64(r, ic.psi));
         }
     }
-#pragma unroll
+    // (the nine upstream forces are unrolled for the nearest-neighbour stencil only: the
+    // 24-site stencil's fully unrolled block is large enough to crash the instruction
+    // scheduler, and this kernel runs once per lattice)
+#pragma unroll(REACH == 1 ? 9 : 1)
     for (int b = 0; b < 9; ++b) {
         // pre-streamed: slot b of (x, y) holds what the first pull of direction b
         // reads, the equilibrium of the upstream site (or of this site's
@@ -773,16 +925,23 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
         if (WALLS) ys = y + dy;
         int xs = x + dx;
         xs = xs < 0 ? xs + k.nx : (xs >= k.nx ? xs - k.nx : xs);
-        // Eq. (7) at the upstream site
+        // Eq. (7) at the upstream site: the nearest-neighbour weights 1/3, 1/12, or the
+        // 24-site weights 4/21, 4/45, 1/60, 2/315, 1/5040 by |e|^2 = 1, 2, 4, 5, 8
         double sx = 0.0, sy = 0.0;
 #pragma unroll
-        for (int c = 1; c < 9; ++c) {
-            const double w = c < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
-            const double ps = psi[2 + dy + EY[c]][2 + dx + EX[c]];
-            sx += w * ps * EX[c];
-            sy += w * ps * EY[c];
-        }
-        const double pc = psi[2 + dy][2 + dx];
+        for (int ey = -REACH; ey <= REACH; ++ey)
+#pragma unroll
+            for (int ex = -REACH; ex <= REACH; ++ex) {
+                const int q = ex * ex + ey * ey;
+                double w = 0.0;
+                if (REACH == 1) w = q == 1 ? 1.0 / 3.0 : (q == 2 ? 1.0 / 12.0 : 0.0);
+                else w = q == 1 ? 4.0 / 21.0 : q == 2 ? 4.0 / 45.0 : q == 4 ? 1.0 / 60.0 : q == 5 ? 2.0 / 315.0
+                       : q == 8 ? 1.0 / 5040.0 : 0.0;
+                const double ps = psi[HB + dy + ey][HB + dx + ex];
+                sx += w * ps * ex;
+                sy += w * ps * ey;
+            }
+        const double pc = psi[HB + dy][HB + dx];
         const double Fx = -ic.psi.G * pc * sx, Fy = -ic.psi.G * pc * sy;
         const long long i = (long long)ys * k.nx + xs;
         const double r = rho0[i];
@@ -938,9 +1097,33 @@ int pair_blocks_per_cu(bool walls)
     return e == hipSuccess ? nb : 0;
 }
 
+// The 24-site stencil (FP32 storage; the host validates that): step, moments or
+// diagnostics by MODE.  k.tiles_x counts 60-column tiles.
+template <int MODE>
+static hipError_t launch_mr(bool walls, const void* fin, void* fout, const StepConst& k, int* flag, float* rho,
+                            float* ux, float* uy, const DiagConst& dg, double* partial, hipStream_t s)
+{
+    const dim3 grid(strip_blocks(k, kWavesPerBlock)), block(kWave * kWavesPerBlock);
+    const float* in = static_cast<const float*>(fin);
+    float* out = static_cast<float*>(fout);
+#define LBMP_MR(W_, P_)                                                                            \
+    hipLaunchKernelGGL((d2q9_mr<W_, MODE, P_>), grid, block, 0, s, in, out, k, flag, rho, ux, uy, dg, partial)
+    if (walls) {
+        if (k.psi_form == kPsiSS) LBMP_MR(true, kPsiSS); else LBMP_MR(true, kPsiCS);
+    } else {
+        if (k.psi_form == kPsiSS) LBMP_MR(false, kPsiSS); else LBMP_MR(false, kPsiCS);
+    }
+#undef LBMP_MR
+    return hipGetLastError();
+}
+
 hipError_t launch_step(int store, bool walls, const void* fin, void* fout, const StepConst& k,
                        int* flag, hipStream_t s)
 {
+    if (k.stencil == kStencilMultirange) {
+        if (store != kStoreF32) return hipErrorInvalidValue;
+        return launch_mr<kModeStep>(walls, fin, fout, k, flag, nullptr, nullptr, nullptr, DiagConst{}, nullptr, s);
+    }
     if (pair_step(store, k.nx)) {
         if (walls)
             return k.psi_form == kPsiSS ? launch_pair_psi<true, kPsiSS>(fin, fout, k, flag, s)
@@ -1024,14 +1207,23 @@ hipError_t launch_moments(int store, bool walls, const void* fin, const StepCons
                           float* rho, float* ux, float* uy, hipStream_t s)
 {
     DiagConst dg{};
+    if (k.stencil == kStencilMultirange) {
+        if (store != kStoreF32) return hipErrorInvalidValue;
+        return launch_mr<kModeMoments>(walls, fin, nullptr, k, flag, rho, ux, uy, dg, nullptr, s);
+    }
     return dispatch<kModeMoments>(store, walls, fin, nullptr, k, flag, rho, ux, uy, dg, nullptr, s);
 }
 
 hipError_t launch_diag(int store, bool walls, const void* fin, const StepConst& k, int* flag,
                        const DiagConst& dg, double* partial, double* out, hipStream_t s)
 {
-    hipError_t e = dispatch<kModeDiag>(store, walls, fin, nullptr, k, flag, nullptr, nullptr,
-                                       nullptr, dg, partial, s);
+    hipError_t e = hipSuccess;
+    if (k.stencil == kStencilMultirange)
+        e = store == kStoreF32 ? launch_mr<kModeDiag>(walls, fin, nullptr, k, flag, nullptr, nullptr, nullptr, dg,
+                                                      partial, s)
+                               : hipErrorInvalidValue;
+    else
+        e = dispatch<kModeDiag>(store, walls, fin, nullptr, k, flag, nullptr, nullptr, nullptr, dg, partial, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(diag_finalize, dim3(1), dim3(256), 0, s, partial, k.tiles_x * k.tiles_y, out);
     return hipGetLastError();
@@ -1043,8 +1235,14 @@ hipError_t launch_init(int store, bool walls, const float* rho0, const float* ux
 {
     dim3 grid((k.nx + 255) / 256, k.ny), block(256);
 #define LBMP_INIT(S_, W_)                                                                          \
-    hipLaunchKernelGGL((d2q9_init<S_, W_>), grid, block, 0, s, rho0, ux0, uy0,                     \
-                       static_cast<typename Codec<S_>::T*>(fout), k, ic, flag)
+    do {                                                                                           \
+        if (k.stencil == kStencilMultirange)                                                       \
+            hipLaunchKernelGGL((d2q9_init<S_, W_, 2>), grid, block, 0, s, rho0, ux0, uy0,          \
+                               static_cast<typename Codec<S_>::T*>(fout), k, ic, flag);            \
+        else                                                                                       \
+            hipLaunchKernelGGL((d2q9_init<S_, W_, 1>), grid, block, 0, s, rho0, ux0, uy0,          \
+                               static_cast<typename Codec<S_>::T*>(fout), k, ic, flag);            \
+    } while (0)
     switch (store) {
     case kStoreF32: if (walls) LBMP_INIT(kStoreF32, true); else LBMP_INIT(kStoreF32, false); break;
     case kStoreF16: if (walls) LBMP_INIT(kStoreF16, true); else LBMP_INIT(kStoreF16, false); break;

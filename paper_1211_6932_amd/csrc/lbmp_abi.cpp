@@ -70,6 +70,9 @@ size_t density_plane_bytes(int store)
 // encodings round to an even count so that their FP32 density row stays 4-byte aligned.
 int pitch_of(int nx, int store) { return local_density(store) ? (nx + 1) / 2 * 2 : nx; }
 
+// Output columns per wavefront strip of the one-column kernels for this stencil.
+int tile_width(const lb_params& p) { return p.stencil == LB_STENCIL_MULTIRANGE ? lbmp::kMrTileW : lbmp::kTileW; }
+
 struct Layout {
     size_t flag_off, dout_off, partial_off, f_off[2], total, buf_bytes;
     int diag_tiles;
@@ -80,7 +83,8 @@ Layout layout_of(const lb_params& p)
     Layout L{};
     const int pitch = pitch_of(p.nx, p.store);
     L.buf_bytes = align_up((size_t)row_slots(p.store) * p.ny * pitch * elem_bytes(p.store), kAlign);
-    const int tx = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
+    const int tw = tile_width(p);
+    const int tx = (p.nx + tw - 1) / tw;
     const int ty = (p.ny + kDiagStripRows - 1) / kDiagStripRows;
     L.diag_tiles = tx * ty;
     L.flag_off = 0;
@@ -111,6 +115,10 @@ lb_status validate(const lb_params* p)
     if ((long long)pitch_of(p->nx, p->store) * row_slots(p->store) * (p->store == LB_STORE_F32 ? 4 : 2) >= (1LL << 32))
         return fail(LB_EINVAL, "a lattice row must stay below 4 GiB");
     if (p->bc != LB_BC_PERIODIC && p->bc != LB_BC_WALLS_Y) return fail(LB_EINVAL, "unknown bc");
+    if (p->stencil != LB_STENCIL_NEAREST && p->stencil != LB_STENCIL_MULTIRANGE)
+        return fail(LB_EINVAL, "unknown stencil");
+    if (p->stencil == LB_STENCIL_MULTIRANGE && p->store != LB_STORE_F32)
+        return fail(LB_EINVAL, "the 24-site stencil runs with LB_STORE_F32 only");
     if (p->store < LB_STORE_F32 || p->store > LB_STORE_F16_DEST) return fail(LB_EINVAL, "unknown store");
     if (!finite_all({p->a, p->b, p->R, p->T, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta, p->s_j,
                      p->s_q, p->nu_l, p->nu_g, p->rho_switch, p->rho_ref, p->psi_eps}))
@@ -148,7 +156,7 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
     k.pitch = pitch_of(p.nx, p.store);
     k.strip_rows = strip_rows;
     k.band = band;
-    k.tiles_x = (p.nx + lbmp::kTileW - 1) / lbmp::kTileW;
+    k.tiles_x = (p.nx + tile_width(p) - 1) / tile_width(p);
     k.tiles_y = (p.ny + strip_rows - 1) / strip_rows;
     k.row_stride = (long long)row_slots(p.store) * k.pitch;
     k.b4 = (float)(p.b / 4.0);
@@ -172,6 +180,7 @@ lbmp::StepConst derive(const lb_params& p, int strip_rows, int band = 1)
     k.c_e = (float)(12.0 * p.sigma * G2 * p.s_e / 36.0);
     k.c_z = (float)(12.0 * p.sigma * G2 * p.s_zeta / 36.0);
     k.psi_form = p.psi_form;
+    k.stencil = p.stencil;
     k.psi_eps = (float)p.psi_eps;
     k.inv_psi_eps = p.psi_eps > 0.0 ? (float)(1.0 / p.psi_eps) : 0.0f;
     static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
@@ -196,7 +205,9 @@ int auto_strip_rows(const lb_params& p)
     // destination-scaled one with one column per lane, 5 for the latter with two
     const bool pair = lbmp::pair_step(p.store, p.nx);
     int preferred = kMinStripRows;
-    if (pair)
+    if (p.stencil == LB_STENCIL_MULTIRANGE)
+        preferred = 8;  // two halo rows a side: taller strips pull fewer extra rows
+    else if (pair)
         preferred = 5;
     else if (p.store == LB_STORE_F16_DEST || p.store == LB_STORE_F16_OFFSET || p.store == LB_STORE_BF16_OFFSET)
         preferred = 8;
@@ -786,6 +797,8 @@ lb_status validate_batch(const lb_params* p, int32_t n)
         if (st != LB_OK) return fail(st, "lattice " + std::to_string(i) + ": " + g_last_error);
         if (p[i].store != p[0].store || p[i].bc != p[0].bc || p[i].psi_form != p[0].psi_form)
             return fail(LB_EINVAL, "all lattices of a batch share store, bc and psi_form");
+        if (p[i].stencil != LB_STENCIL_NEAREST)
+            return fail(LB_EINVAL, "batched lattices use the nearest-neighbour stencil");
     }
     if (p[0].store != LB_STORE_F32 && p[0].store != LB_STORE_F16_LOCAL && p[0].store != LB_STORE_F16_DEST)
         return fail(LB_EINVAL, "batched storage must be LB_STORE_F32, LB_STORE_F16_LOCAL or LB_STORE_F16_DEST");

@@ -21,6 +21,7 @@ LB_BC_PERIODIC, LB_BC_WALLS_Y = 0, 1
 LB_STORE_F32, LB_STORE_F16_OFFSET, LB_STORE_BF16_OFFSET = 0, 1, 2
 LB_STORE_F16_LOCAL, LB_STORE_BF16_LOCAL, LB_STORE_F16_DEST = 3, 4, 5
 LB_PSI_CS, LB_PSI_SS = 0, 1
+LB_STENCIL_NEAREST, LB_STENCIL_MULTIRANGE = 0, 1
 STORE_NAMES = {"f32": LB_STORE_F32, "f16": LB_STORE_F16_OFFSET, "bf16": LB_STORE_BF16_OFFSET,
                "f16local": LB_STORE_F16_LOCAL, "bf16local": LB_STORE_BF16_LOCAL, "f16dest": LB_STORE_F16_DEST}
 STATUS_NAMES = {0: "LB_OK", -1: "LB_EINVAL", -2: "LB_ENOMEM", -3: "LB_EHIP", -4: "LB_EUNSTABLE",
@@ -36,7 +37,7 @@ class lb_params(ctypes.Structure):
         ("s_j", ctypes.c_double), ("s_q", ctypes.c_double),
         ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("rho_switch", ctypes.c_double),
         ("rho_ref", ctypes.c_double),
-        ("psi_form", ctypes.c_int32), ("reserved_", ctypes.c_int32), ("psi_eps", ctypes.c_double),
+        ("psi_form", ctypes.c_int32), ("stencil", ctypes.c_int32), ("psi_eps", ctypes.c_double),
     ]
 
 
@@ -188,8 +189,8 @@ def make_params(d: dict, store="f32", rho_ref=0.0) -> lb_params:
                      float(d["a"]), float(d["b"]), float(d["R"]), float(d["T"]), float(d["G"]),
                      float(d["sigma"]), float(d["s_rho"]), float(d["s_e"]), float(d["s_zeta"]),
                      float(d["s_j"]), float(d["s_q"]), float(d["nu_l"]), float(d["nu_g"]),
-                     float(d["rho_switch"]), float(rho_ref), int(d.get("psi_form", 0)), 0,
-                     float(d.get("psi_eps", 0.0)))
+                     float(d["rho_switch"]), float(rho_ref), int(d.get("psi_form", 0)),
+                     int(d.get("stencil", 0)), float(d.get("psi_eps", 0.0)))
 
 
 # -------------------------------------------------------------- C names (marshalling only)

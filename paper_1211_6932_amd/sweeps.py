@@ -18,7 +18,9 @@ Readings: the coexistence densities of a droplet run are its inner and outer
 mean densities (the droplet's Laplace pressure shifts them slightly from a flat
 interface's); a run "survives" if no site is flagged unstable (non-finite
 density, b rho / 4 >= 1 or psi^2 <= 0) in `steps` steps; the spurious velocity is
-the maximum speed over the lattice, averaged over the window.
+the maximum speed over the lattice, averaged over the window.  The viscosity search
+(Fig. 4) also applies a stricter criterion: a run fails once its maximum speed exceeds
+the lattice speed of sound.
 """
 from __future__ import annotations
 
@@ -76,9 +78,16 @@ def lowest_stable(results):
     return low
 
 
-def survival(ws, steps, every=500):
-    """Advance runs `ws` (with initial velocities) together; return the step at which
-    each first flagged an unstable site (None = survived `steps`)."""
+CS = 1.0 / math.sqrt(3.0)  # lattice speed of sound
+
+
+def survival(ws, steps, every=100, u_limit=CS):
+    """Advance runs `ws` (with initial velocities) together, checking every `every`
+    steps.  Returns two lists: the step at which each run first flagged an unstable
+    site (a non-finite density, b rho/4 >= 1 or psi^2 <= 0), and the step at which it
+    first failed the stricter criterion, that or a maximum speed above `u_limit` (the
+    speed of sound by default: the flow is then no longer a low-Mach-number flow the
+    method models, whether or not the densities stay in range).  None = survived."""
     import torch
 
     def f(a):
@@ -89,6 +98,7 @@ def survival(ws, steps, every=500):
                    [f(w.uy0) for w in ws] if has_u else None)
     dummy = [(0.0, 0.0, 0.0, 1.0)] * len(ws)
     failed = [None] * len(ws)
+    failed_u = [None] * len(ws)
     done = 0
     while done < steps:
         n = min(every, steps - done)
@@ -97,8 +107,10 @@ def survival(ws, steps, every=500):
         for i, d in enumerate(b.diagnostics_all(dummy, dummy)):
             if d["unstable"] and failed[i] is None:
                 failed[i] = done
+            if failed_u[i] is None and (d["unstable"] or not d["max_u"] <= u_limit):
+                failed_u[i] = done
     b.close()
-    return failed
+    return failed, failed_u
 
 
 def lowest_stable_viscosity(nus, failed):

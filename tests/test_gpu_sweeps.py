@@ -134,12 +134,14 @@ def test_lowest_liquid_viscosity_falls_with_the_viscosity_ratio():
     ratios = (1, 20, 50)
     ws = [W.paper_splash(nu, r) for r in ratios for nu in nus]
     print(f"[gpu-case] viscosity-ratio stability search, {len(ws)} splash runs 600x250", flush=True)
-    failed = S.survival(ws, 4000)
-    low = {}
+    failed, failed_u = S.survival(ws, 4000)
+    low, low_u = {}, {}
     for k, r in enumerate(ratios):
         fl = failed[k * len(nus):(k + 1) * len(nus)]
+        fu = failed_u[k * len(nus):(k + 1) * len(nus)]
         low[r] = S.lowest_stable_viscosity(nus, fl)
-        print(f"nu_g/nu_l = {r}: lowest surviving nu_l {low[r]}, failures {fl}")
+        low_u[r] = S.lowest_stable_viscosity(nus, fu)
+        print(f"nu_g/nu_l = {r}: lowest nu_l {low[r]} (flag), {low_u[r]} (max|u| < c_s); failures {fl} / {fu}")
     assert low[1] is not None and low[1] <= 0.075
     assert low[20] is not None and low[20] <= 0.009
     assert low[20] < low[1] and low[50] is not None and low[50] <= low[20]
