@@ -98,6 +98,18 @@ size_t lbml_profile_scratch_bytes(int32_t ny);
 lb_status lbml_profile_extract(const float* rho, int32_t nx, int32_t ny, double cx, double cy, double R,
                                void* scratch, size_t scratch_bytes, float* logrho, void* stream);
 
+/* lbml_profile_extract without a scratch argument, for callers that cannot allocate
+ * device memory (code under graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  The row partials live in a static device array of the library,
+ * 3 x 2048 x 128 doubles (6 MiB, held by each GPU the library runs on until the process
+ * ends); ny > 2048 returns LB_EINVAL.  The call allocates nothing: its first call on a
+ * device looks up that device's copy of the array once.  Results are bitwise those of
+ * lbml_profile_extract.  Every call on one GPU shares the array: calls that overlap on
+ * one GPU (different streams or host threads) race and must be serialised by the caller.
+ * Asynchronous on `stream`. */
+lb_status lbml_profile_extract_noalloc(const float* rho, int32_t nx, int32_t ny, double cx, double cy, double R,
+                                       float* logrho, void* stream);
+
 /* lbml_profile_to_rho0: the field of a profile, into rho0 (device [ny][nx]
  * FP32).  Asynchronous on `stream`. */
 lb_status lbml_profile_to_rho0(const float* logrho, double R, double cx, double cy, int32_t nx, int32_t ny,

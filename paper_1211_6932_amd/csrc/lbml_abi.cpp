@@ -6,7 +6,6 @@
 #include <cmath>
 #include <cstdint>
 #include <new>
-#include <string>
 
 #include "lbml.h"
 #include "lbml_launch.hpp"
@@ -295,6 +294,20 @@ lb_status lbml_profile_extract(const float* rho, int32_t nx, int32_t ny, double 
     hipError_t e = lbml::launch_profile_extract(rho, nx, ny, cx, cy, R, static_cast<double*>(scratch), logrho,
                                                 static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_extract");
+}
+
+lb_status lbml_profile_extract_noalloc(const float* rho, int32_t nx, int32_t ny, double cx, double cy, double R,
+                                       float* logrho, void* stream)
+{
+    if (!rho || !logrho) return abi_fail(LB_EINVAL, "NULL argument");
+    if (nx < 2 || ny < 2 || nx > (1 << 20) || (long long)nx * ny > (1LL << 31))
+        return abi_fail(LB_EINVAL, "bad lattice size");
+    if (ny > lbml::static_profile_rows())
+        return abi_fail(LB_EINVAL, "ny exceeds the 2048 rows of the static profile scratch (use lbml_profile_extract)");
+    if (!std::isfinite(cx) || !std::isfinite(cy) || !std::isfinite(R) || R < 0.0 || R > 1e6)
+        return abi_fail(LB_EINVAL, "centre and radius must be finite, 0 <= R <= 1e6");
+    hipError_t e = lbml::launch_profile_extract_static(rho, nx, ny, cx, cy, R, logrho, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_extract_noalloc");
 }
 
 lb_status lbml_profile_to_rho0(const float* logrho, double R, double cx, double cy, int32_t nx, int32_t ny,

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "lbml_launch.hpp"
 
 namespace lbml {
@@ -405,6 +407,51 @@ hipError_t launch_profile_extract(const float* rho, int nx, int ny, double cx, d
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(profile_solve, dim3(1), dim3(kOut), 0, s, part, ny, logrho);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free profile fit: the [3][ny][128] FP64 row partials for
+// ny <= kStaticProfileRows.  Each GPU the library runs on holds its own copy until the
+// process ends.  In host code the name `scratch` is only a stand-in for the symbol:
+// its device address comes from hipGetSymbolAddress, once per device.
+constexpr int kStaticProfileRows = 2048;  // the limit lbml.h states for lbml_profile_extract_noalloc
+static __device__ __align__(256) double scratch[3 * kStaticProfileRows * kOut];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up with that device
+// current on the first call and kept per device.
+hipError_t static_profile_scratch(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+int static_profile_rows() { return kStaticProfileRows; }
+
+hipError_t launch_profile_extract_static(const float* rho, int nx, int ny, double cx, double cy, double R,
+                                         float* logrho, hipStream_t s)
+{
+    if (ny > kStaticProfileRows) return hipErrorInvalidValue;
+    double* part = nullptr;
+    const hipError_t e = static_profile_scratch(&part);
+    if (e != hipSuccess) return e;
+    // profile_rows writes every partial that profile_solve reads: nothing to clear
+    return launch_profile_extract(rho, nx, ny, cx, cy, R, part, logrho, s);
 }
 
 hipError_t launch_profile_to_rho0(const float* logrho, double R, double cx, double cy, int nx, int ny, float* rho0,

@@ -26,6 +26,11 @@ hipError_t launch_to_bf16(const float* src, __bf16* dst, int rows, int cols, int
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_profile_extract(const float* rho, int nx, int ny, double cx, double cy, double R, double* part,
                                   float* logrho, hipStream_t s);
+// The same fit with its row partials in the library's static device scratch (ny up to
+// static_profile_rows()); hipErrorInvalidValue for a larger ny.
+hipError_t launch_profile_extract_static(const float* rho, int nx, int ny, double cx, double cy, double R,
+                                         float* logrho, hipStream_t s);
+int static_profile_rows();
 hipError_t launch_profile_to_rho0(const float* logrho, double R, double cx, double cy, int nx, int ny, float* rho0,
                                   hipStream_t s);
 hipError_t launch_profile_to_rho0_mass(const float* logrho, double R, double cx, double cy, int nx, int ny,

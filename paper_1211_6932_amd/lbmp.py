@@ -69,6 +69,7 @@ EXPORTS = [
     "lbml_workspace_bytes", "lbml_init", "lbml_set_params", "lbml_get_params", "lbml_forward",
     "lbml_loss_grad", "lbml_adam", "lbml_train_step", "lbml_destroy", "lbml_profile_extract",
     "lbml_profile_to_rho0", "lbml_gemm_bf16", "lbml_profile_scratch_bytes", "lbml_profile_to_rho0_mass",
+    "lbml_profile_extract_noalloc",
 ]
 LBML_IN, LBML_HIDDEN, LBML_OUT, LBML_PARAMS = 4, 256, 128, 165760
 
@@ -157,6 +158,7 @@ def load():
         "lbml_destroy": ([vp], ctypes.c_int),
         "lbml_profile_scratch_bytes": ([i32], ctypes.c_size_t),
         "lbml_profile_extract": ([vp, i32, i32, f64, f64, f64, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
+        "lbml_profile_extract_noalloc": ([vp, i32, i32, f64, f64, f64, vp, vp], ctypes.c_int),
         "lbml_profile_to_rho0": ([vp, f64, f64, f64, i32, i32, vp, vp], ctypes.c_int),
         "lbml_profile_to_rho0_mass": ([vp, f64, f64, f64, i32, i32, f64, vp, vp, vp], ctypes.c_int),
         "lbml_gemm_bf16": ([vp, i64, i64, vp, i64, i64, vp, i32, i32, i32, i32, vp], ctypes.c_int),
@@ -397,6 +399,11 @@ def lbml_destroy(net):
 
 def lbml_profile_scratch_bytes(ny):
     return load().lbml_profile_scratch_bytes(int(ny))
+
+
+def lbml_profile_extract_noalloc(rho_ptr, nx, ny, cx, cy, R, logrho_ptr, stream):
+    return _check(load().lbml_profile_extract_noalloc(_vp(rho_ptr), int(nx), int(ny), float(cx), float(cy), float(R),
+                                                      _vp(logrho_ptr), _vp(stream)), "lbml_profile_extract_noalloc")
 
 
 def lbml_profile_extract(rho_ptr, nx, ny, cx, cy, R, scratch_ptr, scratch_bytes, logrho_ptr, stream):
