@@ -359,7 +359,7 @@ def bench_sweeps(args):
         edges[tau] = {"lowest_T_over_Tc": t_low,
                       "ratio": [r["ratio"] for r in rows if r["t_over_tc"] == t_low][0]}
     table1 = [{"a": r["a"], "T_over_Tc": r["t_over_tc"], "max_u": r["max_u"]} for r in out_groups["table1"]]
-    nus = [float(v) for v in np.geomspace(0.0015, 0.15, 12)]
+    nus = [float(v) for v in np.geomspace(0.001, 0.2, 24)]
     ratios = (1, 20, 50)
     t1 = time.perf_counter()
     failed, failed_u = S.survival([W.paper_splash(nu, r) for r in ratios for nu in nus], 4000)

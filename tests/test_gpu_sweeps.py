@@ -127,11 +127,17 @@ def test_original_scheme_step_matches_oracle():
 def test_lowest_liquid_viscosity_falls_with_the_viscosity_ratio():
     """Sec. IV.C, Fig. 4 (printed: nu_l ~ 0.075 at nu_g/nu_l = 1, 0.009 at 20, 0.0039 at
     50) on the paper's splash geometry (600 x 250, R = 50, U = 0.125, 4000 steps = five
-    impact times D/U).  This implementation survives lower viscosities than the figure
-    at every ratio (documented departure), so the checks are the trend and that the
-    printed values are reachable."""
-    nus = [float(v) for v in np.geomspace(0.0015, 0.15, 12)]
+    impact times D/U), checked every 100 steps, on 24 viscosities a factor 1.26 apart.
+    Two failure criteria: an unstable site (non-finite density or psi^2 <= 0), and that
+    or a maximum speed above the speed of sound.  Measured: both give the same lowest
+    viscosity at every ratio (a run that fails does so within 400-500 steps), 0.0040 /
+    0.0025 / 0.0013 at ratios 1 / 20 / 50, and the same over 16,000 steps.  Against the
+    figure that is 19 x lower at ratio 1 and 3.1-3.6 x lower at ratios 20 and 50, whose
+    ratio (2.0) is the figure's (2.3).  The departure is documented; the checks are those
+    numbers on this grid."""
+    nus = [float(v) for v in np.geomspace(0.001, 0.2, 24)]
     ratios = (1, 20, 50)
+    printed = {1: 0.075, 20: 0.009, 50: 0.0039}
     ws = [W.paper_splash(nu, r) for r in ratios for nu in nus]
     print(f"[gpu-case] viscosity-ratio stability search, {len(ws)} splash runs 600x250", flush=True)
     failed, failed_u = S.survival(ws, 4000)
@@ -142,6 +148,11 @@ def test_lowest_liquid_viscosity_falls_with_the_viscosity_ratio():
         low[r] = S.lowest_stable_viscosity(nus, fl)
         low_u[r] = S.lowest_stable_viscosity(nus, fu)
         print(f"nu_g/nu_l = {r}: lowest nu_l {low[r]} (flag), {low_u[r]} (max|u| < c_s); failures {fl} / {fu}")
-    assert low[1] is not None and low[1] <= 0.075
-    assert low[20] is not None and low[20] <= 0.009
-    assert low[20] < low[1] and low[50] is not None and low[50] <= low[20]
+    assert low == low_u  # the speed criterion moves no threshold
+    assert low[1] > low[20] > low[50]
+    for r in (20, 50):  # 3.1-3.6 x below the figure
+        assert 2.5 <= printed[r] / low[r] <= 5.0, (r, low[r])
+    assert 1.5 <= low[20] / low[50] <= 3.0  # the figure: 2.3
+    assert printed[1] / low[1] >= 10  # the departure at equal viscosities (measured 19 x)
+    # at ratio 50 the most viscous liquids fail too (nu_g = 50 nu_l >~ 3 makes s_nu small)
+    assert failed[3 * len(nus) - 1] is not None
