@@ -26,11 +26,13 @@ give the p50 / p99 per-lattice completion times.
 
 The learned workload runs the droplet-initialiser protocol: 4096 tanh-started
 droplets on 256 x 256 lattices (seed 1212) relax for 30,000 steps; the network
-trains on their least-squares profiles on the device; 256 held-out droplets
-(seed 1213) start from tanh and from the network and run 30,000 steps together.
-The value is the median per-droplet ratio of steps to spurious-current
-convergence (tanh / learned); the strict variant (pressure jump within 1 % as
-well) and the final-state errors are reported beside it.
+trains on their least-squares profiles on the device and the FP64 level model on
+their interior levels; 256 held-out droplets (seed 1213) start from tanh, from the
+anchored prediction and from the network alone, and run 30,000 steps together.
+The value is the median per-droplet ratio of steps to convergence (tanh / learned),
+convergence meaning max|u| within 5 % and the pressure jump within 1 % of the tanh
+run's final values; the max|u|-only ratio, the network-only arm and the final-state
+errors are reported beside it.
 """
 from __future__ import annotations
 
@@ -291,26 +293,27 @@ def bench_learned(args):
     X, base, T, kept = I.generate(train_ws, args.relax_steps, every=1000, log=log)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    net, losses = I.train(X, base, T, steps=args.train_steps, log=log)
+    model, losses = I.train(X, base, T, steps=args.train_steps, log=log)
     t_train = time.perf_counter() - t0
     eval_ws = W.learned_eval_instances(n=args.eval_droplets, side=256)
     t0 = time.perf_counter()
-    res, _ = I.evaluate(net, eval_ws, steps=args.relax_steps, every=50, log=log)
+    res, _ = I.evaluate(model, eval_ws, steps=args.relax_steps, every=50, log=log, ablation=True)
     t_eval = time.perf_counter() - t0
-    net.close()
+    model.close()
     u, strict = res["summary"]["u"], res["summary"]["strict"]
     gen_gbps = BYTES_PER_SITE["f32"] * sites * args.relax_steps / t_gen / 1e9
     out = {
-        "metric": "steps to spurious-current convergence, tanh start / learned start (median per droplet)",
-        "value": round(u.get("median_ratio", float("nan")), 3), "unit": "x", "n_gpus": 1,
+        "metric": "steps to convergence (max|u| within 5 % and pressure jump within 1 % of the tanh run's "
+                  "final values), tanh start / learned start, median per droplet",
+        "value": round(strict.get("median_ratio", float("nan")), 3), "unit": "x", "n_gpus": 1,
         "steps": args.relax_steps, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network (f32 accumulate), f32 lattice",
         "data": "synthetic",
         "config": {"workload": f"learned droplet initialiser: {args.train_runs} training runs and "
                                f"{args.eval_droplets} held-out droplets on 256x256, {args.relax_steps} steps",
                    "parallelism": "single GPU"},
-        "spurious_current": u, "strict": strict,
-        "ratio_of_medians": round(u.get("ratio_of_medians", float("nan")), 3),
+        "strict": strict, "ratio_of_medians": round(strict.get("ratio_of_medians", float("nan")), 3),
+        "spurious_current_only": u, "network_only": res["network_only"],
         "wall_seconds": {"training_runs": round(t_gen, 2), "training": round(t_train, 2),
                          "inference_and_placement": round(res["infer_seconds"], 3),
                          "evaluation_runs": round(t_eval, 2)},

@@ -125,6 +125,60 @@ lb_status lbml_profile_to_rho0(const float* logrho, double R, double cx, double 
 lb_status lbml_profile_to_rho0_mass(const float* logrho, double R, double cx, double cy, int32_t nx, int32_t ny,
                                     double mass, double* shift, float* rho0, void* stream);
 
+/* Liquid level.  Inside a relaxed droplet the density is uniform, the coexisting
+ * liquid density (Sec. IV.A) shifted by the droplet's Laplace pressure
+ * (Sec. IV.B); the start's error in that density sets how far its pressure jump
+ * starts from the relaxed one.  The network's samples carry independent errors of
+ * about 1e-3 in log density, so the interior level is predicted by a separate FP64
+ * linear model and the network's profile is pinned to it.
+ *
+ * Bands of a profile around radius R (sample offsets d_k = (k - 63.5) / 2):
+ * inner = samples with d_k <= -min(12, R / 2), never empty for 0 <= R <= 63.5;
+ * outer = samples with d_k >= 12 (k = 88..127).
+ *
+ * lbml_profile_levels: levels (device [B][2] FP64, 8-byte aligned) = the means of
+ * L_k (device [B][128] FP32) over the inner and over the outer band of each
+ * profile, R = x[b][2] (device [B][4] FP32 raw features); FP64 sums in a fixed
+ * order; NaN for an empty band.  1 <= B <= 2^20.  Asynchronous on `stream`. */
+lb_status lbml_profile_levels(const float* L, const float* x, int32_t B, double* levels, void* stream);
+
+/* lbml_profile_anchor: profile b of L (device [B][128] FP32, in place) pinned to
+ * the inner level target[b] (device [B] FP64, 8-byte aligned): with
+ * rho_k = exp(L_k), rho_in / rho_out = exp of the band means and
+ * rho* = exp(target[b]), rho'_k = rho_out + (rho_k - rho_out) g with
+ * g = (rho* - rho_out) / (rho_in - rho_out), then rho'_k = rho* on the inner
+ * band; L_k = log rho'_k in FP32 (the arithmetic is FP64).  The map is affine in
+ * density: the interface shape and the vapour end are kept and the inner band
+ * becomes exactly flat.  A profile whose target or g is not finite, or whose
+ * rho'_k would not all be positive, is left as it is.  R = x[b][2].
+ * 1 <= B <= 2^20.  Asynchronous on `stream`. */
+lb_status lbml_profile_anchor(float* L, const float* x, const double* target, int32_t B, void* stream);
+
+/* Level model: y(x) = sum_c coef[c] T_i(z_a) T_j(z_t) T_k(z_u) T_l(z_v) over the
+ * Chebyshev polynomials T_n, i <= 2, j <= 6, k <= 3, l <= 1, column
+ * c = ((i * 7 + j) * 4 + k) * 2 + l, of the features (a, T/T_c, u = 1/R,
+ * nu_g/nu_l); z = 2 (v - lo) / (hi - lo) - 1 clamped to [-1, 1] (z = 0 when
+ * hi == lo), lo and hi being in the variable u for R. */
+enum { LBML_LEVEL_TERMS = 168 };
+typedef struct lbml_level_model {
+    double lo[LBML_IN];
+    double hi[LBML_IN];
+    double coef[LBML_LEVEL_TERMS];
+} lbml_level_model;
+
+/* Host, FP64.  Fit: lo and hi = the range of each feature over the rows of x
+ * (host [n][4], finite, R > 0), coef = the least-squares solution of
+ * [A; sqrt(lam) I] c = [y; 0] with A the [n][168] basis matrix and
+ * lam = 1e-12 trace(A^T A) / 168 (a ridge term that keeps a feature with a single
+ * value, or n < 168 rows, solvable), by Householder QR.  y: host [n].
+ * 1 <= n <= 262144.  LB_EINVAL for bad arguments, LB_ENOMEM if the host working
+ * matrix ((n + 168) x 168 doubles) cannot be allocated. */
+lb_status lbml_level_fit(const double* x, const double* y, int32_t n, lbml_level_model* model);
+
+/* Host, FP64: y[i] (host [n]) = the model at row i of x (host [n][4], finite,
+ * R > 0).  0 <= n <= 2^30. */
+lb_status lbml_level_eval(const lbml_level_model* model, const double* x, int32_t n, double* y);
+
 /* Building block, exported for tests: C[M][N] (device FP32, row stride ldc) =
  * sum_k A(m, k) B(k, n) with bf16 device operands A(m, k) = A[m sam + k sak]
  * and B(k, n) = B[k sbk + n sbn].  M, N multiples of 16, K a multiple of 32. */

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmp.so")
-SOURCES = ["d2q9_kernels.hip", "lbmp_abi.cpp", "lbml_kernels.hip", "lbml_abi.cpp"]
+SOURCES = ["d2q9_kernels.hip", "lbmp_abi.cpp", "lbml_kernels.hip", "lbml_abi.cpp", "lbml_level.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 (v_pk_*_f32) is disabled for every device compile.  Floating-point

@@ -337,6 +337,24 @@ lb_status lbml_profile_to_rho0_mass(const float* logrho, double R, double cx, do
     return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_to_rho0_mass");
 }
 
+lb_status lbml_profile_levels(const float* L, const float* x, int32_t B, double* levels, void* stream)
+{
+    if (!L || !x || !levels) return abi_fail(LB_EINVAL, "NULL argument");
+    if (B < 1 || B > (1 << 20)) return abi_fail(LB_EINVAL, "need 1 <= B <= 2^20 profiles");
+    if (reinterpret_cast<uintptr_t>(levels) % 8) return abi_fail(LB_EINVAL, "levels must be 8-byte aligned");
+    hipError_t e = lbml::launch_profile_levels(L, x, B, levels, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_levels");
+}
+
+lb_status lbml_profile_anchor(float* L, const float* x, const double* target, int32_t B, void* stream)
+{
+    if (!L || !x || !target) return abi_fail(LB_EINVAL, "NULL argument");
+    if (B < 1 || B > (1 << 20)) return abi_fail(LB_EINVAL, "need 1 <= B <= 2^20 profiles");
+    if (reinterpret_cast<uintptr_t>(target) % 8) return abi_fail(LB_EINVAL, "target must be 8-byte aligned");
+    hipError_t e = lbml::launch_profile_anchor(L, x, target, B, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LB_OK : abi_hip_fail(e, "lbml_profile_anchor");
+}
+
 lb_status lbml_gemm_bf16(const void* A, int64_t sam, int64_t sak, const void* B, int64_t sbk, int64_t sbn, float* C,
                          int32_t ldc, int32_t M, int32_t N, int32_t K, void* stream)
 {

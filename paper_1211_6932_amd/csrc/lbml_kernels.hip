@@ -324,9 +324,94 @@ __global__ __launch_bounds__(kMassThreads) void profile_mass_shift(const float* 
     }
 }
 
+// ---------------------------------------------------------------- liquid level
+// Bands of a profile around radius R (d_k = (k - 63.5) / 2): inner = samples with
+// d_k <= -min(12, R / 2), outer = samples with d_k >= 12.  Inside a relaxed droplet
+// the density is the Laplace-shifted liquid density (Sec. IV.A-B); the inner band
+// holds it, the outer band the vapour.
+
+constexpr double kBand = 12.0;
+
+// Means of the sample's log density over the two bands, for the workgroup of kOut
+// threads that holds one profile (thread k = sample k).  FP64 tree sums in a fixed
+// order.  An empty band gives NaN (0 / 0).
+__device__ void band_means(double v, double R, double& m_in, double& m_out)
+{
+    __shared__ double part[4][kOut];
+    const int k = threadIdx.x;
+    const double d = (k - 63.5) * 0.5;
+    const bool in = d <= -fmin(kBand, 0.5 * R);
+    const bool out = d >= kBand;
+    part[0][k] = in ? v : 0.0;
+    part[1][k] = in ? 1.0 : 0.0;
+    part[2][k] = out ? v : 0.0;
+    part[3][k] = out ? 1.0 : 0.0;
+    __syncthreads();
+    for (int s = kOut / 2; s > 0; s >>= 1) {
+        if (k < s) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) part[q][k] += part[q][k + s];
+        }
+        __syncthreads();
+    }
+    m_in = part[0][0] / part[1][0];
+    m_out = part[2][0] / part[3][0];
+    __syncthreads();  // part is reused by the next call
+}
+
+// lev[b] = (inner, outer) band means of profile b; R = x[b][2].
+__global__ __launch_bounds__(kOut) void profile_levels(const float* __restrict__ L, const float* __restrict__ x,
+                                                       double* __restrict__ lev)
+{
+    const long long b = blockIdx.x;
+    const int k = threadIdx.x;
+    double m_in, m_out;
+    band_means((double)L[b * kOut + k], (double)x[b * kIn + 2], m_in, m_out);
+    if (k == 0) {
+        lev[2 * b] = m_in;
+        lev[2 * b + 1] = m_out;
+    }
+}
+
+// Profile b pinned to the inner level target[b], in place: with rho = exp(L),
+// rho_in / rho_out = exp of the band means and rho* = exp(target),
+// rho'_k = rho_out + (rho_k - rho_out) g, g = (rho* - rho_out) / (rho_in - rho_out),
+// then rho'_k = rho* on the inner band.  The profile is left as it is when the
+// target or g is not finite or some rho'_k <= 0.
+__global__ __launch_bounds__(kOut) void profile_anchor(float* __restrict__ L, const float* __restrict__ x,
+                                                       const double* __restrict__ target)
+{
+    const long long b = blockIdx.x;
+    const int k = threadIdx.x;
+    const double R = (double)x[b * kIn + 2];
+    const double v = (double)L[b * kOut + k];
+    double m_in, m_out;
+    band_means(v, R, m_in, m_out);
+    const double lev = target[b];
+    const double r_in = exp(m_in), r_out = exp(m_out), r_t = exp(lev);
+    const double g = (r_t - r_out) / (r_in - r_out);
+    const bool in = (k - 63.5) * 0.5 <= -fmin(kBand, 0.5 * R);
+    const double rho = in ? r_t : r_out + (exp(v) - r_out) * g;
+    const bool usable = isfinite(lev) && isfinite(g);
+    const int bad = __syncthreads_or(!(rho > 0.0));
+    if (usable && !bad) L[b * kOut + k] = (float)log(rho);
+}
+
 // ---------------------------------------------------------------- launchers
 
 static unsigned grid1(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_profile_levels(const float* L, const float* x, int B, double* lev, hipStream_t s)
+{
+    hipLaunchKernelGGL(profile_levels, dim3(B), dim3(kOut), 0, s, L, x, lev);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_anchor(float* L, const float* x, const double* target, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(profile_anchor, dim3(B), dim3(kOut), 0, s, L, x, target);
+    return hipGetLastError();
+}
 
 hipError_t gemm(const __bf16* A, long long sam, long long sak, const __bf16* B, long long sbk, long long sbn,
                 float* C, int ldc, int M, int N, int K, hipStream_t s)

@@ -35,5 +35,7 @@ hipError_t launch_profile_to_rho0(const float* logrho, double R, double cx, doub
                                   hipStream_t s);
 hipError_t launch_profile_to_rho0_mass(const float* logrho, double R, double cx, double cy, int nx, int ny,
                                        double mass, double* shift, float* rho0, hipStream_t s);
+hipError_t launch_profile_levels(const float* L, const float* x, int B, double* lev, hipStream_t s);
+hipError_t launch_profile_anchor(float* L, const float* x, const double* target, int B, hipStream_t s);
 
 }  // namespace lbml

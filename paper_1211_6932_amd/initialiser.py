@@ -25,11 +25,22 @@ tanh-started run of the same droplet reaches at the end of the window:
   * strict convergence: the same, and the Laplace pressure jump within 1 %.
 A run that is outside those bounds at the last check does not converge in the
 window (None).
+
+Liquid level.  The network's 128 outputs each carry an independent error of
+about 1e-3 in log density (the matrix products take bf16 operands), and the
+density inside the droplet sets how far the start's pressure jump lies from the
+relaxed one: an interior 1e-3 too dense puts the jump tens of per cent off, and
+that error then relaxes over thousands of steps.  The interior level is
+therefore predicted separately, by an FP64 linear model on a Chebyshev basis of
+the features fitted to the training profiles' inner band means (relative to the
+tanh base's), and the network's profile is pinned to it (lbml_profile_anchor:
+affine in density, interior band made flat, interface and vapour kept).
 """
 from __future__ import annotations
 
 import math
 import time
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -209,32 +220,66 @@ def train(X, base, T, steps=3000, lr=1e-3, lr_min=1e-5, minibatch=512, seed=1211
             if log and (k % 1000 == 0 or k == steps - 1):
                 log(f"train step {k}/{steps} loss {loss:.3e} lr {rate:.2e}  {time.time() - t0:.1f} s")
     net.stream.synchronize()
-    return net, losses
+    return Initialiser(net, fit_level(net.device, X, base, T)), losses
 
 
-def predict(net, ws):
-    """Predicted profiles [n][128] (device) for droplets described by workloads."""
+@dataclass
+class Initialiser:
+    """The trained network and the level model of the droplet interior."""
+    net: "lbmp.Net"
+    level: "lbmp.lbml_level_model | None" = None
+
+    def close(self):
+        self.net.close()
+
+
+def inner_levels(device, X, P):
+    """Inner band means of profiles P [n][128] around the radii of features X (host
+    arrays), computed by the library on `device`; float64 [n]."""
     import torch
+    x = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(device)
+    p = torch.from_numpy(np.ascontiguousarray(P, dtype=np.float32)).to(device)
+    lev = lbmp.profile_levels(p, x, stream=torch.cuda.current_stream(device).cuda_stream)
+    return lev[:, 0].cpu().numpy()
+
+
+def fit_level(device, X, base, T):
+    """Level model of the training profiles' inner level relative to the tanh base's."""
+    return lbmp.lbml_level_fit(X, inner_levels(device, X, T) - inner_levels(device, X, base))
+
+
+def predict(model, ws, anchored=True):
+    """Predicted profiles [n][128] (device) for droplets described by workloads:
+    network + tanh base, pinned to the level model's interior level when `anchored`
+    (and the model has one)."""
+    import torch
+    net = model.net
     n = len(ws)
     pad = (n + 15) // 16 * 16
     X = np.zeros((pad, lbmp.LBML_IN))
     base = np.zeros((pad, N_OUT))
     X[:n], base[:n] = features(ws), tanh_base(ws)
     X[n:] = X[0]
+    base[n:] = base[0]
     out = torch.empty((pad, N_OUT), dtype=torch.float32, device=net.device)
     for s in range(0, pad, net.max_batch // 16 * 16):
         e = min(pad, s + net.max_batch // 16 * 16)
         out[s:e] = net.forward(torch.from_numpy(X[s:e].astype(np.float32)),
                                torch.from_numpy(base[s:e].astype(np.float32)))
+    if anchored and model.level is not None:
+        target = inner_levels(net.device, X, base) + lbmp.lbml_level_eval(model.level, X)
+        x = torch.from_numpy(X.astype(np.float32)).to(net.device)
+        t = torch.from_numpy(target).to(net.device)
+        lbmp.profile_anchor(out, x, t, stream=torch.cuda.current_stream(net.device).cuda_stream)
     return out[:n]
 
 
-def learned_rho0(net, ws):
-    """Initial density fields from the network's profiles (device tensors), each moved
+def learned_rho0(model, ws, anchored=True):
+    """Initial density fields from the predicted profiles (device tensors), each moved
     radially so that it carries the mass of the tanh start of the same droplet (both
     starts then relax towards the same equilibrium).  Returns (fields, shifts)."""
     import torch
-    prof = predict(net, ws)
+    prof = predict(model, ws, anchored)
     fields, shifts = [], []
     for i, w in enumerate(ws):
         mass = float(w.rho0.astype(np.float32).sum(dtype=np.float64))
@@ -246,35 +291,52 @@ def learned_rho0(net, ws):
     return fields, [float(s[0]) for s in torch.stack(shifts).cpu()]
 
 
-def evaluate(net, ws, steps=30000, every=50, log=None):
+def evaluate(model, ws, steps=30000, every=50, log=None, ablation=False):
     """Tanh and learned starts of the same droplets, advanced together in one batch.
     Returns per-droplet n_conv of both arms, the final-state errors of the learned
-    arm against the tanh arm and the inference wall time."""
+    arm against the tanh arm and the inference wall time.  With `ablation`, a third
+    arm starts from the network's profile without the level anchoring; its summary
+    is res["network_only"]."""
     import torch
     n = len(ws)
     t0 = time.time()
-    rho_l, shifts = learned_rho0(net, ws)
+    rho_l, shifts = learned_rho0(model, ws)
     t_infer = time.time() - t0
     rho_t = [torch.from_numpy(w.rho0.astype(np.float32)) for w in ws]
+    arms = [rho_t, rho_l]
+    if ablation:
+        arms.append(learned_rho0(model, ws, anchored=False)[0])
     # fallback to the tanh start where a prediction is not a usable density
     fallback = [i for i, f in enumerate(rho_l) if not bool(torch.isfinite(f).all() and (f > 0).all())]
-    for i in fallback:
-        rho_l[i] = rho_t[i]
-    batch = lbmp.Batch([w.params for w in ws] * 2, rho_t + rho_l)
-    rec = record(batch, list(ws) * 2, steps, every, log=log, tag="evaluation")
+    for arm in arms[1:]:
+        for i in range(n):
+            if not bool(torch.isfinite(arm[i]).all() and (arm[i] > 0).all()):
+                arm[i] = rho_t[i]
+    batch = lbmp.Batch([w.params for w in ws] * len(arms), [f for arm in arms for f in arm])
+    rec = record(batch, list(ws) * len(arms), steps, every, log=log, tag="evaluation")
     batch.close()
-    tanh = {k: v[:n] for k, v in rec.items()}
-    lrn = {k: v[n:] for k, v in rec.items()}
+    parts = [{k: v[a * n:(a + 1) * n] for k, v in rec.items()} for a in range(len(arms))]
+    tanh = parts[0]
     u_ref, dp_ref = tanh["U"][:, -1], tanh["DP"][:, -1]
-    res = dict(unstable=(tanh["unstable"] | lrn["unstable"]).tolist(),
-               dp_err=(lrn["DP"][:, -1] / dp_ref - 1.0).tolist(),
-               rho_in_err=(lrn["RHO_IN"][:, -1] / tanh["RHO_IN"][:, -1] - 1.0).tolist(),
-               rho_out_err=(lrn["RHO_OUT"][:, -1] / tanh["RHO_OUT"][:, -1] - 1.0).tolist(),
-               infer_seconds=t_infer, steps=steps, every=every, fallback=fallback, shifts=shifts)
-    for crit, strict in (("u", False), ("strict", True)):
-        res[f"n_tanh_{crit}"] = n_conv(tanh["U"], tanh["DP"], u_ref, dp_ref, every, strict)
-        res[f"n_learned_{crit}"] = n_conv(lrn["U"], lrn["DP"], u_ref, dp_ref, every, strict)
-    res["summary"] = {crit: summarise(res, crit) for crit in ("u", "strict")}
+    bad = np.zeros(n, dtype=bool)
+    for p in parts:
+        bad |= p["unstable"]
+
+    def compare(lrn):
+        res = dict(unstable=bad.tolist(), dp_err=(lrn["DP"][:, -1] / dp_ref - 1.0).tolist(),
+                   rho_in_err=(lrn["RHO_IN"][:, -1] / tanh["RHO_IN"][:, -1] - 1.0).tolist(),
+                   rho_out_err=(lrn["RHO_OUT"][:, -1] / tanh["RHO_OUT"][:, -1] - 1.0).tolist(),
+                   dp_err_start=(lrn["DP"][:, 0] / dp_ref - 1.0).tolist(), steps=steps, every=every)
+        for crit, strict in (("u", False), ("strict", True)):
+            res[f"n_tanh_{crit}"] = n_conv(tanh["U"], tanh["DP"], u_ref, dp_ref, every, strict)
+            res[f"n_learned_{crit}"] = n_conv(lrn["U"], lrn["DP"], u_ref, dp_ref, every, strict)
+        res["summary"] = {crit: summarise(res, crit) for crit in ("u", "strict")}
+        return res
+
+    res = compare(parts[1])
+    res.update(infer_seconds=t_infer, fallback=fallback, shifts=shifts)
+    if ablation:
+        res["network_only"] = compare(parts[2])["summary"]
     return res, rec
 
 
@@ -299,4 +361,5 @@ def summarise(res, crit="u"):
                 ratio_of_medians=float(np.median(a) / np.median(b)), median_ratio=float(np.median(a / b)),
                 learned_not_converged=int(sum(1 for i in idx if nl[i] is None)),
                 median_abs_dp_err=med("dp_err"), max_abs_dp_err=float(np.max(np.abs([res["dp_err"][i] for i in idx]))),
-                median_abs_rho_in_err=med("rho_in_err"), median_abs_rho_out_err=med("rho_out_err"))
+                median_abs_rho_in_err=med("rho_in_err"), median_abs_rho_out_err=med("rho_out_err"),
+                median_abs_dp_err_start=med("dp_err_start"))

@@ -69,9 +69,17 @@ EXPORTS = [
     "lbml_workspace_bytes", "lbml_init", "lbml_set_params", "lbml_get_params", "lbml_forward",
     "lbml_loss_grad", "lbml_adam", "lbml_train_step", "lbml_destroy", "lbml_profile_extract",
     "lbml_profile_to_rho0", "lbml_gemm_bf16", "lbml_profile_scratch_bytes", "lbml_profile_to_rho0_mass",
-    "lbml_profile_extract_noalloc",
+    "lbml_profile_extract_noalloc", "lbml_profile_levels", "lbml_profile_anchor", "lbml_level_fit",
+    "lbml_level_eval",
 ]
 LBML_IN, LBML_HIDDEN, LBML_OUT, LBML_PARAMS = 4, 256, 128, 165760
+LBML_LEVEL_TERMS = 168
+
+
+class lbml_level_model(ctypes.Structure):
+    """Level model of include/lbml.h: feature ranges and Chebyshev coefficients."""
+    _fields_ = [("lo", ctypes.c_double * LBML_IN), ("hi", ctypes.c_double * LBML_IN),
+                ("coef", ctypes.c_double * LBML_LEVEL_TERMS)]
 
 _lib = None
 
@@ -162,6 +170,10 @@ def load():
         "lbml_profile_to_rho0": ([vp, f64, f64, f64, i32, i32, vp, vp], ctypes.c_int),
         "lbml_profile_to_rho0_mass": ([vp, f64, f64, f64, i32, i32, f64, vp, vp, vp], ctypes.c_int),
         "lbml_gemm_bf16": ([vp, i64, i64, vp, i64, i64, vp, i32, i32, i32, i32, vp], ctypes.c_int),
+        "lbml_profile_levels": ([vp, vp, i32, vp, vp], ctypes.c_int),
+        "lbml_profile_anchor": ([vp, vp, vp, i32, vp], ctypes.c_int),
+        "lbml_level_fit": ([dp, dp, i32, ctypes.POINTER(lbml_level_model)], ctypes.c_int),
+        "lbml_level_eval": ([ctypes.POINTER(lbml_level_model), dp, i32, dp], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -421,6 +433,45 @@ def lbml_profile_to_rho0_mass(logrho_ptr, R, cx, cy, nx, ny, mass, shift_ptr, rh
     return _check(load().lbml_profile_to_rho0_mass(_vp(logrho_ptr), float(R), float(cx), float(cy), int(nx), int(ny),
                                                    float(mass), _vp(shift_ptr), _vp(rho0_ptr), _vp(stream)),
                   "lbml_profile_to_rho0_mass")
+
+
+def lbml_profile_levels(L_ptr, x_ptr, B, levels_ptr, stream):
+    return _check(load().lbml_profile_levels(_vp(L_ptr), _vp(x_ptr), int(B), _vp(levels_ptr), _vp(stream)),
+                  "lbml_profile_levels")
+
+
+def lbml_profile_anchor(L_ptr, x_ptr, target_ptr, B, stream):
+    return _check(load().lbml_profile_anchor(_vp(L_ptr), _vp(x_ptr), _vp(target_ptr), int(B), _vp(stream)),
+                  "lbml_profile_anchor")
+
+
+def _host_f64(a, cols=None):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if cols is not None:
+        a = a.reshape(-1, cols)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lbml_level_fit(x, y):
+    """Level model fitted to targets y [n] at raw features x [n][4] (host arrays)."""
+    x, xp = _host_f64(x, LBML_IN)
+    y, yp = _host_f64(y)
+    if y.size != x.shape[0]:
+        raise ValueError("x and y disagree in length")
+    m = lbml_level_model()
+    _check(load().lbml_level_fit(xp, yp, int(x.shape[0]), ctypes.byref(m)), "lbml_level_fit")
+    return m
+
+
+def lbml_level_eval(model, x):
+    """The level model at raw features x [n][4] (host); returns a float64 array [n]."""
+    import numpy as np
+    x, xp = _host_f64(x, LBML_IN)
+    y = np.empty(x.shape[0], dtype=np.float64)
+    _check(load().lbml_level_eval(ctypes.byref(model), xp, int(x.shape[0]),
+                                  y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "lbml_level_eval")
+    return y
 
 
 def lbml_gemm_bf16(A_ptr, sam, sak, B_ptr, sbk, sbn, C_ptr, ldc, M, N, K, stream):
@@ -738,3 +789,20 @@ def profile_to_rho0_mass(logrho, R, cx, cy, nx, ny, mass, out=None, shift=None, 
         shift = torch.empty(2, dtype=torch.float64, device=logrho.device)
     lbml_profile_to_rho0_mass(logrho.data_ptr(), R, cx, cy, nx, ny, mass, shift.data_ptr(), out.data_ptr(), stream)
     return out, shift
+
+
+def profile_levels(L, x, out=None, stream=0):
+    """Inner and outer band means [B][2] (device float64) of device profiles L [B][128]
+    around the radii x[:, 2] of device features x [B][4]."""
+    import torch
+    if out is None:
+        out = torch.empty((L.shape[0], 2), dtype=torch.float64, device=L.device)
+    lbml_profile_levels(L.data_ptr(), x.data_ptr(), L.shape[0], out.data_ptr(), stream)
+    return out
+
+
+def profile_anchor(L, x, target, stream=0):
+    """Pin device profiles L [B][128] (in place) to the inner levels target [B]
+    (device float64); radii from device features x [B][4]."""
+    lbml_profile_anchor(L.data_ptr(), x.data_ptr(), target.data_ptr(), L.shape[0], stream)
+    return L

@@ -185,3 +185,56 @@ def test_learned_initialiser_host_checks():
     assert L.lbml_profile_to_rho0_mass(vp(256), 10.0, 0.0, 0.0, 64, 64, 100.0, None, vp(256), None) == B.LB_EINVAL
     assert L.lbml_profile_to_rho0_mass(vp(256), 10.0, 0.0, 0.0, 64, 64, -1.0, vp(256), vp(256), None) == B.LB_EINVAL
     assert L.lbml_profile_to_rho0_mass(vp(256), 10.0, 0.0, 0.0, 64, 64, 100.0, vp(260), vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_levels(vp(256), vp(256), 0, vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_levels(vp(256), vp(256), 4, vp(260), None) == B.LB_EINVAL
+    assert L.lbml_profile_levels(None, vp(256), 4, vp(256), None) == B.LB_EINVAL
+    assert L.lbml_profile_anchor(vp(256), vp(256), vp(256), (1 << 20) + 1, None) == B.LB_EINVAL
+    assert L.lbml_profile_anchor(vp(256), vp(256), vp(252), 4, None) == B.LB_EINVAL
+    assert L.lbml_profile_anchor(vp(256), None, vp(256), 4, None) == B.LB_EINVAL
+
+
+def _level_features(n, seed, a_values=(0.25, 0.5, 1.0)):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return np.c_[rng.choice(a_values, n), rng.uniform(0.5, 0.85, n), rng.uniform(25.0, 77.0, n),
+                 rng.uniform(1.0, 15.0, n)]
+
+
+@pytest.mark.parametrize("n, a_values", [(3000, (0.25, 0.5, 1.0)), (600, (0.5,)), (40, (0.25, 1.0))])
+def test_level_fit_matches_the_oracle(n, a_values):
+    """The library's host Householder fit against the oracle's least squares on the
+    same stacked ridge system: full rank, a feature with one value, fewer rows than
+    terms."""
+    import numpy as np
+    from oracle import level as OL
+    x = _level_features(n, 11, a_values)
+    y = 1e-3 * np.sin(5.0 * x[:, 1]) * (1.0 + x[:, 0]) + 0.03 / x[:, 2] + 1e-4 * x[:, 3]
+    m = B.lbml_level_fit(x, y)
+    lo, hi, coef = OL.fit(x, y)
+    np.testing.assert_array_equal(np.array(m.lo), lo)
+    np.testing.assert_array_equal(np.array(m.hi), hi)
+    scale = np.max(np.abs(coef))
+    np.testing.assert_allclose(np.array(m.coef), coef, rtol=0, atol=1e-8 * scale)
+    xe = _level_features(200, 12, a_values)
+    np.testing.assert_allclose(B.lbml_level_eval(m, xe), OL.evaluate((lo, hi, coef), xe), rtol=0, atol=1e-12)
+
+
+def test_level_fit_and_eval_reject_bad_input():
+    import numpy as np
+    L = B.load()
+    x = _level_features(50, 3)
+    y = np.zeros(50)
+    m = B.lbml_level_fit(x, y)
+    bad = x.copy()
+    bad[7, 2] = 0.0
+    for xx, yy in ((bad, y), (x, np.full(50, np.nan))):
+        with pytest.raises(B.LbError):
+            B.lbml_level_fit(xx, yy)
+    with pytest.raises(B.LbError):
+        B.lbml_level_eval(m, bad)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert L.lbml_level_fit(None, None, 10, None) == B.LB_EINVAL
+    assert L.lbml_level_fit(x.ctypes.data_as(dp), y.ctypes.data_as(dp), 0, ctypes.byref(m)) == B.LB_EINVAL
+    assert L.lbml_level_fit(x.ctypes.data_as(dp), y.ctypes.data_as(dp), 262145, ctypes.byref(m)) == B.LB_EINVAL
+    assert L.lbml_level_eval(ctypes.byref(m), None, 0, None) == B.LB_OK
+    assert L.lbml_level_eval(ctypes.byref(m), x.ctypes.data_as(dp), -1, y.ctypes.data_as(dp)) == B.LB_EINVAL

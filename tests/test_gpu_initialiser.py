@@ -1,13 +1,18 @@
 """What the learned initialiser gains over the tanh start (small scale, seconds).
 
 256 tanh-started droplets on 128 x 128 lattices relax for 12,000 steps; the
-least-squares profiles of their densities train the network on the device; 32
-held-out droplets then start from the tanh profile and from the network's
-profile (placed radially so it carries the tanh start's mass) and run 12,000
-steps together.  Checked against the tanh runs' final state:
-  * spurious-current convergence (max|u| within 5 % for good): the learned
+least-squares profiles of their densities train the network on the device and
+the FP64 level model on their interior levels; 32 held-out droplets then start
+from the tanh profile, from the anchored prediction and from the network alone
+(each learned start placed radially so it carries the tanh start's mass) and run
+12,000 steps together.  Checked against the tanh runs' final state:
+  * spurious-current convergence (max|u| within 5 % for good): the anchored
     starts need at least 1.5 x fewer steps (median per-droplet ratio);
-  * with the pressure jump also within 1 %: at least 1.1 x fewer;
+  * with the pressure jump also within 1 %: at least 1.3 x fewer (1.59 x measured;
+    the network alone 1.56 x: at this size the tanh runs settle in 5000 steps and
+    the level model has only 256 rows);
+  * the anchored start's pressure jump is at least 3 x closer to the relaxed one
+    than the network alone's (median over droplets; 5.4 x measured);
   * the learned runs end on the same state: median |Delta dp| <= 1e-3,
     coexistence densities within 1e-4;
   * no prediction falls back to the tanh start.
@@ -39,16 +44,18 @@ def test_learned_start_converges_faster_than_tanh():
     train = W.learned_train_instances(n=256, side_lo=128, side_hi=128)
     X, base, T, kept = I.generate(train, 12000, every=4000, log=print)
     assert kept.sum() >= 240 and np.all(np.isfinite(T))
-    net, losses = I.train(X, base, T, steps=2000, log=print)
+    model, losses = I.train(X, base, T, steps=2000, log=print)
     assert losses[-1][1] < 0.01 * losses[0][1]
     held_out = W.learned_eval_instances(n=32, side=128)
-    res, _ = I.evaluate(net, held_out, steps=12000, every=50)
-    net.close()
-    u, strict = res["summary"]["u"], res["summary"]["strict"]
+    res, _ = I.evaluate(model, held_out, steps=12000, every=50, ablation=True)
+    model.close()
+    u, strict, net_only = res["summary"]["u"], res["summary"]["strict"], res["network_only"]["strict"]
     print("spurious-current convergence:", u)
     print("strict convergence:", strict)
+    print("strict convergence, network alone:", net_only)
     assert res["fallback"] == []
     assert u["converged"] >= 24 and u["median_ratio"] >= 1.5
-    assert strict["converged"] >= 16 and strict["median_ratio"] >= 1.1
+    assert strict["converged"] >= 16 and strict["median_ratio"] >= 1.3
+    assert strict["median_abs_dp_err_start"] * 3.0 <= net_only["median_abs_dp_err_start"]
     assert u["median_abs_dp_err"] <= 1e-3
     assert u["median_abs_rho_in_err"] <= 1e-4 and u["median_abs_rho_out_err"] <= 1e-4

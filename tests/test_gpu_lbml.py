@@ -10,7 +10,10 @@ Tolerances:
   * gradients, per parameter block: relative Frobenius 1e-3;
   * Adam: FP32 arithmetic of the same update, 1e-6 lr absolute;
   * profile field: FP64 geometry on FP32 data, 1e-6 relative;
-  * profile fit: FP64 normal equations summed in another order, FP32 result, 2e-6.
+  * profile fit: FP64 normal equations summed in another order, FP32 result, 2e-6;
+  * band levels: FP64 means of the same FP32 samples in another order, 1e-14;
+  * anchoring: FP64 arithmetic rounded once to FP32 on both sides, 2 ulp (rtol
+    2.5e-7); samples whose profile must stay unchanged, bitwise.
 """
 import math
 
@@ -18,6 +21,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from oracle import level as OL
 from oracle import mlp as M
 from oracle import profile as P
 
@@ -238,3 +242,50 @@ def test_entry_points_reject_bad_batches():
     assert L.lbml_loss_grad(net.net, B._vp(x.data_ptr()), None, B._vp(y.data_ptr()), 48, None, None) == B.LB_EINVAL
     assert L.lbml_adam(net.net, 1e-3) == B.LB_ESTATE  # no gradient yet
     net.close()
+
+
+def _noisy_profiles(n, seed):
+    """Droplet-like log profiles with per-sample noise of the network's size, at radii
+    8..80 (small radii put part of the inner band at r_k < 0)."""
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(8.0, 80.0, n)
+    rl, rg = rng.uniform(0.3, 0.45, n), rng.uniform(0.002, 0.05, n)
+    d = (np.arange(128) - 63.5) * 0.5
+    s = 0.5 * (1.0 - np.tanh(2.0 * d[None, :] / rng.uniform(4.0, 8.0, (n, 1))))
+    L = np.log(rg[:, None] + (rl - rg)[:, None] * s) + 1e-3 * rng.standard_normal((n, 128))
+    x = np.c_[rng.choice([0.25, 0.5, 1.0], n), rng.uniform(0.5, 0.85, n), R, rng.uniform(1.0, 15.0, n)]
+    return L.astype(np.float32), x.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 37, 1000])
+def test_profile_levels_match_oracle(n):
+    print(f"[gpu-case] profile levels n={n}", flush=True)
+    L, x = _noisy_profiles(n, 20 + n)
+    got = B.profile_levels(torch.from_numpy(L).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+    torch.cuda.synchronize()
+    want = np.array([OL.levels(L[i].astype(np.float64), float(x[i, 2])) for i in range(n)])
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("n", [1, 37, 1000])
+def test_profile_anchor_matches_oracle(n):
+    print(f"[gpu-case] profile anchor n={n}", flush=True)
+    L, x = _noisy_profiles(n, 40 + n)
+    rng = np.random.default_rng(n)
+    lev = np.array([OL.levels(L[i].astype(np.float64), float(x[i, 2]))[0] for i in range(n)])
+    target = lev + rng.uniform(-3e-3, 3e-3, n)
+    # unusable targets and a reversed map that would turn a sample negative: left alone
+    if n > 4:
+        target[1], target[2] = np.nan, np.inf
+        L[3, 50] = np.log(0.6)
+        target[3] = np.log(1e-5)
+    Ld = torch.from_numpy(L).cuda()
+    B.profile_anchor(Ld, torch.from_numpy(x).cuda(), torch.from_numpy(target).cuda())
+    got = Ld.cpu().numpy()
+    for i in range(n):
+        want = OL.anchor(L[i].astype(np.float64), float(x[i, 2]), target[i]).astype(np.float32)
+        if n > 4 and i in (1, 2, 3):
+            np.testing.assert_array_equal(got[i], L[i])
+            np.testing.assert_array_equal(want, L[i])
+        else:
+            np.testing.assert_allclose(got[i], want, rtol=2.5e-7, atol=0)
