@@ -910,7 +910,8 @@ __global__ __launch_bounds__(256) void d2q9_init(const float* __restrict__ rho0,
     // (the nine upstream forces are unrolled for the nearest-neighbour stencil only: the
     // 24-site stencil's fully unrolled block is large enough to crash the instruction
     // scheduler, and this kernel runs once per lattice)
-#pragma unroll(REACH == 1 ? 9 : 1)
+    constexpr int kUnrollForces = REACH == 1 ? 9 : 1;
+#pragma unroll kUnrollForces
     for (int b = 0; b < 9; ++b) {
         // pre-streamed: slot b of (x, y) holds what the first pull of direction b
         // reads, the equilibrium of the upstream site (or of this site's
