@@ -78,6 +78,21 @@ lb_status lbml_adam(lbml_net* net, float lr);
 lb_status lbml_train_step(lbml_net* net, const float* x, const float* base, const float* target, int32_t B,
                           float lr, float* loss);
 
+/* A training loop on the device: `steps` Adam steps, step s on the minibatch of
+ * the B rows idx[s][0..B-1] (device [steps][B] int32, each in [0, rows)) of
+ * x_all (device [rows][4] raw features), base_all (device [rows][128], or NULL
+ * for zero) and target_all (device [rows][128]), at learning rate lr[s] (device
+ * [steps] FP32).  loss (device [steps] FP32, or NULL) receives each step's loss.
+ * The kernels of one step (row gather, forward, backward, Adam, bf16 refresh)
+ * are captured once into a HIP graph and replayed `steps` times; the step index,
+ * learning rate and Adam's bias correction come from a schedule kept on the
+ * device.  The result is bitwise that of `steps` calls of lbml_train_step on the
+ * gathered rows.  B: multiple of 32, at most max_batch.  The net's stream must
+ * not be the null stream (it is captured).  The indices are checked first
+ * (LB_EINVAL, nothing trained, if one is out of range).  Synchronises the stream. */
+lb_status lbml_train_steps(lbml_net* net, const float* x_all, const float* base_all, const float* target_all,
+                           int32_t rows, const int32_t* idx, const float* lr, int32_t steps, int32_t B, float* loss);
+
 /* Release the handle (not the caller's workspace). */
 lb_status lbml_destroy(lbml_net* net);
 

@@ -39,7 +39,9 @@ constexpr size_t b_off(int i) { return w_off(i) + (size_t)kOutN[i] * kIn[i]; }
 static_assert(w_off(kLayers) == LBML_PARAMS, "parameter count");
 
 struct Layout {
-    size_t theta, m, v, grad, norm, loss, wb[kLayers], x16, z[kLayers], h[kLayers - 1], c, dz[2], total;
+    size_t theta, m, v, grad, norm, loss, wb[kLayers], x16, z[kLayers], h[kLayers - 1], c, dz[2];
+    size_t xg, bg, tg, sched;  // a graph-replayed training step: gathered rows and the device schedule
+    size_t total;
 };
 
 Layout layout_of(int B)
@@ -66,11 +68,18 @@ Layout layout_of(int B)
     L.c = take((size_t)B * lbml::kHidden * 4);
     L.dz[0] = take((size_t)B * lbml::kHidden * 2);
     L.dz[1] = take((size_t)B * lbml::kHidden * 2);
+    L.xg = take((size_t)B * lbml::kIn * 4);
+    L.bg = take((size_t)B * lbml::kOut * 4);
+    L.tg = take((size_t)B * lbml::kOut * 4);
+    L.sched = take(sizeof(lbml::TrainSched));
     L.total = o;
     return L;
 }
 
 bool batch_ok(int32_t B) { return B >= 32 && B % 32 == 0 && B <= (1 << 20); }
+
+constexpr double kBeta1 = 0.9, kBeta2 = 0.999;
+constexpr float kEps = 1e-8f;
 
 }  // namespace
 
@@ -79,8 +88,10 @@ struct lbml_net {
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     Layout L{};
-    long long t = 0;  // Adam steps taken
+    long long t = 0;          // Adam steps taken
+    double p1 = 1.0, p2 = 1.0;  // b1^t and b2^t, one FP64 product per step (the device schedule repeats them)
     bool have_grad = false;
+    lbml::TrainSched sched_init{};  // host copy of the schedule uploaded before a graph-replayed loop
 
     float* f(size_t off) { return reinterpret_cast<float*>(ws + off); }
     __bf16* h16(size_t off) { return reinterpret_cast<__bf16*>(ws + off); }
@@ -250,14 +261,15 @@ lb_status lbml_adam(lbml_net* n, float lr)
     if (!n) return abi_fail(LB_EINVAL, "net is NULL");
     if (!n->have_grad) return abi_fail(LB_ESTATE, "no gradient: call lbml_loss_grad first");
     if (!(lr > 0.0f) || !std::isfinite(lr)) return abi_fail(LB_EINVAL, "learning rate must be positive");
-    const double b1 = 0.9, b2 = 0.999;
-    const long long t = n->t + 1;
-    const float c1 = (float)(1.0 - std::pow(b1, (double)t)), c2 = (float)(1.0 - std::pow(b2, (double)t));
+    const double p1 = n->p1 * kBeta1, p2 = n->p2 * kBeta2;
+    const float c1 = (float)(1.0 - p1), c2 = (float)(1.0 - p2);
     hipError_t e = lbml::launch_adam(n->f(n->L.theta), n->f(n->L.m), n->f(n->L.v), n->f(n->L.grad), LBML_PARAMS, lr,
-                                     (float)b1, (float)b2, 1e-8f, c1, c2, n->stream);
+                                     (float)kBeta1, (float)kBeta2, kEps, c1, c2, n->stream);
     if (e == hipSuccess) e = refresh_bf16(n);
     if (e != hipSuccess) return abi_hip_fail(e, "lbml_adam");
-    n->t = t;
+    n->t += 1;
+    n->p1 = p1;
+    n->p2 = p2;
     return LB_OK;
 }
 
@@ -266,6 +278,70 @@ lb_status lbml_train_step(lbml_net* n, const float* x, const float* base, const 
 {
     lb_status st = lbml_loss_grad(n, x, base, target, B, loss, nullptr);
     return st == LB_OK ? lbml_adam(n, lr) : st;
+}
+
+lb_status lbml_train_steps(lbml_net* n, const float* x_all, const float* base_all, const float* target_all,
+                           int32_t rows, const int32_t* idx, const float* lr, int32_t steps, int32_t B, float* loss)
+{
+    lb_status st = check_net(n, B, true);
+    if (st != LB_OK) return st;
+    if (!x_all || !target_all || !idx || !lr) return abi_fail(LB_EINVAL, "NULL argument");
+    if (rows < 1 || steps < 0) return abi_fail(LB_EINVAL, "need rows >= 1 and steps >= 0");
+    if (!n->stream) return abi_fail(LB_EINVAL, "lbml_train_steps needs the net on a non-null stream (graph capture)");
+    if (steps == 0) return LB_OK;
+    hipStream_t s = n->stream;
+    auto* sc = reinterpret_cast<lbml::TrainSched*>(n->ws + n->L.sched);
+    // the schedule starts at step 0 with the net's Adam state; indices are checked first
+    n->sched_init = lbml::TrainSched{};
+    n->sched_init.p1 = n->p1;
+    n->sched_init.p2 = n->p2;
+    hipError_t e = hipMemcpyAsync(sc, &n->sched_init, sizeof(lbml::TrainSched), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = lbml::launch_check_rows(idx, (long long)steps * B, rows, &sc->bad_rows, s);
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, &sc->bad_rows, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return abi_hip_fail(e, "lbml_train_steps");
+    if (bad) return abi_fail(LB_EINVAL, "lbml_train_steps: a row index lies outside [0, rows)");
+
+    // one step, captured: schedule, gather, forward, backward, loss record, Adam, bf16 refresh
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return abi_hip_fail(e, "lbml_train_steps (begin capture)");
+    float* xg = n->f(n->L.xg);
+    float* bg = base_all ? n->f(n->L.bg) : nullptr;
+    float* tg = n->f(n->L.tg);
+    e = lbml::launch_sched_advance(sc, lr, kBeta1, kBeta2, s);
+    if (e == hipSuccess) e = lbml::launch_gather_rows(x_all, base_all, target_all, idx, sc, B, xg, bg, tg, s);
+    if (e == hipSuccess) e = forward(n, xg, bg, B, n->f(n->L.z[kLayers - 1]));
+    if (e == hipSuccess) e = backward(n, tg, B, n->f(n->L.loss));
+    if (e == hipSuccess && loss) e = lbml::launch_record_loss(n->f(n->L.loss), sc, loss, s);
+    if (e == hipSuccess)
+        e = lbml::launch_adam_sched(n->f(n->L.theta), n->f(n->L.m), n->f(n->L.v), n->f(n->L.grad), LBML_PARAMS, sc,
+                                    (float)kBeta1, (float)kBeta2, kEps, s);
+    if (e == hipSuccess) e = refresh_bf16(n);
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = ec;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (int32_t i = 0; i < steps && e == hipSuccess; ++i) e = hipGraphLaunch(exec, s);
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
+    if (exec) {
+        const hipError_t ed = hipGraphExecDestroy(exec);
+        if (e == hipSuccess) e = ed;
+    }
+    if (graph) {
+        const hipError_t ed = hipGraphDestroy(graph);
+        if (e == hipSuccess) e = ed;
+    }
+    if (e != hipSuccess) return abi_hip_fail(e, "lbml_train_steps");
+    for (int32_t i = 0; i < steps; ++i) {
+        n->p1 *= kBeta1;
+        n->p2 *= kBeta2;
+    }
+    n->t += steps;
+    n->have_grad = true;
+    return LB_OK;
 }
 
 lb_status lbml_destroy(lbml_net* n)

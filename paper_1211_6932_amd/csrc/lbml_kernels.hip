@@ -20,7 +20,11 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // v_mfma_f32_16x16x32_bf16: lane l holds row (or column) l % 16 and the eight
 // consecutive k values 8 (l / 16) .. 8 (l / 16) + 7 of each operand; the
 // accumulator holds rows 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16.
+// AV / BV: the operand is contiguous in k (sak == 1 / sbk == 1) with 16-byte
+// aligned rows, so a lane's eight k values are one 16-byte load; otherwise eight
+// 2-byte loads.  Either way the matrix cores see the same values.
 // M, N multiples of 16 and K a multiple of 32 (checked by the launcher).
+template <bool AV, bool BV>
 __global__ __launch_bounds__(256) void gemm_bf16(const __bf16* __restrict__ A, long long sam,
                                                  long long sak, const __bf16* __restrict__ B,
                                                  long long sbk, long long sbn, float* __restrict__ C,
@@ -32,13 +36,22 @@ __global__ __launch_bounds__(256) void gemm_bf16(const __bf16* __restrict__ A, l
     if (tile >= (M / 16) * tiles_n) return;
     const int m0 = (tile / tiles_n) * 16, n0 = (tile % tiles_n) * 16;
     const int r = lane & 15, kq = (lane >> 4) * 8;
+    const __bf16* arow = A + (long long)(m0 + r) * sam;
+    const __bf16* bcol = B + (long long)(n0 + r) * sbn;
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = 0; k0 < K; k0 += 32) {
         bf16x8 a, b;
+        if constexpr (AV) {
+            a = *reinterpret_cast<const bf16x8*>(arow + k0 + kq);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            a[i] = A[(long long)(m0 + r) * sam + (long long)(k0 + kq + i) * sak];
-            b[i] = B[(long long)(k0 + kq + i) * sbk + (long long)(n0 + r) * sbn];
+            for (int i = 0; i < 8; ++i) a[i] = arow[(long long)(k0 + kq + i) * sak];
+        }
+        if constexpr (BV) {
+            b = *reinterpret_cast<const bf16x8*>(bcol + k0 + kq);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) b[i] = bcol[(long long)(k0 + kq + i) * sbk];
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
     }
@@ -139,20 +152,80 @@ __global__ void copy_cols(const float* __restrict__ src, int lds, float* __restr
     if (i < rows * cols) dst[i] = src[(i / cols) * lds + i % cols];
 }
 
-// Adam on the FP32 master parameters, then refresh the bf16 copies of the
-// weights (first-layer weights into their zero-padded rows).
-__global__ void adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                     const float* __restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
-                     float c2)
+// Adam on the FP32 master parameters (the bf16 copies of the weights are
+// refreshed by to_bf16 afterwards).  c1, c2: the bias corrections 1 - b1^t, 1 - b2^t.
+__device__ __forceinline__ void adam_update(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                            const float* __restrict__ g, int i, float lr, float b1, float b2,
+                                            float eps, float c1, float c2)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                     const float* __restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
+                     float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) adam_update(p, m, v, g, i, lr, b1, b2, eps, c1, c2);
+}
+
+// The same update with the learning rate and bias corrections of the current
+// step read from the device schedule (training loops replayed from a graph).
+__global__ void adam_sched(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                           const float* __restrict__ g, int n, const TrainSched* __restrict__ sc, float b1,
+                           float b2, float eps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) adam_update(p, m, v, g, i, sc->lr, b1, b2, eps, sc->c1, sc->c2);
+}
+
+// One thread: advance the schedule to the next step: step index, learning rate
+// lr[step], running powers b1^t, b2^t (FP64 products, as the host keeps them) and
+// the bias corrections rounded to FP32.
+__global__ void sched_advance(TrainSched* __restrict__ sc, const float* __restrict__ lr, double b1, double b2)
+{
+    const int s = sc->next;
+    sc->cur = s;
+    sc->next = s + 1;
+    sc->p1 *= b1;
+    sc->p2 *= b2;
+    sc->lr = lr[s];
+    sc->c1 = (float)(1.0 - sc->p1);
+    sc->c2 = (float)(1.0 - sc->p2);
+}
+
+// Rows idx[cur][i] of the training set into the step's buffers: features [B][4],
+// base [B][128] (if base_all is not NULL) and target [B][128].  One workgroup of
+// 128 threads per row.
+__global__ __launch_bounds__(kOut) void gather_rows(const float* __restrict__ x_all, const float* __restrict__ base_all,
+                                                    const float* __restrict__ t_all, const int* __restrict__ idx,
+                                                    const TrainSched* __restrict__ sc, int B, float* __restrict__ x,
+                                                    float* __restrict__ base, float* __restrict__ t)
+{
+    const int i = blockIdx.x, k = threadIdx.x;
+    const long long row = idx[(long long)sc->cur * B + i];
+    if (k < kIn) x[i * kIn + k] = x_all[row * kIn + k];
+    if (base_all) base[i * kOut + k] = base_all[row * kOut + k];
+    t[i * kOut + k] = t_all[row * kOut + k];
+}
+
+// loss_out[cur] = loss (one thread).
+__global__ void record_loss(const float* __restrict__ loss, const TrainSched* __restrict__ sc,
+                            float* __restrict__ loss_out)
+{
+    loss_out[sc->cur] = loss[0];
+}
+
+// flag[0] = 1 if some idx[j], j < n, lies outside [0, rows).
+__global__ void check_rows(const int* __restrict__ idx, long long n, int rows, int* __restrict__ flag)
+{
+    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (long long)gridDim.x * blockDim.x)
+        if (idx[j] < 0 || idx[j] >= rows) flag[0] = 1;
 }
 
 __global__ void to_bf16(const float* __restrict__ src, __bf16* __restrict__ dst, int rows, int cols, int ldd)
@@ -413,13 +486,21 @@ hipError_t launch_profile_anchor(float* L, const float* x, const double* target,
     return hipGetLastError();
 }
 
+// An operand that is contiguous in k with 16-byte aligned rows loads eight k values at once.
+static bool rows_of_8(const __bf16* P, long long s_row, long long s_k)
+{
+    return s_k == 1 && s_row % 8 == 0 && reinterpret_cast<uintptr_t>(P) % 16 == 0;
+}
+
 hipError_t gemm(const __bf16* A, long long sam, long long sak, const __bf16* B, long long sbk, long long sbn,
                 float* C, int ldc, int M, int N, int K, hipStream_t s)
 {
     if (M % 16 || N % 16 || K % 32 || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
     const long long tiles = (long long)(M / 16) * (N / 16);
-    hipLaunchKernelGGL(gemm_bf16, dim3(grid1(tiles, 4)), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N,
-                       K);
+    const bool av = rows_of_8(A, sam, sak), bv = rows_of_8(B, sbn, sbk);
+    auto kern = av ? (bv ? gemm_bf16<true, true> : gemm_bf16<true, false>)
+                   : (bv ? gemm_bf16<false, true> : gemm_bf16<false, false>);
+    hipLaunchKernelGGL(kern, dim3(grid1(tiles, 4)), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K);
     return hipGetLastError();
 }
 
@@ -474,6 +555,38 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int n, floa
                        float c1, float c2, hipStream_t s)
 {
     hipLaunchKernelGGL(adam, dim3(grid1(n, 256)), dim3(256), 0, s, p, m, v, g, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_sched(float* p, float* m, float* v, const float* g, int n, const TrainSched* sc, float b1,
+                             float b2, float eps, hipStream_t s)
+{
+    hipLaunchKernelGGL(adam_sched, dim3(grid1(n, 256)), dim3(256), 0, s, p, m, v, g, n, sc, b1, b2, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_sched_advance(TrainSched* sc, const float* lr, double b1, double b2, hipStream_t s)
+{
+    hipLaunchKernelGGL(sched_advance, dim3(1), dim3(1), 0, s, sc, lr, b1, b2);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const float* x_all, const float* base_all, const float* t_all, const int* idx,
+                              const TrainSched* sc, int B, float* x, float* base, float* t, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_rows, dim3(B), dim3(kOut), 0, s, x_all, base_all, t_all, idx, sc, B, x, base, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_loss(const float* loss, const TrainSched* sc, float* loss_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(record_loss, dim3(1), dim3(1), 0, s, loss, sc, loss_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_rows(const int* idx, long long n, int rows, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_rows, dim3(256), dim3(256), 0, s, idx, n, rows, flag);
     return hipGetLastError();
 }
 

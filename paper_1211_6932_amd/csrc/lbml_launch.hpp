@@ -10,6 +10,17 @@ constexpr int kHidden = 256;
 constexpr int kOut = 128;    // log-density samples across the interface
 constexpr double kSmooth = 1e-4;  // weight of the profile fit's smoothness term
 
+// Device state of a training loop replayed from a graph: the step being run
+// (cur), the next one, the running powers b1^t and b2^t of Adam's bias
+// correction (FP64, multiplied once per step as the host does), and the current
+// step's learning rate and FP32 bias corrections.
+struct TrainSched {
+    int cur, next;
+    double p1, p2;
+    float lr, c1, c2;
+    int bad_rows;
+};
+
 hipError_t gemm(const __bf16* A, long long sam, long long sak, const __bf16* B, long long sbk, long long sbn,
                 float* C, int ldc, int M, int N, int K, hipStream_t s);
 hipError_t launch_pack_input(const float* x, const float* mu, const float* inv_sd, __bf16* x16, int B,
@@ -22,6 +33,13 @@ hipError_t launch_bias_grad(const __bf16* dZ, float* db, int B, int N, hipStream
 hipError_t launch_copy_cols(const float* src, int lds, float* dst, int rows, int cols, hipStream_t s);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
                        float c1, float c2, hipStream_t s);
+hipError_t launch_adam_sched(float* p, float* m, float* v, const float* g, int n, const TrainSched* sc, float b1,
+                             float b2, float eps, hipStream_t s);
+hipError_t launch_sched_advance(TrainSched* sc, const float* lr, double b1, double b2, hipStream_t s);
+hipError_t launch_gather_rows(const float* x_all, const float* base_all, const float* t_all, const int* idx,
+                              const TrainSched* sc, int B, float* x, float* base, float* t, hipStream_t s);
+hipError_t launch_record_loss(const float* loss, const TrainSched* sc, float* loss_out, hipStream_t s);
+hipError_t launch_check_rows(const int* idx, long long n, int rows, int* flag, hipStream_t s);
 hipError_t launch_to_bf16(const float* src, __bf16* dst, int rows, int cols, int ldd, hipStream_t s);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_profile_extract(const float* rho, int nx, int ny, double cx, double cy, double R, double* part,

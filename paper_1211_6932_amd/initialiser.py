@@ -184,15 +184,37 @@ def init_params(seed=1211):
     return theta
 
 
-def train(X, base, T, steps=3000, lr=1e-3, lr_min=1e-5, minibatch=512, seed=1211, log=None):
-    """Adam on the mean squared error of (network + base) against T with a cosine
-    learning-rate decay from lr to lr_min; minibatches drawn without replacement
-    within each pass over the data.  Returns (net, losses)."""
+def schedule(n, steps, minibatch, lr, lr_min, seed):
+    """Minibatch rows (int32 [steps][mb], drawn without replacement within each pass
+    over the n rows, a new permutation per pass) and the cosine learning-rate decay
+    from lr to lr_min (float32 [steps])."""
     import torch
-    n = X.shape[0]
     mb = min(minibatch, n // 32 * 32)
     if mb < 32:
         raise ValueError("need at least 32 training profiles")
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    order, pos = torch.randperm(n, generator=gen), 0
+    idx = torch.empty((steps, mb), dtype=torch.int32)
+    rates = np.empty(steps, dtype=np.float32)
+    for k in range(steps):
+        if pos + mb > n:
+            order, pos = torch.randperm(n, generator=gen), 0
+        idx[k] = order[pos:pos + mb].to(torch.int32)
+        pos += mb
+        rates[k] = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * k / max(1, steps - 1)))
+    return idx, rates
+
+
+def train(X, base, T, steps=3000, lr=1e-3, lr_min=1e-5, minibatch=512, seed=1211, log=None, chunk=1000):
+    """Adam on the mean squared error of (network + base) against T with a cosine
+    learning-rate decay from lr to lr_min; minibatches drawn without replacement
+    within each pass over the data.  The steps run on the device in graph-replayed
+    chunks (lbml_train_steps).  Then the FP64 level model of the interior is fitted.
+    Returns (Initialiser, losses) with losses [(step, loss)] every 100 steps."""
+    import torch
+    n = X.shape[0]
+    idx, rates = schedule(n, steps, minibatch, lr, lr_min, seed)
+    mb = idx.shape[1]
     mu, sd = X.mean(0), X.std(0)
     sd = np.where(sd > 0, sd, 1.0)
     net = lbmp.Net(init_params(seed), mu, sd, max_batch=max(mb, 32))
@@ -200,26 +222,18 @@ def train(X, base, T, steps=3000, lr=1e-3, lr_min=1e-5, minibatch=512, seed=1211
     x = torch.from_numpy(X.astype(np.float32)).to(dev)
     b = torch.from_numpy(base.astype(np.float32)).to(dev)
     t = torch.from_numpy(T.astype(np.float32)).to(dev)
-    gen = torch.Generator(device="cpu").manual_seed(seed)
-    order, pos = torch.randperm(n, generator=gen), 0
-    losses = []
+    idx_d = idx.to(dev)
+    lr_d = torch.from_numpy(rates).to(dev)
+    loss_d = torch.zeros(steps, dtype=torch.float32, device=dev)
     t0 = time.time()
-    for k in range(steps):
-        if pos + mb > n:
-            order, pos = torch.randperm(n, generator=gen), 0
-        idx = order[pos:pos + mb].to(dev)
-        pos += mb
-        xb, bb, tb = x.index_select(0, idx), b.index_select(0, idx), t.index_select(0, idx)
-        net.stream.wait_stream(torch.cuda.current_stream(dev))
-        rate = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * k / max(1, steps - 1)))
-        report = k % 100 == 0 or k == steps - 1
-        loss = net.train_step(xb, tb, rate, base=bb, sync=report)
-        torch.cuda.current_stream(dev).wait_stream(net.stream)
-        if report:
-            losses.append((k, loss))
-            if log and (k % 1000 == 0 or k == steps - 1):
-                log(f"train step {k}/{steps} loss {loss:.3e} lr {rate:.2e}  {time.time() - t0:.1f} s")
-    net.stream.synchronize()
+    for s in range(0, steps, chunk):
+        e = min(steps, s + chunk)
+        net.train_steps(x, t, idx_d[s:e], lr_d[s:e], base_all=b, loss=loss_d[s:e])
+        if log:
+            log(f"train step {e - 1}/{steps} loss {float(loss_d[e - 1]):.3e} lr {rates[e - 1]:.2e}  "
+                f"{time.time() - t0:.1f} s")
+    all_losses = loss_d.cpu().numpy()
+    losses = [(k, float(all_losses[k])) for k in range(steps) if k % 100 == 0 or k == steps - 1]
     return Initialiser(net, fit_level(net.device, X, base, T)), losses
 
 

@@ -70,7 +70,7 @@ EXPORTS = [
     "lbml_loss_grad", "lbml_adam", "lbml_train_step", "lbml_destroy", "lbml_profile_extract",
     "lbml_profile_to_rho0", "lbml_gemm_bf16", "lbml_profile_scratch_bytes", "lbml_profile_to_rho0_mass",
     "lbml_profile_extract_noalloc", "lbml_profile_levels", "lbml_profile_anchor", "lbml_level_fit",
-    "lbml_level_eval",
+    "lbml_level_eval", "lbml_train_steps",
 ]
 LBML_IN, LBML_HIDDEN, LBML_OUT, LBML_PARAMS = 4, 256, 128, 165760
 LBML_LEVEL_TERMS = 168
@@ -163,6 +163,7 @@ def load():
         "lbml_loss_grad": ([vp, vp, vp, vp, i32, vp, vp], ctypes.c_int),
         "lbml_adam": ([vp, f32], ctypes.c_int),
         "lbml_train_step": ([vp, vp, vp, vp, i32, f32, vp], ctypes.c_int),
+        "lbml_train_steps": ([vp, vp, vp, vp, i32, vp, vp, i32, i32, vp], ctypes.c_int),
         "lbml_destroy": ([vp], ctypes.c_int),
         "lbml_profile_scratch_bytes": ([i32], ctypes.c_size_t),
         "lbml_profile_extract": ([vp, i32, i32, f64, f64, f64, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
@@ -744,6 +745,25 @@ class Net:
             self.stream.synchronize()
             return float(self.loss_buf.item())
         return None
+
+    def train_steps(self, x_all, target_all, idx, lr, base_all=None, loss=None):
+        """len(lr) Adam steps replayed from a graph: step s on rows idx[s] of the device
+        tensors x_all [rows][4], target_all [rows][128] and base_all [rows][128] (or
+        None), learning rate lr[s]; idx: device int32 [steps][B], lr: device float32
+        [steps]; loss: device float32 [steps] receiving each step's loss, or None."""
+        steps, B = idx.shape
+        for t, cols in ((x_all, LBML_IN), (target_all, LBML_OUT), (base_all, LBML_OUT)):
+            if t is not None and (t.dim() != 2 or t.shape[1] != cols or t.dtype != self.torch.float32
+                                  or not t.is_contiguous()):
+                raise ValueError(f"expected a contiguous float32 [rows][{cols}] tensor")
+        if idx.dtype != self.torch.int32 or lr.dtype != self.torch.float32 or lr.numel() != steps:
+            raise ValueError("idx must be int32 [steps][B] and lr float32 [steps]")
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        _check(load().lbml_train_steps(self.net, _vp(x_all.data_ptr()),
+                                       _vp(0 if base_all is None else base_all.data_ptr()),
+                                       _vp(target_all.data_ptr()), int(x_all.shape[0]), _vp(idx.data_ptr()),
+                                       _vp(lr.data_ptr()), int(steps), int(B),
+                                       _vp(0 if loss is None else loss.data_ptr())), "lbml_train_steps")
 
     def params(self):
         th = self.torch.empty(LBML_PARAMS, dtype=self.torch.float32, device=self.device)

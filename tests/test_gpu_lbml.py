@@ -171,6 +171,61 @@ def test_training_reduces_the_loss():
     assert np.isfinite(last) and last < 0.02 * first, (first, last)
 
 
+@pytest.mark.parametrize("with_base", [False, True])
+def test_graph_replayed_training_equals_single_steps(with_base):
+    """lbml_train_steps (one step captured into a HIP graph, replayed) against the same
+    minibatches run one lbml_train_step at a time: parameters and every step's loss
+    bitwise equal, over two consecutive calls (the schedule and Adam's bias correction
+    carry over) with different learning rates per step."""
+    print(f"[gpu-case] lbml graph-replayed training with_base={with_base}", flush=True)
+    rows, B, steps = 200, 64, 37
+    X = features(rows, 21)
+    rng = np.random.default_rng(22)
+    T = -1.0 + 0.3 * rng.standard_normal((rows, 128))
+    base = 0.1 * rng.standard_normal((rows, 128)) if with_base else None
+    idx = np.stack([rng.choice(rows, B, replace=False) for _ in range(2 * steps)]).astype(np.int32)
+    lr = (1e-3 * (0.5 + rng.random(2 * steps))).astype(np.float32)
+    th = M.init_params(7)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    x_all, t_all = dev(X), dev(T)
+    b_all = None if base is None else dev(base)
+    # one step at a time
+    net1, _, _ = make_net(th, X, max_batch=B)
+    loss1 = []
+    for s in range(2 * steps):
+        sel = torch.from_numpy(idx[s].astype(np.int64)).cuda()
+        loss1.append(net1.train_step(x_all.index_select(0, sel), t_all.index_select(0, sel), float(lr[s]),
+                                     base=None if b_all is None else b_all.index_select(0, sel)))
+    p1 = net1.params().cpu().numpy()
+    net1.close()
+    # the same, graph-replayed, in two calls
+    net2, _, _ = make_net(th, X, max_batch=B)
+    idx_d = torch.from_numpy(idx).cuda()
+    lr_d = torch.from_numpy(lr).cuda()
+    loss2 = torch.full((2 * steps,), -1.0, dtype=torch.float32, device="cuda")
+    net2.train_steps(x_all, t_all, idx_d[:steps], lr_d[:steps], base_all=b_all, loss=loss2[:steps])
+    net2.train_steps(x_all, t_all, idx_d[steps:], lr_d[steps:], base_all=b_all, loss=loss2[steps:])
+    p2 = net2.params().cpu().numpy()
+    net2.close()
+    np.testing.assert_array_equal(loss2.cpu().numpy(), np.array(loss1, dtype=np.float32))
+    np.testing.assert_array_equal(p2, p1)
+
+
+def test_graph_replayed_training_rejects_bad_rows():
+    print("[gpu-case] lbml graph-replayed training, out-of-range row", flush=True)
+    X = features(64, 23)
+    net, _, _ = make_net(M.init_params(8), X, max_batch=32)
+    th0 = net.params().cpu().numpy()
+    x_all = torch.from_numpy(X.astype(np.float32)).cuda()
+    t_all = torch.zeros((64, 128), dtype=torch.float32, device="cuda")
+    idx = torch.zeros((3, 32), dtype=torch.int32)
+    idx[2, 5] = 64
+    with pytest.raises(B.LbError):
+        net.train_steps(x_all, t_all, idx.cuda(), torch.full((3,), 1e-3, device="cuda"))
+    np.testing.assert_array_equal(net.params().cpu().numpy(), th0)
+    net.close()
+
+
 def test_profile_extract_matches_oracle():
     print("[gpu-case] lbml profile extract", flush=True)
     rl, rg = W.coexistence(0.6)
