@@ -198,3 +198,45 @@ def test_batch_tune_keeps_the_state_and_sets_heights(store):
     assert e.value.status == B.LB_EINVAL
     a.close()
     b.close()
+
+
+def _state_f64(b, i, w):
+    nb = B.lb_state_bytes(B.make_params(w.params, "f32"))
+    a = b.get_state(i, nb).view(torch.float32).cpu().numpy().astype(np.float64)
+    return a.reshape(9, w.params["ny"], w.params["nx"])
+
+
+def test_full_size_batch_sampled_one_step_parity():
+    """The 512-lattice sweep (seed 1211, sides 64-512, 51.8 M sites) in the benchmark's
+    launch configuration (stepwise launches, strip heights autotuned on the device):
+    after two steps, the third step of 24 lattices (the smallest, the largest and 22
+    drawn at random) at 2000 random sites each, plus the corners of the first tiles,
+    matches the oracle's collision of the streamed GPU state to 2e-6 of max|f*|, the
+    bound of the single-lattice full-size test."""
+    from oracle import lbref as O
+    ws = W.batch_instances()
+    sides = np.array([w.params["nx"] for w in ws])
+    rng = np.random.default_rng(77)
+    pick = sorted(set([int(sides.argmin()), int(sides.argmax())]
+                      + [int(i) for i in rng.choice(len(ws), 22, replace=False)]))
+    print(f"[gpu-case] full-size batch n={len(ws)} sampled lattices {pick}", flush=True)
+    b = B.Batch([w.params for w in ws], [f32(w.rho0) for w in ws])
+    rows = b.tune()
+    b.step(2)
+    S2 = {i: _state_f64(b, i, ws[i]) for i in pick}
+    b.step(1)
+    assert b.check() == (B.LB_OK, 0)
+    for i in pick:
+        w = ws[i]
+        nx, ny = w.params["nx"], w.params["ny"]
+        S3 = _state_f64(b, i, w)
+        p = O.Params(**w.params)
+        f2 = O.stream(p, S2.pop(i))
+        ys = np.concatenate([rng.integers(0, ny, 2000), [0, 0, ny - 1, ny - 1, 1, 2, rows[i], rows[i] - 1]])
+        xs = np.concatenate([rng.integers(0, nx, 2000), [0, nx - 1, 0, nx - 1, 61, 62, 61, 62]])
+        ref = O.collide_at(p, f2, ys.astype(np.int64) * nx + xs)
+        got = S3[:, ys, xs].T
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"  lattice {i} {nx}x{ny} rows {rows[i]}: max|df*|/max|f*| {err:.2e}")
+        assert err <= 2e-6, (i, err)
+    b.close()

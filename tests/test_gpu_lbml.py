@@ -94,13 +94,13 @@ def make_net(theta, X, max_batch=256):
     return B.Net(torch.from_numpy(theta.astype(np.float32)), mu, sd, max_batch=max_batch), mu, sd
 
 
-@pytest.mark.parametrize("batch,with_base", [(16, False), (48, True), (256, False), (256, True)])
+@pytest.mark.parametrize("batch,with_base", [(16, False), (48, True), (256, False), (256, True), (512, True)])
 def test_forward_matches_oracle(batch, with_base):
     print(f"[gpu-case] lbml forward B={batch} base={with_base}", flush=True)
     th = theta32(1)
     X = features(batch, 11)
     base = np.random.default_rng(21).normal(-3.0, 2.0, (batch, 128)).astype(np.float32) if with_base else None
-    net, mu, sd = make_net(th, X)
+    net, mu, sd = make_net(th, X, max_batch=max(256, batch))
     y = net.forward(torch.from_numpy(X.astype(np.float32)),
                     None if base is None else torch.from_numpy(base)).cpu().numpy().astype(np.float64)
     net.close()
@@ -109,14 +109,15 @@ def test_forward_matches_oracle(batch, with_base):
     assert rel(y, ref) < 2e-4, rel(y, ref)
 
 
-@pytest.mark.parametrize("batch,with_base", [(32, False), (96, True)])
+@pytest.mark.parametrize("batch,with_base", [(32, False), (96, True), (512, True)])
 def test_gradients_match_oracle(batch, with_base):
+    """Batch 512 with a base is the training minibatch of the full protocol."""
     print(f"[gpu-case] lbml gradients B={batch} base={with_base}", flush=True)
     th = theta32(2)
     X = features(batch, 12)
     T = np.random.default_rng(13).normal(-2.0, 1.0, (batch, 128)).astype(np.float32).astype(np.float64)
     base = np.random.default_rng(22).normal(-2.0, 1.0, (batch, 128)).astype(np.float32) if with_base else None
-    net, mu, sd = make_net(th, X)
+    net, mu, sd = make_net(th, X, max_batch=max(256, batch))
     loss, g = net.loss_grad(torch.from_numpy(X.astype(np.float32)), torch.from_numpy(T.astype(np.float32)),
                             None if base is None else torch.from_numpy(base))
     net.close()
