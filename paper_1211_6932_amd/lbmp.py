@@ -756,8 +756,12 @@ class Net:
             if t is not None and (t.dim() != 2 or t.shape[1] != cols or t.dtype != self.torch.float32
                                   or not t.is_contiguous()):
                 raise ValueError(f"expected a contiguous float32 [rows][{cols}] tensor")
-        if idx.dtype != self.torch.int32 or lr.dtype != self.torch.float32 or lr.numel() != steps:
-            raise ValueError("idx must be int32 [steps][B] and lr float32 [steps]")
+        if (idx.dtype != self.torch.int32 or lr.dtype != self.torch.float32 or lr.numel() != steps
+                or not idx.is_contiguous() or not lr.is_contiguous()):
+            raise ValueError("idx must be a contiguous int32 [steps][B] tensor and lr a contiguous float32 [steps]")
+        if loss is not None and (loss.dtype != self.torch.float32 or loss.numel() != steps
+                                 or not loss.is_contiguous()):
+            raise ValueError("loss must be a contiguous float32 [steps] tensor")
         self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         _check(load().lbml_train_steps(self.net, _vp(x_all.data_ptr()),
                                        _vp(0 if base_all is None else base_all.data_ptr()),
