@@ -238,3 +238,25 @@ def test_level_fit_and_eval_reject_bad_input():
     assert L.lbml_level_fit(x.ctypes.data_as(dp), y.ctypes.data_as(dp), 262145, ctypes.byref(m)) == B.LB_EINVAL
     assert L.lbml_level_eval(ctypes.byref(m), None, 0, None) == B.LB_OK
     assert L.lbml_level_eval(ctypes.byref(m), x.ctypes.data_as(dp), -1, y.ctypes.data_as(dp)) == B.LB_EINVAL
+
+
+def test_headers_are_plain_c(tmp_path):
+    """include/*.h declare a C ABI: a C99 translation unit that includes both headers and
+    links every declared function (by taking its address) compiles with -pedantic and no
+    warnings, and the struct sizes seen by C equal those of the ctypes binding."""
+    names = declared_functions()
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include <stdio.h>\n#include "lbmp.h"\n#include "lbml.h"\n'
+        "int main(void) {\n"
+        + "".join(f"    (void)&{n};\n" for n in names)
+        + '    printf("%zu %zu %zu %zu\\n", sizeof(lb_params), sizeof(lb_diag), sizeof(lb_region),'
+          " sizeof(lbml_level_model));\n"
+        "    return 0;\n}\n")
+    exe = tmp_path / "abi"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe), "-L", os.path.dirname(B.LIB_PATH), "-llbmp",
+                    f"-Wl,-rpath,{os.path.dirname(B.LIB_PATH)}"], check=True, capture_output=True, text=True)
+    sizes = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert sizes == [ctypes.sizeof(B.lb_params), ctypes.sizeof(B.lb_diag), ctypes.sizeof(B.lb_region),
+                     ctypes.sizeof(B.lbml_level_model)]
