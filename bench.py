@@ -17,6 +17,7 @@ force, MRT collision with the improved forcing, store).  The metric is MLUPS
     python bench.py --workload lamb      (droplet oscillation against Lamb, Sec. IV.A)
     python bench.py --workload sweeps    (coexistence curves, stability edges, Table I, Fig. 4)
     python bench.py --workload spread    (splash spread radius and Weber number, Sec. IV.C)
+    python bench.py --workload precision (every storage encoding's speed against the same run's FP32)
 
 The batch workload advances 512 independent droplet lattices (seed 1211: sides 64-512,
 a in {0.25, 0.5, 1}, T/Tc in [0.5, 0.85], half of them elliptic): strip heights are
@@ -277,6 +278,64 @@ def bench_splash1k(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_precision(args):
+    """Every storage encoding on the 8192x4096 splash in one process: MLUPS, step-kernel
+    time (HIP events on the library stream) and the speed ratio to the same run's FP32
+    step.  The error of each encoding against the FP64 oracle is a GPU test."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1211_6932_amd import lbmp
+
+    torch.cuda.set_device(0)
+    lbmp.load()
+    w = W.splash(scale=args.scale, Re=200)
+    nx, ny = w.params["nx"], w.params["ny"]
+    sites = nx * ny
+    f = lambda a: torch.from_numpy(np.asarray(a, np.float32))
+    res = {}
+    for store in ("f32", "f16dest", "f16local", "f16", "bf16local", "bf16"):
+        rho_ref = w.info["rho_l"] if store in ("f16", "bf16") else 0.0
+        sim = lbmp.Sim(w.params, f(w.rho0), f(w.ux0), f(w.uy0), store=store, rho_ref=rho_ref)
+        sim.step(args.warmup)
+        sim.stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(sim.stream)
+        sim.step(args.steps)
+        e1.record(sim.stream)
+        sim.stream.synchronize()
+        wall = time.perf_counter() - t0
+        kern_ms = e0.elapsed_time(e1) / args.steps
+        stable = lbmp.lb_check(sim.ctx) == lbmp.LB_OK
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        bps = BYTES_PER_SITE[store]
+        res[store] = {"MLUPS": round(sites * args.steps / wall / 1e6, 1), "kernel_ms": round(kern_ms, 5),
+                      "bytes_per_site": bps,
+                      "hbm_frac": round(bps * sites / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+                      "stable": bool(stable)}
+        log(f"{store}: {res[store]['MLUPS']:.0f} MLUPS, step {kern_ms:.4f} ms")
+    for store, r in res.items():
+        r["vs_f32"] = round(r["MLUPS"] / res["f32"]["MLUPS"], 3)
+    out = {
+        "metric": "MLUPS of destination-scaled FP16 storage over the same run's FP32 step",
+        "value": res["f16dest"]["vs_f32"], "unit": "x", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "16-bit storage, f32 compute", "data": "synthetic",
+        "config": {"workload": f"droplet splash on a thin film, {nx}x{ny}, walls in y, x periodic, a=0.25, "
+                               "T=0.45Tc, Re=200, every storage encoding", "parallelism": "single GPU"},
+        "stores": res,
+        "roofline": {"bound": "hbm", "achieved": round(40 * sites / (res["f16dest"]["kernel_ms"] * 1e-3) / 1e9, 1),
+                     "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": res["f16dest"]["hbm_frac"], "traffic": None,
+                     "kernel": "f16dest step (40 B/site)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_learned(args):
     import numpy as np
     import torch
@@ -506,6 +565,8 @@ def main():
         return bench_sweeps(args)
     if args.workload == "spread":
         return bench_spread(args)
+    if args.workload == "precision":
+        return bench_precision(args)
 
     import numpy as np
     import torch
