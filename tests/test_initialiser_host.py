@@ -95,3 +95,19 @@ def test_schedule_draws_without_replacement_and_decays_the_rate():
     assert np.array_equal(a, idx2.numpy())
     with pytest.raises(ValueError):
         I.schedule(31, 2, 512, 1e-3, 1e-5, seed=1)
+
+
+def test_sweep_edge_helpers():
+    """The sweeps' host reductions: lowest temperature above which every run survived,
+    and the lowest surviving viscosity of a grid."""
+    from paper_1211_6932_amd import sweeps as S
+    rows = [dict(t_over_tc=t, stable=s) for t, s in
+            [(0.9, True), (0.85, True), (0.85, True), (0.8, True), (0.8, False), (0.75, True), (0.7, True)]]
+    # 0.8 has a failed run, so the edge is 0.85 even though 0.75 and 0.7 survived
+    assert S.lowest_stable(rows) == 0.85
+    assert S.lowest_stable([dict(t_over_tc=0.9, stable=False)]) is None
+    assert S.lowest_stable([dict(t_over_tc=t, stable=True) for t in (0.6, 0.9, 0.7)]) == 0.6
+    nus = [0.001, 0.002, 0.004, 0.008, 0.016]
+    assert S.lowest_stable_viscosity(nus, [100, 300, None, None, 50]) == 0.004
+    assert S.lowest_stable_viscosity(nus, [1, 1, 1, 1, 1]) is None
+    assert S.CS == pytest.approx(1.0 / math.sqrt(3.0))
