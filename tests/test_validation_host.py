@@ -81,3 +81,29 @@ def test_profile_parser_picks_the_time_step_instantiation():
     assert not prof._is_step_kernel("void lbmp::d2q9_strip<0, true, 2, 0>(lbmp::Codec<0>::T const*, ...)")
     assert not prof._is_step_kernel("void lbmp::d2q9_strip<0, true, 1, 0>(lbmp::Codec<0>::T const*, ...)")
     assert not prof._is_step_kernel("void lbmp::d2q9_batch<0, true, 0>(lbmp::BatchInstance const*, ...)")
+
+
+def test_traffic_scales_each_counter_by_the_copy_probe(tmp_path):
+    """prof.traffic: per-launch median of the step kernel's counter, scaled by what the same
+    counter reads for the 1 GiB copy probe (FETCH_SIZE reporting half the bytes read
+    gives a scale of 2), summed over read and write, against the algorithmic bytes."""
+    from paper_1211_6932_amd import prof
+    step = "_ZN4lbmp9d2q9_pairILb1ELi0EEEvPKDF16_PDF16_NS_9StepConstEPi"
+    other = "void lbmp::d2q9_strip<5, true, 2, 0>(lbmp::Codec<5>::T const*, ...)"
+    copy = "lbmp::copy_probe(HIP_vector_type<float, 4u> const*, HIP_vector_type<float, 4u>*, unsigned long)"
+    for counter, name, copy_kib, vals in (("FETCH_SIZE", "fetch", 524288.0, [330000.0, 340000.0, 990000.0]),
+                                          ("WRITE_SIZE", "write", 1048576.0, [660000.0, 670000.0, 680000.0])):
+        d = tmp_path / name
+        d.mkdir()
+        rows = ["Kernel_Name,Counter_Name,Counter_Value"]
+        rows += [f'"{step}",{counter},{v}' for v in vals]
+        rows += [f'"{other}",{counter},123.0', f'"{copy}",{counter},{copy_kib}', f'"{copy}",OTHER,7.0']
+        (d / f"{name}_counter_collection.csv").write_text("\n".join(rows) + "\n")
+    sites = 1000000
+    r = prof.traffic(str(tmp_path / "fetch"), str(tmp_path / "write"), "f16dest", sites)
+    assert r["detail"]["read"]["scale"] == 2.0 and r["detail"]["write"]["scale"] == 1.0
+    assert r["detail"]["read"]["bytes_per_launch"] == 340000.0 * 1024 * 2.0  # median, not mean
+    assert r["detail"]["write"]["bytes_per_launch"] == 670000.0 * 1024
+    assert r["bytes_per_launch"] == (340000.0 * 2.0 + 670000.0) * 1024
+    assert r["algorithmic_bytes"] == 40 * sites and r["ratio"] == r["bytes_per_launch"] / (40 * sites)
+    assert r["kernel_sha"] == prof.kernel_hash()
