@@ -89,7 +89,8 @@ lb_status lbml_train_step(lbml_net* net, const float* x, const float* base, cons
  * device.  The result is bitwise that of `steps` calls of lbml_train_step on the
  * gathered rows.  B: multiple of 32, at most max_batch.  The net's stream must
  * not be the null stream (it is captured).  The indices are checked first
- * (LB_EINVAL, nothing trained, if one is out of range).  Synchronises the stream. */
+ * (LB_EINVAL, nothing trained, if one is out of range).  steps = 0 returns LB_OK
+ * at once (the array arguments may then be NULL).  Synchronises the stream. */
 lb_status lbml_train_steps(lbml_net* net, const float* x_all, const float* base_all, const float* target_all,
                            int32_t rows, const int32_t* idx, const float* lr, int32_t steps, int32_t B, float* loss);
 

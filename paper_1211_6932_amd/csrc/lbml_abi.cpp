@@ -285,10 +285,11 @@ lb_status lbml_train_steps(lbml_net* n, const float* x_all, const float* base_al
 {
     lb_status st = check_net(n, B, true);
     if (st != LB_OK) return st;
-    if (!x_all || !target_all || !idx || !lr) return abi_fail(LB_EINVAL, "NULL argument");
-    if (rows < 1 || steps < 0) return abi_fail(LB_EINVAL, "need rows >= 1 and steps >= 0");
-    if (!n->stream) return abi_fail(LB_EINVAL, "lbml_train_steps needs the net on a non-null stream (graph capture)");
+    if (steps < 0) return abi_fail(LB_EINVAL, "need steps >= 0");
     if (steps == 0) return LB_OK;
+    if (!x_all || !target_all || !idx || !lr) return abi_fail(LB_EINVAL, "NULL argument");
+    if (rows < 1) return abi_fail(LB_EINVAL, "need rows >= 1");
+    if (!n->stream) return abi_fail(LB_EINVAL, "lbml_train_steps needs the net on a non-null stream (graph capture)");
     hipStream_t s = n->stream;
     auto* sc = reinterpret_cast<lbml::TrainSched*>(n->ws + n->L.sched);
     // the schedule starts at step 0 with the net's Adam state; indices are checked first

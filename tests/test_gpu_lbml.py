@@ -212,6 +212,32 @@ def test_graph_replayed_training_equals_single_steps(with_base):
     np.testing.assert_array_equal(p2, p1)
 
 
+def test_graph_replayed_training_without_loss_output_and_with_no_steps():
+    """loss=None leaves the loss-record kernel out of the captured graph: the parameters
+    are bitwise those of the same steps with a loss output; steps = 0 changes nothing."""
+    print("[gpu-case] lbml graph-replayed training, no loss output, zero steps", flush=True)
+    rows, B, steps = 96, 32, 9
+    X = features(rows, 31)
+    T = -1.0 + 0.3 * np.random.default_rng(32).standard_normal((rows, 128))
+    idx = np.stack([np.random.default_rng(33 + s).choice(rows, B, replace=False) for s in range(steps)])
+    th = M.init_params(9)
+    x_all = torch.from_numpy(X.astype(np.float32)).cuda()
+    t_all = torch.from_numpy(T.astype(np.float32)).cuda()
+    idx_d = torch.from_numpy(idx.astype(np.int32)).cuda()
+    lr_d = torch.full((steps,), 1e-3, dtype=torch.float32, device="cuda")
+    out = []
+    for with_loss in (True, False):
+        net, _, _ = make_net(th, X, max_batch=B)
+        p0 = net.params().cpu().numpy()
+        net.train_steps(x_all, t_all, idx_d[:0], lr_d[:0])
+        assert np.array_equal(net.params().cpu().numpy(), p0)
+        loss = torch.zeros(steps, dtype=torch.float32, device="cuda") if with_loss else None
+        net.train_steps(x_all, t_all, idx_d, lr_d, loss=loss)
+        out.append(net.params().cpu().numpy())
+        net.close()
+    np.testing.assert_array_equal(out[0], out[1])
+
+
 def test_graph_replayed_training_rejects_bad_rows():
     print("[gpu-case] lbml graph-replayed training, out-of-range row", flush=True)
     X = features(64, 23)
